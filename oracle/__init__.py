@@ -1,0 +1,20 @@
+"""Plain CPU reference ("oracle") for the Benchmark-Streaming operations.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library path imports, links or
+calls this package: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark do.  It shares no code with the HIP library; the two meet
+only through the seeded inputs of ``bsgen``.
+
+Everything here is binary64 numpy (plus ``math.fsum``), written to be read
+against the paper (Chalmers & Warburton, "Portable high-order finite element
+kernels I: Streaming Operations"):
+
+  ops    -- the seven streaming operations of Table 1 (BS1-BS7)
+  mesh   -- the structured hex mesh, its scatter map Z (eq. scatter_def),
+            the CSR form of the gather operator Z^T, node degrees, weights
+  model  -- the launch-latency + bandwidth model, its least-squares fit and
+            the Fischer-Brown point (eqs. time_model, perf_model,
+            Fischer-Brown)
+"""
+
+from . import ops, mesh, model  # noqa: F401
