@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the seven Benchmark-Streaming operations on one MI355X.
+
+One step is one pass of the whole hot path over resident synthetic inputs:
+BS1 copy, BS2 AXPY, BS3 weighted norm, BS4 inner product and BS5 fused CG
+update on global vectors of n = (7*128+1)^3 = 721,734,273 binary64 values
+(the N = 7, E = 128^3 global mesh vector, the top of the length sweep), then
+BS7 scatter and BS6 gather on that mesh's element map (E = 128^3, N = 7:
+1,073,741,824 local nodes; elements randomly permuted and oriented).
+
+Prints one JSON line: aggregate algorithmic GB/s over the step (`value`),
+per-operation GB/s, fraction of the 8 TB/s HBM peak and GDOF/s, the
+roofline record of the dominant kernel (the fused CG update) and a timed
+CPU baseline (the oracle on a bounded sample of the same workload).
+
+    python bench.py [--steps K] [--warmup W] [--small] [--no-cpu-baseline]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HBM GB/s & %peak per op; CG-update GDOF/s, FP64 plain vs mixed/batched"
+HBM_PEAK_GBS = 8000.0
+OPS = ("copy", "axpy", "norm", "dot", "cg_update", "scatter", "gather")
+
+
+def alg_bytes(n, nl, ng, s=8, idx=4):
+    """Algorithmic bytes per call (weighted norm and CG update)."""
+    return {
+        "copy": 2 * s * n,
+        "axpy": 3 * s * n,
+        "norm": 2 * s * n,
+        "dot": 2 * s * n,
+        "cg_update": 7 * s * n,
+        "scatter": idx * nl + s * ng + s * nl,
+        "gather": s * nl + idx * nl + s * ng,
+    }
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("bs_device.h", "bs_stream.hip"):
+        with open(os.path.join(ROOT, "paper_2009_10917_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(per_launch_alg):
+    """HBM bytes per launch of the CG-update kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "cg_update_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n_sample, K_mesh, N_mesh, seed):
+    """Time the oracle (as it stands) on a bounded sample of the workload."""
+    import numpy as np
+
+    import bsgen
+    from oracle import mesh, ops
+
+    xs = {k: bsgen.uniform(seed, bsgen.STREAM[k], n_sample) for k in ("x", "y", "p", "r", "Ap")}
+    w = bsgen.uniform(seed, bsgen.STREAM["w"], n_sample, lo=0.0)
+    a, b = 0.37, 0.91
+    E, NL, NG = mesh.sizes(K_mesh, N_mesh)
+    ids = mesh.hex_map(K_mesh, N_mesh, bsgen.permutation(seed, E), bsgen.orientations(seed, E))
+    rs, ci = mesh.csr_inverse(ids, NG)
+    xL = bsgen.uniform(seed, bsgen.STREAM["xL"], NL)
+    xG = bsgen.uniform(seed, bsgen.STREAM["xG"], NG)
+    t0 = time.perf_counter()
+    ops.copy(xs["x"])
+    ops.axpy(a, xs["x"], b, xs["y"])
+    ops.norm(xs["x"], w)
+    ops.dot(xs["x"], xs["y"])
+    ops.cg_update(a, xs["x"], xs["p"], xs["r"], xs["Ap"], w)
+    ops.scatter(ids, xG, xL)
+    ops.gather(rs, ci, xL)
+    dt = time.perf_counter() - t0
+    byt = alg_bytes(n_sample, NL, NG)
+    total = sum(byt.values())
+    return {
+        "value": round(total / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "seconds": round(dt, 3),
+        "sample": (f"oracle (numpy binary64, exact fsum reductions), one thread: BS1-BS5 on n={n_sample} "
+                   f"global values and BS6/BS7 on the K={K_mesh}, N={N_mesh} permuted/oriented mesh "
+                   f"(N_L={NL}, N_G={NG}); algorithmic bytes / wall time"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=10917)
+    ap.add_argument("--K", type=int, default=128, help="mesh elements per axis (vector n = (7K+1)^3)")
+    ap.add_argument("--small", action="store_true", help="K = 32 (a quick check, not the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        return 2
+    K = 32 if args.small else args.K
+    N = 7
+
+    import numpy as np
+    import torch
+
+    import bsgen
+    import paper_2009_10917_amd as bs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    hs = stream.cuda_stream
+    ctx = bs.bs_ctx_create(0)
+
+    E = K ** 3
+    n = (K * N + 1) ** 3
+    NL = E * (N + 1) ** 3
+    print(f"# setup: n={n} NL={NL} (K={K}, N={N})", file=sys.stderr, flush=True)
+
+    def vec(stream_id, lo=-1.0, size=n):
+        t = torch.empty(size, dtype=torch.float64, device=dev)
+        bsgen.device_uniform(t, args.seed, stream_id, lo=lo)
+        return t
+
+    S = bsgen.STREAM
+    x, y, p, r, Ap = (vec(S[k]) for k in ("x", "y", "p", "r", "Ap"))
+    w = vec(S["w"], lo=0.0)
+    alpha, beta = (float(v) for v in bsgen.scalars(args.seed, K))
+    out = torch.zeros(4, dtype=torch.float64, device=dev)
+
+    perm = torch.from_numpy(bsgen.permutation(args.seed, E).astype(np.int32)).to(dev)
+    orient = torch.from_numpy(bsgen.orientations(args.seed, E).astype(np.uint8)).to(dev)
+    d_map = torch.empty(NL, dtype=torch.int32, device=dev)
+    bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+    plan = bs.bs_gs_create(ctx, d_map, n)
+    del d_map, perm, orient
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    xL = vec(S["xL"], size=NL)
+    xG = vec(S["xG"], size=n)
+    xG_out = torch.empty(n, dtype=torch.float64, device=dev)  # gather target, so no step feeds the next
+    torch.cuda.synchronize()
+    print("# inputs resident", file=sys.stderr, flush=True)
+
+    def step(ev=None):
+        calls = (
+            lambda: bs.bs_copy(ctx, x, y, hs),
+            lambda: bs.bs_axpy(ctx, alpha, x, beta, y, hs),
+            lambda: bs.bs_norm(ctx, x, w, out[0:1], hs),
+            lambda: bs.bs_dot(ctx, x, y, out[1:2], hs),
+            lambda: bs.bs_cg_update(ctx, alpha, x, p, r, Ap, w, out[2:3], hs),
+            lambda: bs.bs_scatter(ctx, plan, xG, xL, hs),
+            lambda: bs.bs_gather(ctx, plan, xL, xG_out, hs),
+        )
+        for i, c in enumerate(calls):
+            if ev is not None:
+                ev[i][0].record(stream)
+            c()
+            if ev is not None:
+                ev[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    events = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in OPS] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(events[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = max(ms_total, wall * 1e3) / args.steps
+
+    per_ms = {op: sum(events[k][i][0].elapsed_time(events[k][i][1]) for k in range(args.steps)) / args.steps
+              for i, op in enumerate(OPS)}
+    byt = alg_bytes(n, NL, n)
+    step_bytes = sum(byt.values())
+    per_op = {}
+    for op in OPS:
+        gbs = byt[op] / (per_ms[op] * 1e-3) / 1e9
+        per_op[op] = {"ms": round(per_ms[op], 4), "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                      "alg_bytes": byt[op]}
+    per_op["cg_update"]["GDOF_s"] = round(n / (per_ms["cg_update"] * 1e-3) / 1e9, 3)
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+
+    cg_gbs = per_op["cg_update"]["GB_s"]
+    traffic = read_traffic(byt["cg_update"])
+    roofline = {"bound": "hbm", "kernel": "k_cg_update<double, 2, 4, true>", "achieved": cg_gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cg_gbs / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": byt["cg_update"],
+                "avg_launch_ms": round(per_ms["cg_update"], 4)}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"BS1-BS5 on binary64 global vectors of n=(7*{K}+1)^3={n} (uniform[-1,1), "
+                                f"weights uniform[0,1)); BS7 scatter and BS6 gather on the N=7, E={K}^3 hex mesh "
+                                f"(N_L={NL}, N_G={n}; elements permuted and oriented from the seed)"),
+                   "n": n, "n_local": NL, "n_global": n, "mesh_K": K, "degree_N": N, "seed": args.seed,
+                   "alpha": alpha, "beta": beta},
+        "per_op": per_op,
+        "roofline": roofline,
+    }
+    del x, y, p, r, Ap, w, xL, xG, xG_out
+    plan.close()
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample, 16, N, args.seed)
+    print(json.dumps(result))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

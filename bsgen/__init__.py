@@ -165,3 +165,47 @@ def round_bf16_bits(x: np.ndarray) -> np.ndarray:
 
 def bf16_bits_to_f64(b: np.ndarray) -> np.ndarray:
     return (np.asarray(b, dtype=np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------- device form
+
+_DEVLIB = None
+
+
+def _devlib():
+    global _DEVLIB
+    if _DEVLIB is None:
+        import ctypes
+        import os
+
+        import torch  # noqa: F401  (bind to torch's HIP runtime, loaded first)
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbsgen.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built (python -m paper_2009_10917_amd.build)")
+        lib = ctypes.CDLL(path)
+        lib.bsgen_uniform.restype = ctypes.c_int
+        lib.bsgen_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        _DEVLIB = lib
+    return _DEVLIB
+
+
+def device_uniform(out, seed, stream, lo=-1.0, start=0, hip_stream=None):
+    """Fill a contiguous device tensor with values start.. of one stream.
+
+    float64 tensors get the binary64 draws; float32 and bfloat16 tensors get
+    them rounded (binary64 -> binary32 -> bfloat16, nearest even), exactly
+    as ``round_f32`` / ``round_bf16_bits`` do on the host.
+    """
+    import torch
+    codes = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2}
+    if out.dtype not in codes or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("device_uniform needs a contiguous float64/float32/bfloat16 device tensor")
+    if lo not in (-1.0, 0.0):
+        raise ValueError("lo must be -1.0 or 0.0")
+    hs = torch.cuda.current_stream().cuda_stream if hip_stream is None else hip_stream
+    rc = _devlib().bsgen_uniform(seed & _MASK64, stream, start, out.numel(), 1 if lo == -1.0 else 0,
+                                 codes[out.dtype], out.data_ptr(), hs)
+    if rc != 0:
+        raise RuntimeError(f"bsgen_uniform failed with HIP error {rc}")
+    return out

@@ -1,0 +1,196 @@
+/*
+ * bs.h -- C ABI of the Benchmark-Streaming operations for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The seven streaming operations of a conjugate-gradient solve for high-order
+ * hexahedral finite elements (Chalmers & Warburton, "Portable high-order
+ * finite element kernels I: Streaming Operations", Table 1):
+ *
+ *   BS1 copy        y = x
+ *   BS2 AXPY        y = alpha x + beta y
+ *   BS3 norm        rho = x.x            (optionally weighted: sum w_i x_i^2)
+ *   BS4 inner prod. sigma = x.y
+ *   BS5 CG update   x += alpha p; r -= alpha Ap; rho = r.r   (Algorithm 1,
+ *                   steps 8-10 fused)
+ *   BS6 gather      x_G = Z^T x_L        (sum over local copies)
+ *   BS7 scatter     x_L = Z x_G          (copy to local copies)
+ *
+ * plus the one-time mesh set-up that gather and scatter need (Section 5): the
+ * scatter map Z of a structured hex mesh and the CSR form of Z^T.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* and all vector arguments are DEVICE pointers on the
+ *   context's device; the caller owns them.  The library owns only what it
+ *   allocates inside bs_ctx and bs_gs objects.
+ * - `stream` is a hipStream_t passed as void*; NULL means the null stream of
+ *   the current device.  Every operation is asynchronous on that stream: it
+ *   neither allocates, nor synchronises, nor reads back, so calls can be
+ *   captured into a hipGraph.  The set-up calls (bs_ctx_create,
+ *   bs_mesh_hex_map, bs_gs_create) allocate and synchronise.
+ * - The calling thread's current HIP device must be the context's device.
+ * - Lengths are int64_t; n == 0 is a valid no-op (reductions then write 0.0).
+ * - Vectors must be aligned to their element size.  Writable vectors must
+ *   not overlap any other argument; read-only inputs may alias each other
+ *   (bs_dot(x, x) is fine).
+ * - Reductions write one binary64 value to a caller-owned device double.
+ * - Arguments are validated on the host before anything is launched; a
+ *   failed check returns BS_ERR_INVALID_ARG (or BS_ERR_UNSUPPORTED for a
+ *   valid but unimplemented dtype) and launches nothing.  A HIP launch or
+ *   runtime failure returns BS_ERR_HIP.  bs_last_error() then describes the
+ *   failure of the calling thread's most recent unsuccessful call.
+ * - One bs_ctx serves one stream at a time: its reduction workspace is
+ *   reused by every reduction launched through it.
+ * - Results are deterministic: the same inputs, sizes and context give the
+ *   same bits on every call.
+ */
+#ifndef BS_H
+#define BS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BS_F64 = 0,  /* binary64 storage and arithmetic                         */
+  BS_F32 = 1,  /* binary32 storage, binary32 arithmetic                   */
+  BS_BF16 = 2  /* bfloat16 storage, binary32 arithmetic                   */
+} bs_dtype;
+
+typedef enum {
+  BS_OK = 0,
+  BS_ERR_INVALID_ARG = 1,
+  BS_ERR_UNSUPPORTED = 2,
+  BS_ERR_ALLOC = 3,
+  BS_ERR_HIP = 4,
+  BS_ERR_NO_CONVERGENCE = 5
+} bs_status;
+
+typedef struct bs_ctx bs_ctx; /* per device: reduction workspace            */
+typedef struct bs_gs bs_gs;   /* gather/scatter plan built from a map       */
+
+/* Human-readable name of a status code (static storage). */
+const char* bs_status_string(bs_status s);
+
+/* Detail of the calling thread's most recent failure ("" if none). */
+const char* bs_last_error(void);
+
+/* Library version string (static storage). */
+const char* bs_version(void);
+
+/* Create a context on HIP device `device` (allocates its workspace and
+ * synchronises).  *out receives the handle; destroy it with bs_ctx_destroy. */
+bs_status bs_ctx_create(int device, bs_ctx** out);
+bs_status bs_ctx_destroy(bs_ctx* ctx);
+
+/* Launch-shape knobs of one operation on this context (the autotuner's
+ * output).  op: 0 copy, 1 axpy, 2 norm, 3 dot, 4 cg_update, 5 gather,
+ * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets each
+ * thread moves per loop trip; grid_cap bounds the number of 256-thread
+ * workgroups (kernels grid-stride beyond it; reductions are further capped
+ * at 8192).  The setting applies to every dtype.  Results of the bit-exact
+ * operations do not depend on it; reduction results depend on it only
+ * through the order of their compensated additions. */
+bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap);
+bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap);
+
+/* BS1 (Table 1; Listing 1): y[i] = x[i] for 0 <= i < n, bit for bit. */
+bs_status bs_copy(bs_ctx* ctx, bs_dtype dtype, int64_t n, const void* x, void* y,
+                  void* stream);
+
+/* BS2 (Table 1; Listing 2): y[i] = alpha*x[i] + beta*y[i].
+ * binary64: both products and the sum are rounded separately (no fused
+ * multiply-add).  y is always read (beta == 0 does not skip it). */
+bs_status bs_axpy(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const void* x,
+                  double beta, void* y, void* stream);
+
+/* BS3 (Table 1; Listing 3): *d_out = sum_i w[i]*x[i]*x[i], the SQUARED norm
+ * (no square root).  w == NULL means w[i] = 1, the paper's form; a non-NULL
+ * w (for instance the 1/degree weights of bs_gs_weights) gives the weighted
+ * inner product of the scattered form (Section 2).  Terms are rounded
+ * products; the sum is compensated, so the result is within a few units in
+ * the last place of the exact sum of the terms. */
+bs_status bs_norm(bs_ctx* ctx, bs_dtype dtype, int64_t n, const void* x, const void* w,
+                  double* d_out, void* stream);
+
+/* BS4 (Table 1): *d_out = sum_i x[i]*y[i], accumulated with exact products
+ * and compensated sums (accurate even for ill-conditioned sums). */
+bs_status bs_dot(bs_ctx* ctx, bs_dtype dtype, int64_t n, const void* x, const void* y,
+                 double* d_out, void* stream);
+
+/* BS5 (Table 1; Algorithm 1 steps 8-10 fused, Section 3):
+ *   x[i] <- x[i] + alpha*p[i];  r[i] <- r[i] - alpha*Ap[i];
+ *   *d_rr = sum_i w[i]*r[i]*r[i] over the STORED updated r (w NULL => 1).
+ * x and r are updated in place with separately rounded products and sums.
+ * The CG ratio beta = rr_new/rr_old is left to the caller. */
+bs_status bs_cg_update(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, void* x,
+                       const void* p, void* r, const void* Ap, const void* w,
+                       double* d_rr, void* stream);
+
+/* Scatter map of a structured K x K x K hex mesh of degree N (Section 2,
+ * eq. scatter_def): for element slot s (0 <= s < K^3) and local node
+ * (i,j,k) (0 <= i,j,k <= N), local index l = s*(N+1)^3 + i + (N+1)*(j + (N+1)*k)
+ * gets the global id X + M*(Y + M*Z), M = K*N+1, of its lattice point.
+ * Slot s holds lattice element e = d_perm[s] at (e%K, (e/K)%K, e/K^2),
+ * turned by orientation d_orient[s] in [0,24): a permutation pi of the axes
+ * (lexicographic order) and flip bits f0+2f1+4f2, keeping the 24 proper
+ * rotations in that order (0 is the identity); local (i,j,k) = t lands on
+ * lattice offset o_d = t[pi[d]], or N - t[pi[d]] when flip d is set.
+ * d_perm (int32[K^3]) and d_orient (uint8[K^3]) may be NULL for the
+ * lexicographic, unrotated mesh.  d_map is int32[K^3 (N+1)^3].
+ * Requires (K*N+1)^3 < 2^31 and K^3 (N+1)^3 < 2^31.  Synchronises `stream`;
+ * returns BS_ERR_INVALID_ARG if a perm entry lies outside [0, K^3) or an
+ * orientation outside [0, 24). */
+bs_status bs_mesh_hex_map(int64_t K, int N, const int32_t* d_perm, const uint8_t* d_orient,
+                          int32_t* d_map, void* stream);
+
+/* The same map computed on the host into host memory (same arguments, host
+ * pointers; perm/orient may be NULL). */
+bs_status bs_mesh_hex_map_host(int64_t K, int N, const int32_t* perm, const uint8_t* orient,
+                               int32_t* map);
+
+/* Build a gather/scatter plan from a scatter map d_map[n_local] (Section 5):
+ * entries in [0, n_global) are global ids, negative entries are masked
+ * (excluded from gather, untouched by scatter).  The plan keeps its own copy
+ * of the map and builds the CSR form of Z^T without values: row g lists the
+ * unmasked local indices l with map[l] == g in ascending order.  Requires
+ * n_local, n_global < 2^31.  Allocates and synchronises `stream`; returns
+ * BS_ERR_INVALID_ARG if any entry is >= n_global. */
+bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_local, int64_t n_global,
+                       void* stream, bs_gs** out);
+bs_status bs_gs_destroy(bs_gs* gs);
+
+/* Sizes of a plan: local length, global length, unmasked local entries,
+ * largest node degree.  Any output pointer may be NULL. */
+bs_status bs_gs_info(const bs_gs* gs, int64_t* n_local, int64_t* n_global,
+                     int64_t* n_unmasked, int64_t* max_degree);
+
+/* Copy the plan's CSR arrays into caller buffers: d_row_starts int32[n_global+1],
+ * d_col_ids int32[n_unmasked]. */
+bs_status bs_gs_csr(const bs_gs* gs, int32_t* d_row_starts, int32_t* d_col_ids, void* stream);
+
+/* d_deg[g] = number of unmasked local copies of global node g (int32[n_global]). */
+bs_status bs_gs_degree(const bs_gs* gs, int32_t* d_deg, void* stream);
+
+/* d_wL[l] = 1/deg(map[l]) (correctly rounded division) for unmasked l,
+ * 0 for masked l; d_wL has n_local entries of `dtype`. */
+bs_status bs_gs_weights(const bs_gs* gs, bs_dtype dtype, void* d_wL, void* stream);
+
+/* BS6 (Table 1; Listing 4): x_G[g] = sum of x_L[l] over row g of the CSR,
+ * added one at a time in ascending l starting from +0.0; rows with no copies
+ * give +0.0.  x_L has n_local entries, x_G n_global. */
+bs_status bs_gather(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xL, void* xG,
+                    void* stream);
+
+/* BS7 (Table 1; Listing 5): x_L[l] = x_G[map[l]] where map[l] >= 0; masked
+ * entries of x_L are left untouched.  Bit-exact copy of the values. */
+bs_status bs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BS_H */

@@ -54,12 +54,17 @@ def sizes(K, N):
 
 
 def hex_map(K, N, perm=None, orient=None):
-    """Scatter ids (map[l] = global id of local node l) of the K^3 mesh."""
-    E = K ** 3
+    """Scatter ids (map[l] = global id of local node l) of the K^3 mesh.
+
+    perm[s] is the lattice element in slot s and orient[s] its orientation.
+    Passing the entries of a subset of slots gives the map rows of just those
+    slots, in that order ((N+1)^3 ids per slot).
+    """
     Np = N + 1
     M = K * N + 1
-    perm = np.arange(E, dtype=np.int64) if perm is None else np.asarray(perm, dtype=np.int64)
-    orient = np.zeros(E, dtype=np.int64) if orient is None else np.asarray(orient, dtype=np.int64)
+    perm = np.arange(K ** 3, dtype=np.int64) if perm is None else np.asarray(perm, dtype=np.int64)
+    orient = np.zeros(perm.size, dtype=np.int64) if orient is None else np.asarray(orient, dtype=np.int64)
+    E = perm.size
     table = orientation_table()
     # local (i, j, k) of one element, in local order (i fastest)
     kk, jj, ii = np.meshgrid(np.arange(Np), np.arange(Np), np.arange(Np), indexing="ij")

@@ -1,0 +1,293 @@
+"""Python binding of the Benchmark-Streaming library (libbs.so, include/bs.h).
+
+Argument marshalling only: every operation runs in the library's HIP kernels
+for gfx950.  Vectors are passed as contiguous torch tensors on the current
+HIP device (their data pointers go to the C ABI; torch supplies memory and
+streams, nothing else).  Each function has the name of the C entry point it
+calls, raises ``BSError`` on a non-OK status, and launches on
+``torch.cuda.current_stream()`` unless a stream handle is given.
+
+Importing this package fails with ImportError if libbs.so has not been
+built (``python -m paper_2009_10917_amd.build``); there is no fallback path.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbs.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bs.h")
+
+BS_F64, BS_F32, BS_BF16 = 0, 1, 2
+STATUS_NAMES = {
+    0: "BS_OK", 1: "BS_ERR_INVALID_ARG", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_ALLOC",
+    4: "BS_ERR_HIP", 5: "BS_ERR_NO_CONVERGENCE",
+}
+OP_IDS = {"copy": 0, "axpy": 1, "norm": 2, "dot": 3, "cg_update": 4, "gather": 5, "scatter": 6}
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int
+_d = ctypes.c_double
+_st = ctypes.c_int
+
+# name -> (restype, argtypes), mirroring include/bs.h
+PROTOTYPES = {
+    "bs_status_string": (ctypes.c_char_p, [_st]),
+    "bs_last_error": (ctypes.c_char_p, []),
+    "bs_version": (ctypes.c_char_p, []),
+    "bs_ctx_create": (_st, [_i32, ctypes.POINTER(_p)]),
+    "bs_ctx_destroy": (_st, [_p]),
+    "bs_ctx_set_tune": (_st, [_p, _i32, _i32, _i32, _i32]),
+    "bs_ctx_get_tune": (_st, [_p, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "bs_copy": (_st, [_p, _i32, _i64, _p, _p, _p]),
+    "bs_axpy": (_st, [_p, _i32, _i64, _d, _p, _d, _p, _p]),
+    "bs_norm": (_st, [_p, _i32, _i64, _p, _p, _p, _p]),
+    "bs_dot": (_st, [_p, _i32, _i64, _p, _p, _p, _p]),
+    "bs_cg_update": (_st, [_p, _i32, _i64, _d, _p, _p, _p, _p, _p, _p, _p]),
+    "bs_mesh_hex_map": (_st, [_i64, _i32, _p, _p, _p, _p]),
+    "bs_mesh_hex_map_host": (_st, [_i64, _i32, _p, _p, _p]),
+    "bs_gs_create": (_st, [_p, _p, _i64, _i64, _p, ctypes.POINTER(_p)]),
+    "bs_gs_destroy": (_st, [_p]),
+    "bs_gs_info": (_st, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                         ctypes.POINTER(_i64)]),
+    "bs_gs_csr": (_st, [_p, _p, _p, _p]),
+    "bs_gs_degree": (_st, [_p, _p, _p]),
+    "bs_gs_weights": (_st, [_p, _i32, _p, _p]),
+    "bs_gather": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "bs_scatter": (_st, [_p, _p, _i32, _p, _p, _p]),
+}
+
+
+class BSError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {name}" + (f" ({detail})" if detail else ""))
+
+
+def _load():
+    # torch ships its own HIP runtime; loading it first makes libbs bind to
+    # that same runtime instead of mapping a second one into the process
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -m paper_2009_10917_amd.build` "
+            "(the streaming operations have no non-HIP implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status, where):
+    if status != 0:
+        raise BSError(status, where, lib.bs_last_error().decode())
+
+
+def _ptr(t):
+    """Device address of a tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return t.data_ptr()
+
+
+def _dtype_id(t):
+    import torch
+    ids = {torch.float64: BS_F64, torch.float32: BS_F32, torch.bfloat16: BS_BF16}
+    if t.dtype not in ids:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return ids[t.dtype]
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _same(a, b, what):
+    if a.dtype != b.dtype or a.numel() != b.numel():
+        raise ValueError(f"{what}: operands differ in dtype or length")
+
+
+class Ctx:
+    """A bs_ctx handle (one per device and stream)."""
+
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.bs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A bs_gs gather/scatter plan."""
+
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+        self.n_local = self.n_global = self.n_unmasked = self.max_degree = 0
+
+    def expect(self, t, n, what):
+        if t is None or t.numel() != n:
+            raise ValueError(f"{what}: expected {n} entries")
+
+    def close(self):
+        if self.handle:
+            lib.bs_gs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bs_version():
+    return lib.bs_version().decode()
+
+
+def bs_ctx_create(device=0):
+    h = _p()
+    _check(lib.bs_ctx_create(device, ctypes.byref(h)), "bs_ctx_create")
+    return Ctx(h.value, device)
+
+
+def bs_ctx_set_tune(ctx, op, unroll, grid_cap, dtype=BS_F64):
+    _check(lib.bs_ctx_set_tune(ctx.handle, OP_IDS.get(op, op), dtype, unroll, grid_cap), "bs_ctx_set_tune")
+
+
+def bs_ctx_get_tune(ctx, op, dtype=BS_F64):
+    u, g = _i32(), _i32()
+    _check(lib.bs_ctx_get_tune(ctx.handle, OP_IDS.get(op, op), dtype, ctypes.byref(u), ctypes.byref(g)),
+           "bs_ctx_get_tune")
+    return u.value, g.value
+
+
+def bs_copy(ctx, x, y, stream=None):
+    _same(x, y, "bs_copy")
+    _check(lib.bs_copy(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(y), _stream(stream)), "bs_copy")
+
+
+def bs_axpy(ctx, alpha, x, beta, y, stream=None):
+    _same(x, y, "bs_axpy")
+    _check(lib.bs_axpy(ctx.handle, _dtype_id(x), x.numel(), float(alpha), _ptr(x), float(beta), _ptr(y),
+                       _stream(stream)), "bs_axpy")
+
+
+def _out(t, what):
+    import torch
+    if t is None or t.dtype != torch.float64 or t.numel() < 1:
+        raise ValueError(f"{what}: result must go to a float64 device tensor")
+
+
+def bs_norm(ctx, x, w, out, stream=None):
+    _out(out, "bs_norm")
+    if w is not None:
+        _same(x, w, "bs_norm")
+    _check(lib.bs_norm(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(w), _ptr(out), _stream(stream)),
+           "bs_norm")
+
+
+def bs_dot(ctx, x, y, out, stream=None):
+    _out(out, "bs_dot")
+    _same(x, y, "bs_dot")
+    _check(lib.bs_dot(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream(stream)),
+           "bs_dot")
+
+
+def bs_cg_update(ctx, alpha, x, p, r, Ap, w, out, stream=None):
+    _out(out, "bs_cg_update")
+    for v, nm in ((p, "p"), (r, "r"), (Ap, "Ap")):
+        _same(x, v, "bs_cg_update " + nm)
+    if w is not None:
+        _same(x, w, "bs_cg_update w")
+    _check(lib.bs_cg_update(ctx.handle, _dtype_id(x), x.numel(), float(alpha), _ptr(x), _ptr(p), _ptr(r),
+                            _ptr(Ap), _ptr(w), _ptr(out), _stream(stream)), "bs_cg_update")
+
+
+def bs_mesh_hex_map(K, N, perm, orient, out, stream=None):
+    E = K ** 3
+    if out.numel() != E * (N + 1) ** 3 or (perm is not None and perm.numel() != E) or \
+            (orient is not None and orient.numel() != E):
+        raise ValueError("bs_mesh_hex_map: array sizes do not match the mesh")
+    _check(lib.bs_mesh_hex_map(K, N, _ptr(perm), _ptr(orient), _ptr(out), _stream(stream)), "bs_mesh_hex_map")
+
+
+def bs_mesh_hex_map_host(K, N, perm=None, orient=None):
+    """Host-side map into a new numpy int32 array (perm int32, orient uint8)."""
+    import numpy as np
+    n_local = K ** 3 * (N + 1) ** 3
+    out = np.empty(n_local, dtype=np.int32)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    oo = None if orient is None else np.ascontiguousarray(orient, dtype=np.uint8)
+    _check(lib.bs_mesh_hex_map_host(K, N, None if pp is None else pp.ctypes.data,
+                                    None if oo is None else oo.ctypes.data, out.ctypes.data),
+           "bs_mesh_hex_map_host")
+    return out
+
+
+def bs_gs_create(ctx, d_map, n_global, stream=None):
+    h = _p()
+    _check(lib.bs_gs_create(ctx.handle, _ptr(d_map), d_map.numel(), int(n_global), _stream(stream),
+                            ctypes.byref(h)), "bs_gs_create")
+    plan = Plan(h.value, ctx.device)
+    for k, v in bs_gs_info(plan).items():
+        setattr(plan, k, v)
+    return plan
+
+
+def bs_gs_info(plan):
+    v = [_i64() for _ in range(4)]
+    _check(lib.bs_gs_info(plan.handle, *[ctypes.byref(a) for a in v]), "bs_gs_info")
+    return dict(zip(("n_local", "n_global", "n_unmasked", "max_degree"), (a.value for a in v)))
+
+
+def bs_gs_csr(plan, row_starts, col_ids, stream=None):
+    plan.expect(row_starts, plan.n_global + 1, "bs_gs_csr row_starts")
+    plan.expect(col_ids, plan.n_unmasked, "bs_gs_csr col_ids")
+    _check(lib.bs_gs_csr(plan.handle, _ptr(row_starts), _ptr(col_ids), _stream(stream)), "bs_gs_csr")
+
+
+def bs_gs_degree(plan, deg, stream=None):
+    plan.expect(deg, plan.n_global, "bs_gs_degree")
+    _check(lib.bs_gs_degree(plan.handle, _ptr(deg), _stream(stream)), "bs_gs_degree")
+
+
+def bs_gs_weights(plan, wL, stream=None):
+    plan.expect(wL, plan.n_local, "bs_gs_weights")
+    _check(lib.bs_gs_weights(plan.handle, _dtype_id(wL), _ptr(wL), _stream(stream)), "bs_gs_weights")
+
+
+def bs_gather(ctx, plan, xL, xG, stream=None):
+    plan.expect(xL, plan.n_local, "bs_gather xL")
+    plan.expect(xG, plan.n_global, "bs_gather xG")
+    _check(lib.bs_gather(ctx.handle, plan.handle, _dtype_id(xL), _ptr(xL), _ptr(xG), _stream(stream)), "bs_gather")
+
+
+def bs_scatter(ctx, plan, xG, xL, stream=None):
+    plan.expect(xL, plan.n_local, "bs_scatter xL")
+    plan.expect(xG, plan.n_global, "bs_scatter xG")
+    _check(lib.bs_scatter(ctx.handle, plan.handle, _dtype_id(xG), _ptr(xG), _ptr(xL), _stream(stream)),
+           "bs_scatter")

@@ -1,0 +1,212 @@
+// Device-side building blocks for gfx950 (wave64, 8 XCDs).
+//
+// Every kernel translation unit that includes this header is compiled with
+// floating-point contraction off, so `a*b + c` is two roundings unless a
+// fused multiply-add is written out with __builtin_fma.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#pragma clang fp contract(off)
+
+namespace bs {
+namespace dev {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- storage
+
+// Tag type of the bfloat16 dtype; its elements are stored as 16-bit patterns.
+struct bf16 {};
+
+// Storage type E, arithmetic type C and native packet width V (elements per
+// 16 bytes) of each dtype, with the conversions between E and C.
+template <class T> struct Storage;
+template <> struct Storage<double> {
+  using E = double;
+  using C = double;
+  static constexpr int V = 2;
+  __device__ static double load(double x) { return x; }
+  __device__ static double store(double x) { return x; }
+};
+template <> struct Storage<float> {
+  using E = float;
+  using C = float;
+  static constexpr int V = 4;
+  __device__ static float load(float x) { return x; }
+  __device__ static float store(float x) { return x; }
+};
+template <> struct Storage<bf16> {
+  using E = uint16_t;
+  using C = float;
+  static constexpr int V = 8;
+  __device__ static float load(uint16_t x) { return __uint_as_float(static_cast<uint32_t>(x) << 16); }
+  // binary32 -> bfloat16, round to nearest, ties to even; NaN stays NaN.
+  __device__ static uint16_t store(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+  }
+};
+
+// Register packet of V storage elements: a native vector, so that a full
+// packet is one 16-byte (dwordx4) access and stays in VGPRs.
+template <class E, int V>
+struct VecOf {
+  typedef E type __attribute__((ext_vector_type(V)));
+};
+template <class E>
+struct VecOf<E, 1> {
+  typedef E type;
+};
+
+template <class Vec, class E>
+__device__ __forceinline__ E vget(const Vec& v, int k) {
+  if constexpr (sizeof(Vec) == sizeof(E)) {
+    return v;
+  } else {
+    return v[k];
+  }
+}
+template <class Vec, class E>
+__device__ __forceinline__ void vset(Vec& v, int k, E e) {
+  if constexpr (sizeof(Vec) == sizeof(E)) {
+    v = e;
+  } else {
+    v[k] = e;
+  }
+}
+
+// ---------------------------------------------------------------- compensated sums
+
+// Unevaluated pair s + c carrying a running sum and its accumulated
+// rounding errors (the cascaded "Sum2"/"Dot2" scheme of Ogita, Rump & Oishi,
+// SIAM J. Sci. Comput. 2005).
+template <class C>
+struct DW {
+  C s;
+  C c;
+};
+
+// Knuth's branch-free TwoSum: t + e == a + b exactly.
+template <class C>
+__device__ __forceinline__ void two_sum(C a, C b, C& t, C& e) {
+  t = a + b;
+  C z = t - a;
+  e = (a - (t - z)) + (b - z);
+}
+
+template <class C>
+__device__ __forceinline__ void dw_acc(DW<C>& a, C v) {
+  C t, e;
+  two_sum(a.s, v, t, e);
+  a.s = t;
+  a.c += e;
+}
+
+// Accumulate the exact product x*y: p + q == x*y (q from a fused multiply-add).
+template <class C>
+__device__ __forceinline__ void dw_acc_prod(DW<C>& a, C x, C y) {
+  C p = x * y;
+  C q = __builtin_fma(x, y, -p);
+  dw_acc(a, p);
+  a.c += q;
+}
+
+template <class C>
+__device__ __forceinline__ DW<C> dw_add(DW<C> a, DW<C> b) {
+  C t, e;
+  two_sum(a.s, b.s, t, e);
+  return DW<C>{t, (a.c + b.c) + e};
+}
+
+template <class C>
+__device__ __forceinline__ DW<C> wave_reduce(DW<C> a) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    DW<C> b{__shfl_xor(a.s, off, kWave), __shfl_xor(a.c, off, kWave)};
+    a = dw_add(a, b);
+  }
+  return a;
+}
+
+// Workgroup-wide reduction in a fixed order; the result is valid in thread 0.
+template <int BLOCK>
+__device__ __forceinline__ DW<double> block_reduce(DW<double> a) {
+  constexpr int NW = BLOCK / kWave;
+  __shared__ double s_s[NW], s_c[NW];
+  a = wave_reduce(a);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) {
+    s_s[w] = a.s;
+    s_c[w] = a.c;
+  }
+  __syncthreads();
+  DW<double> r{0.0, 0.0};
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r = dw_add(r, DW<double>{s_s[i], s_c[i]});
+  }
+  return r;
+}
+
+// Coherent (agent-scope) 64-bit accesses for data exchanged between
+// workgroups that may run on different XCDs, whose L2 caches are separate.
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double(static_cast<long long>(v));
+}
+
+// Single-launch deterministic grid reduction.  Every workgroup stores its
+// pair in partials[blockIdx.x]; the workgroup that finishes last (ticket)
+// adds all pairs in index order and writes the rounded sum to *out, then
+// re-arms the ticket for the next reduction on this workspace.  The result
+// depends only on the grid size, never on the order in which workgroups ran.
+template <int BLOCK>
+__device__ __forceinline__ void grid_finish(DW<double> a, double* partials, unsigned int* ticket, double* out) {
+  __shared__ bool s_last;
+  a = block_reduce<BLOCK>(a);
+  if (threadIdx.x == 0) {
+    store_agent(&partials[2 * blockIdx.x], a.s);
+    store_agent(&partials[2 * blockIdx.x + 1], a.c);
+    __threadfence();
+    unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  DW<double> r{0.0, 0.0};
+  for (unsigned int i = threadIdx.x; i < gridDim.x; i += BLOCK)
+    r = dw_add(r, DW<double>{load_agent(&partials[2 * i]), load_agent(&partials[2 * i + 1])});
+  __syncthreads();  // block_reduce reuses its shared arrays
+  r = block_reduce<BLOCK>(r);
+  if (threadIdx.x == 0) {
+    *out = r.s + r.c;
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------- launch geometry
+
+// Workgroups are dispatched round-robin over the 8 XCDs (hardware id p runs
+// on XCD p % 8).  Renumber them so that each XCD works through one
+// contiguous range of logical blocks: neighbouring blocks, which touch
+// neighbouring data, then share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t p, uint32_t G) {
+  constexpr uint32_t X = 8;
+  const uint32_t q = G / X, r = G % X;
+  const uint32_t x = p % X, i = p / X;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+}  // namespace dev
+}  // namespace bs

@@ -1,0 +1,73 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bs.h"
+
+namespace bs {
+
+// Record a failure for bs_last_error() and return its status.
+bs_status fail(bs_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// Turn the pending HIP error (if any) after a launch into BS_ERR_HIP.
+bs_status check_launch(const char* what);
+bs_status check_hip(hipError_t e, const char* what);
+
+// Element size in bytes of a storage dtype (0 for an unknown dtype).
+inline int dtype_size(bs_dtype d) {
+  switch (d) {
+    case BS_F64: return 8;
+    case BS_F32: return 4;
+    case BS_BF16: return 2;
+  }
+  return 0;
+}
+
+inline bool aligned_to(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Checks common to every vector operation: known dtype, n >= 0, non-NULL and
+// element-aligned pointers when n > 0, and the caller's device matching the
+// context.  Returns BS_OK or the failure status (with the message recorded).
+bs_status check_ctx(const bs_ctx* ctx, const char* op);
+bs_status check_vec(const char* op, const char* name, const void* p, int64_t n, bs_dtype d);
+bs_status check_dtype(const char* op, bs_dtype d);
+
+// Launch-shape knobs of one operation.  `unroll` selects the compiled
+// variant (packs of 16 bytes per thread per loop trip: 1, 2, 4 or 8) and
+// `grid_cap` bounds the number of 256-thread workgroups (the kernels
+// grid-stride beyond it).
+struct Tune {
+  int unroll;
+  int grid_cap;
+};
+
+enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCATTER, OP_COUNT };
+
+// Largest number of workgroups a reduction may use: the context's partial
+// buffer holds one compensated pair per workgroup.
+constexpr int kMaxReduceBlocks = 8192;
+constexpr int kBlock = 256;
+
+}  // namespace bs
+
+struct bs_ctx {
+  int device;
+  double* partials;       // 2 * kMaxReduceBlocks doubles: (sum, compensation)
+  unsigned int* ticket;   // workgroups finished in the current reduction
+  bs::Tune tune[bs::OP_COUNT][3];
+};
+
+struct bs_gs {
+  int device;
+  int64_t n_local;
+  int64_t n_global;
+  int64_t n_unmasked;
+  int64_t max_degree;
+  int32_t* map;         // [n_local] copy of the scatter ids
+  int32_t* row_starts;  // [n_global + 1]
+  int32_t* col_ids;     // [n_unmasked]
+};

@@ -1,0 +1,110 @@
+"""The C ABI without a GPU: symbols, prototypes, host-side checks, host map."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import bsgen
+from oracle import mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bs.h")
+LIB = os.path.join(ROOT, "paper_2009_10917_amd", "libbs.so")
+
+
+def _ensure_built():
+    if not os.path.exists(LIB):
+        from paper_2009_10917_amd import build
+        build.build()
+
+
+_ensure_built()
+import paper_2009_10917_amd as bs  # noqa: E402
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decls = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+(bs_\w+)\s*\(([^;]*?)\)\s*;", text, flags=re.M | re.S)
+    out = {}
+    for name, args in decls:
+        args = args.strip()
+        out[name] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_every_declared_symbol_is_exported_with_matching_arity():
+    decls = header_functions()
+    assert len(decls) >= 20
+    lib = ctypes.CDLL(LIB)
+    for name, nargs in decls.items():
+        assert hasattr(lib, name), name
+        assert name in bs.PROTOTYPES, name
+        assert len(bs.PROTOTYPES[name][1]) == nargs, name
+    assert set(bs.PROTOTYPES) == set(decls)
+
+
+def test_status_strings_and_version():
+    for code, name in bs.STATUS_NAMES.items():
+        assert bs.lib.bs_status_string(code).decode() == name
+    assert "gfx950" in bs.bs_version()
+
+
+def test_host_checks_reject_bad_arguments_before_any_launch():
+    L = bs.lib
+    INVALID = 1
+    # NULL context: rejected on the host, nothing touches a device
+    assert L.bs_copy(None, 0, 10, 16, 32, None) == INVALID
+    assert b"ctx is NULL" in L.bs_last_error()
+    assert L.bs_axpy(None, 0, 10, 1.0, 16, 1.0, 32, None) == INVALID
+    assert L.bs_norm(None, 0, 10, 16, None, 64, None) == INVALID
+    assert L.bs_dot(None, 0, 10, 16, 32, 64, None) == INVALID
+    assert L.bs_cg_update(None, 0, 10, 1.0, 16, 32, 48, 64, None, 80, None) == INVALID
+    assert L.bs_gather(None, None, 0, 16, 32, None) == INVALID
+    assert L.bs_scatter(None, None, 0, 16, 32, None) == INVALID
+    assert L.bs_gs_info(None, None, None, None, None) == INVALID
+    assert L.bs_gs_degree(None, 16, None) == INVALID
+    assert L.bs_ctx_set_tune(None, 0, 0, 4, 16) == INVALID
+    out = ctypes.c_void_p()
+    assert L.bs_gs_create(None, 16, 10, 10, None, ctypes.byref(out)) == INVALID
+    assert L.bs_ctx_create(0, None) == INVALID
+    # destroying NULL handles is a no-op
+    assert L.bs_ctx_destroy(None) == 0 and L.bs_gs_destroy(None) == 0
+
+
+def test_mesh_size_limits():
+    L = bs.lib
+    assert L.bs_mesh_hex_map_host(0, 3, None, None, 16) == 1
+    assert L.bs_mesh_hex_map_host(4, 0, None, None, 16) == 1
+    assert L.bs_mesh_hex_map_host(4, 3, None, None, None) == 1
+    # (K N + 1)^3 must stay below 2^31
+    assert L.bs_mesh_hex_map_host(200, 7, None, None, 16) == 1
+    assert b"32-bit" in L.bs_last_error()
+
+
+@pytest.mark.parametrize("K,N,seed", [(1, 1, 0), (2, 1, 1), (3, 2, 2), (4, 3, 3), (3, 7, 4), (2, 15, 5), (8, 3, None)])
+def test_host_map_bit_exact_against_oracle(K, N, seed):
+    E = K ** 3
+    if seed is None:
+        perm = orient = None
+    else:
+        perm = bsgen.permutation(seed, E)
+        orient = bsgen.orientations(seed, E)
+    got = bs.bs_mesh_hex_map_host(K, N, perm, orient)
+    ref = mesh.hex_map(K, N, perm, orient)
+    assert got.dtype == np.int32
+    assert np.array_equal(got.astype(np.int64), ref)
+
+
+def test_host_map_rejects_out_of_range_entries():
+    perm = np.arange(8, dtype=np.int32)
+    perm[3] = 8
+    with pytest.raises(bs.BSError):
+        bs.bs_mesh_hex_map_host(2, 2, perm, None)
+    orient = np.zeros(8, dtype=np.uint8)
+    orient[5] = 24
+    with pytest.raises(bs.BSError):
+        bs.bs_mesh_hex_map_host(2, 2, None, orient)

@@ -1,0 +1,168 @@
+"""GPU parity of the mesh map, the gather/scatter plan, BS6 and BS7.
+
+Map, CSR, degrees, weights, gather and scatter are all compared bit for bit
+with the oracle (gather adds in the oracle's fixed order, so its bits are
+reproducible; the stated bar is 1e-14 relative).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import bsgen
+from oracle import mesh, ops
+
+pytestmark = pytest.mark.gpu
+
+import paper_2009_10917_amd as bs  # noqa: E402
+from gpu_util import bits, dev_uniform, host_uniform, to_host  # noqa: E402
+
+MESHES = [(1, 1, None), (2, 1, 1), (3, 2, 2), (8, 3, None), (4, 7, 3), (3, 15, 4), (6, 5, 5), (5, 4, None),
+          (12, 2, 6)]
+
+
+def device_map(K, N, seed):
+    E = K ** 3
+    if seed is None:
+        perm = orient = None
+        dp = do = None
+    else:
+        perm = bsgen.permutation(seed, E)
+        orient = bsgen.orientations(seed, E)
+        dp = torch.from_numpy(perm.astype(np.int32)).cuda()
+        do = torch.from_numpy(orient.astype(np.uint8)).cuda()
+    d_map = torch.empty(E * (N + 1) ** 3, dtype=torch.int32, device="cuda")
+    bs.bs_mesh_hex_map(K, N, dp, do, d_map)
+    return d_map, mesh.hex_map(K, N, perm, orient)
+
+
+@pytest.mark.parametrize("K,N,seed", MESHES)
+def test_map_plan_gather_scatter(ctx, K, N, seed):
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ref_map = device_map(K, N, seed)
+    assert np.array_equal(to_host(d_map).astype(np.int64), ref_map)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    assert (plan.n_local, plan.n_global, plan.n_unmasked) == (NL, NG, NL)
+    rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+    deg_ref = mesh.degree(ref_map, NG)
+    assert plan.max_degree == int(deg_ref.max())
+    rs = torch.empty(NG + 1, dtype=torch.int32, device="cuda")
+    ci = torch.empty(NL, dtype=torch.int32, device="cuda")
+    bs.bs_gs_csr(plan, rs, ci)
+    assert np.array_equal(to_host(rs), rs_ref) and np.array_equal(to_host(ci), ci_ref)
+    deg = torch.empty(NG, dtype=torch.int32, device="cuda")
+    bs.bs_gs_degree(plan, deg)
+    assert np.array_equal(to_host(deg), deg_ref)
+    w_ref = mesh.weights(ref_map, NG)
+    for dt in (torch.float64, torch.float32, torch.bfloat16):
+        w = torch.empty(NL, dtype=dt, device="cuda")
+        bs.bs_gs_weights(plan, w)
+        if dt == torch.float64:
+            assert np.array_equal(bits(to_host(w)), bits(w_ref))
+        elif dt == torch.float32:
+            assert np.array_equal(to_host(w), bsgen.round_f32(w_ref))
+        else:
+            assert np.array_equal(to_host(w), bsgen.round_bf16_bits(w_ref))
+    # BS6 gather
+    xL = dev_uniform(NL, 11)
+    xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    g_ref = ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))
+    assert np.array_equal(bits(to_host(xG)), bits(g_ref))
+    # BS7 scatter
+    xG2 = dev_uniform(NG, 12)
+    bs.bs_scatter(ctx, plan, xG2, xL)
+    s_ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
+    assert np.array_equal(bits(to_host(xL)), bits(s_ref))
+    # gather(scatter(1)) is the degree, exactly
+    ones = torch.ones(NG, dtype=torch.float64, device="cuda")
+    bs.bs_scatter(ctx, plan, ones, xL)
+    bs.bs_gather(ctx, plan, xL, xG)
+    assert np.array_equal(to_host(xG), deg_ref.astype(np.float64))
+    plan.close()
+
+
+def test_masked_entries(ctx):
+    K, N = 5, 3
+    E, NL, NG = mesh.sizes(K, N)
+    ref_map = mesh.hex_map(K, N, bsgen.permutation(9, E), bsgen.orientations(9, E))
+    ref_map[::7] = -1
+    ref_map[3::11] = -5
+    d_map = torch.from_numpy(ref_map.astype(np.int32)).cuda()
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    assert plan.n_unmasked == int(np.count_nonzero(ref_map >= 0))
+    rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+    xL = dev_uniform(NL, 11)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))))
+    xG2 = dev_uniform(NG, 12)
+    bs.bs_scatter(ctx, plan, xG2, xL)
+    assert np.array_equal(bits(to_host(xL)), bits(ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))))
+    w = torch.empty(NL, dtype=torch.float64, device="cuda")
+    bs.bs_gs_weights(plan, w)
+    assert np.array_equal(bits(to_host(w)), bits(mesh.weights(ref_map, NG)))
+
+
+def test_high_degree_rows_use_the_unstaged_path(ctx):
+    # 7 global nodes with ~14000 copies each: a workgroup's rows hold far
+    # more values than its LDS stage, so the direct path adds them
+    NL, NG = 100_003, 7
+    ref_map = (np.arange(NL) * 5) % NG
+    ref_map[::13] = -1
+    d_map = torch.from_numpy(ref_map.astype(np.int32)).cuda()
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    assert plan.max_degree > 10000
+    rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+    xL = dev_uniform(NL, 11)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))))
+
+
+def test_rows_without_copies_and_empty_plans(ctx):
+    # global ids 0..9, only even ones used: odd rows gather to +0.0
+    ref_map = np.array([0, 2, 2, 4, 6, 8, 8, 8, -1], dtype=np.int64)
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), 10)
+    xL = torch.tensor([1.0, -0.0, -0.0, 3.0, 4.0, 5.0, 6.0, 7.0, 9.0], dtype=torch.float64, device="cuda")
+    xG = torch.full((10,), -1.0, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    got = to_host(xG)
+    assert list(got) == [1.0, 0.0, 0.0, 0.0, 3.0, 0.0, 4.0, 0.0, 18.0, 0.0]
+    assert not np.any(np.signbit(got))
+    empty = bs.bs_gs_create(ctx, torch.empty(0, dtype=torch.int32, device="cuda"), 5)
+    assert empty.n_unmasked == 0
+    xG = torch.full((5,), 7.0, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, empty, torch.empty(0, dtype=torch.float64, device="cuda"), xG)
+    assert np.array_equal(to_host(xG), np.zeros(5))
+
+
+def test_invalid_maps_and_meshes_are_rejected(ctx):
+    bad = torch.tensor([0, 1, 5], dtype=torch.int32, device="cuda")
+    with pytest.raises(bs.BSError) as e:
+        bs.bs_gs_create(ctx, bad, 5)
+    assert e.value.status == 1
+    perm = torch.arange(8, dtype=torch.int32, device="cuda")
+    orient = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    orient[3] = 30
+    out = torch.empty(8 * 27, dtype=torch.int32, device="cuda")
+    with pytest.raises(bs.BSError):
+        bs.bs_mesh_hex_map(2, 2, perm, orient, out)
+    with pytest.raises(ValueError):
+        plan = bs.bs_gs_create(ctx, torch.tensor([0, 1], dtype=torch.int32, device="cuda"), 2)
+        bs.bs_gather(ctx, plan, torch.zeros(3, dtype=torch.float64, device="cuda"),
+                     torch.zeros(2, dtype=torch.float64, device="cuda"))
+
+
+def test_gather_scatter_deterministic(ctx):
+    K, N = 10, 7
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, _ = device_map(K, N, 21)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    xL = dev_uniform(NL, 11)
+    outs = []
+    for _ in range(3):
+        xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+        bs.bs_gather(ctx, plan, xL, xG)
+        outs.append(bits(to_host(xG)))
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])

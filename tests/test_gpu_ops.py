@@ -1,0 +1,223 @@
+"""GPU parity of BS1-BS5 (binary64) against the oracle.
+
+Copy, AXPY and the vector part of the fused CG update are compared bit for
+bit; the reductions must lie within 1e-14 relative of the oracle's
+correctly rounded exact sum.  Sizes span several 256-thread tiles and grid
+trips, with ragged tails and 8-byte (not 16-byte) aligned pointers.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import bsgen
+from oracle import ops
+
+pytestmark = pytest.mark.gpu
+
+import paper_2009_10917_amd as bs  # noqa: E402
+from gpu_util import bits, dev_uniform, host_uniform, rel_err, scalar_out, to_host  # noqa: E402
+
+SIZES = [0, 1, 2, 3, 7, 255, 256, 257, 2047, 2048, 2049, 100003, (1 << 20) + 3, 5_000_011]
+OFFSETS = [(0, 0), (1, 1), (1, 0), (0, 1)]  # element offsets of the two main operands
+TOL = 1e-14
+
+
+def test_device_generator_matches_host_generator():
+    for n, start in ((1, 0), (1000, 0), (4097, 123456)):
+        for stream in (1, 6):
+            for lo in (-1.0, 0.0):
+                t = torch.empty(n, dtype=torch.float64, device="cuda")
+                bsgen.device_uniform(t, 77, stream, lo=lo, start=start)
+                ref = bsgen.uniform(77, stream, n, lo=lo, start=start)
+                assert np.array_equal(bits(to_host(t)), bits(ref))
+    x = bsgen.uniform(5, 2, 10000)
+    t32 = torch.empty(10000, dtype=torch.float32, device="cuda")
+    bsgen.device_uniform(t32, 5, 2)
+    assert np.array_equal(to_host(t32), bsgen.round_f32(x))
+    t16 = torch.empty(10000, dtype=torch.bfloat16, device="cuda")
+    bsgen.device_uniform(t16, 5, 2)
+    assert np.array_equal(to_host(t16), bsgen.round_bf16_bits(x))
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("offs", OFFSETS)
+def test_copy_bit_exact(ctx, n, offs):
+    x = dev_uniform(n, 1, offset=offs[0])
+    y = dev_uniform(n, 2, offset=offs[1])
+    bs.bs_copy(ctx, x, y)
+    assert np.array_equal(bits(to_host(y)), bits(host_uniform(n, 1)))
+
+
+def test_copy_special_values(ctx):
+    special = np.array([0.0, -0.0, np.inf, -np.inf, 5e-324, -1.5], dtype=np.float64)
+    nans = np.array([0x7FF8000000000ABC, 0xFFF0000000000001, 0x7FF0000000C0FFEE], dtype=np.uint64).view(np.float64)
+    src = np.tile(np.concatenate([special, nans]), 1000)
+    x = torch.from_numpy(src).cuda()
+    y = torch.zeros_like(x)
+    bs.bs_copy(ctx, x, y)
+    assert np.array_equal(bits(to_host(y)), bits(src))
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("offs", OFFSETS)
+@pytest.mark.parametrize("ab", [(0.37, 1.0), (1.0, 0.37), (-2.5, 0.0)])
+def test_axpy_bit_exact(ctx, n, offs, ab):
+    a, b = ab
+    x = dev_uniform(n, 1, offset=offs[0])
+    y = dev_uniform(n, 2, offset=offs[1])
+    bs.bs_axpy(ctx, a, x, b, y)
+    ref = ops.axpy(a, host_uniform(n, 1), b, host_uniform(n, 2))
+    assert np.array_equal(bits(to_host(y)), bits(ref))
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("offs", [(0, 0), (1, 1), (1, 0)])
+def test_norm_within_tolerance(ctx, n, weighted, offs):
+    x = dev_uniform(n, 1, offset=offs[0])
+    w = dev_uniform(n, 6, lo=0.0, offset=offs[1]) if weighted else None
+    out = scalar_out()
+    bs.bs_norm(ctx, x, w, out)
+    ref = ops.norm(host_uniform(n, 1), host_uniform(n, 6, lo=0.0) if weighted else None)
+    got = float(to_host(out)[0])
+    if n == 0:
+        assert got == 0.0
+    assert rel_err(got, ref) <= TOL, (got, ref)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("offs", [(0, 0), (1, 1), (0, 1)])
+def test_dot_within_tolerance(ctx, n, offs):
+    x = dev_uniform(n, 1, offset=offs[0])
+    y = dev_uniform(n, 2, offset=offs[1])
+    out = scalar_out()
+    bs.bs_dot(ctx, x, y, out)
+    ref = ops.dot(host_uniform(n, 1), host_uniform(n, 2))
+    got = float(to_host(out)[0])
+    assert rel_err(got, ref) <= TOL, (got, ref)
+
+
+def test_dot_compensation_under_cancellation(ctx):
+    # two terms of +-1e16 far apart in the vector cancel exactly; an
+    # uncompensated binary64 sum loses the O(1) remainder's low digits
+    n = 3_000_017
+    xh = host_uniform(n, 1)
+    yh = host_uniform(n, 2)
+    xh[7], yh[7] = 1e16, 1.0
+    xh[n - 5], yh[n - 5] = -1e16, 1.0
+    xh[n // 2], yh[n // 2] = 3e15, 3.0
+    xh[n // 3], yh[n // 3] = -9e15, 1.0
+    x, y = torch.from_numpy(xh).cuda(), torch.from_numpy(yh).cuda()
+    out = scalar_out()
+    bs.bs_dot(ctx, x, y, out)
+    ref = ops.dot(xh, yh)
+    assert rel_err(float(to_host(out)[0]), ref) <= TOL
+
+
+def test_dot_of_x_with_itself_equals_norm(ctx):
+    n = 2_000_003
+    x = dev_uniform(n, 1)
+    a, b = scalar_out(), scalar_out()
+    bs.bs_dot(ctx, x, x, a)
+    bs.bs_norm(ctx, x, None, b)
+    assert rel_err(float(to_host(a)[0]), float(to_host(b)[0])) <= TOL
+
+
+def test_norm_constant_vector_exact(ctx):
+    for n in (1, 1000, 4_194_304 + 77):
+        for c in (1.0, 0.5, -3.0):
+            x = torch.full((n,), c, dtype=torch.float64, device="cuda")
+            out = scalar_out()
+            bs.bs_norm(ctx, x, None, out)
+            assert float(to_host(out)[0]) == n * c * c
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("alpha", [0.37, 0.0])
+def test_cg_update(ctx, n, weighted, alpha):
+    x, p, r, Ap = (dev_uniform(n, s) for s in (1, 3, 4, 5))
+    w = dev_uniform(n, 6, lo=0.0) if weighted else None
+    out = scalar_out()
+    bs.bs_cg_update(ctx, alpha, x, p, r, Ap, w, out)
+    hx, hp, hr, hA = (host_uniform(n, s) for s in (1, 3, 4, 5))
+    hw = host_uniform(n, 6, lo=0.0) if weighted else None
+    xr, rr, rho = ops.cg_update(alpha, hx, hp, hr, hA, hw)
+    assert np.array_equal(bits(to_host(x)), bits(xr))
+    assert np.array_equal(bits(to_host(r)), bits(rr))
+    assert rel_err(float(to_host(out)[0]), rho) <= TOL
+    if alpha == 0.0:
+        assert np.array_equal(bits(to_host(r)), bits(hr))
+
+
+def test_cg_update_unaligned(ctx):
+    n = 100_003
+    x, p, r, Ap = (dev_uniform(n, s, offset=1) for s in (1, 3, 4, 5))
+    out = scalar_out()
+    bs.bs_cg_update(ctx, 0.37, x, p, r, Ap, None, out)
+    xr, rr, rho = ops.cg_update(0.37, *(host_uniform(n, s) for s in (1, 3, 4, 5)))
+    assert np.array_equal(bits(to_host(x)), bits(xr)) and np.array_equal(bits(to_host(r)), bits(rr))
+    assert rel_err(float(to_host(out)[0]), rho) <= TOL
+
+
+def test_reductions_deterministic(ctx):
+    n = 3_000_001
+    x, y = dev_uniform(n, 1), dev_uniform(n, 2)
+    outs = []
+    for _ in range(4):
+        o = scalar_out()
+        bs.bs_dot(ctx, x, y, o)
+        outs.append(to_host(o)[0])
+    assert len({np.float64(v).tobytes() for v in outs}) == 1
+
+
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+@pytest.mark.parametrize("cap", [1, 7, 300, 8192])
+def test_launch_shapes_do_not_change_results(ctx, unroll, cap):
+    n = 1_000_003
+    try:
+        for op in ("copy", "axpy", "norm", "dot", "cg_update"):
+            bs.bs_ctx_set_tune(ctx, op, unroll, cap)
+        x, y = dev_uniform(n, 1), dev_uniform(n, 2)
+        bs.bs_axpy(ctx, 0.37, x, 1.0, y)
+        assert np.array_equal(bits(to_host(y)), bits(ops.axpy(0.37, host_uniform(n, 1), 1.0, host_uniform(n, 2))))
+        z = torch.empty_like(x)
+        bs.bs_copy(ctx, x, z)
+        assert np.array_equal(bits(to_host(z)), bits(host_uniform(n, 1)))
+        o = scalar_out()
+        bs.bs_dot(ctx, x, z, o)
+        assert rel_err(float(to_host(o)[0]), ops.norm(host_uniform(n, 1))) <= TOL
+    finally:
+        for op in ("copy", "axpy"):
+            bs.bs_ctx_set_tune(ctx, op, 4, 1 << 30)
+        for op in ("norm", "dot", "cg_update"):
+            bs.bs_ctx_set_tune(ctx, op, 4, 2048)
+
+
+def test_error_paths(ctx):
+    L = bs.lib
+    x = torch.zeros(64, dtype=torch.float64, device="cuda")
+    y = torch.zeros(64, dtype=torch.float64, device="cuda")
+    o = scalar_out()
+    s = torch.cuda.current_stream().cuda_stream
+    INVALID = 1
+    h = ctx.handle
+    assert L.bs_copy(h, 0, -1, x.data_ptr(), y.data_ptr(), s) == INVALID
+    assert L.bs_copy(h, 0, 10, None, y.data_ptr(), s) == INVALID
+    assert L.bs_copy(h, 0, 10, x.data_ptr() + 1, y.data_ptr(), s) == INVALID  # misaligned
+    assert L.bs_copy(h, 9, 10, x.data_ptr(), y.data_ptr(), s) == INVALID  # unknown dtype
+    assert L.bs_copy(h, 0, 10, x.data_ptr(), x.data_ptr() + 8, s) == INVALID  # overlap
+    assert L.bs_axpy(h, 0, 10, 1.0, x.data_ptr(), 1.0, x.data_ptr(), s) == INVALID  # y aliases x
+    assert L.bs_norm(h, 0, 10, x.data_ptr(), None, None, s) == INVALID
+    assert L.bs_dot(h, 0, 10, x.data_ptr(), y.data_ptr(), o.data_ptr() + 4, s) == INVALID
+    assert L.bs_cg_update(h, 0, 10, 1.0, x.data_ptr(), y.data_ptr(), x.data_ptr(), y.data_ptr(), None,
+                          o.data_ptr(), s) == INVALID  # r aliases x
+    assert L.bs_ctx_set_tune(h, 0, 0, 3, 16) == INVALID
+    assert L.bs_ctx_set_tune(h, 99, 0, 4, 16) == INVALID
+    # n == 0 with NULL pointers is a valid no-op; reductions write 0
+    assert L.bs_copy(h, 0, 0, None, None, s) == 0
+    assert L.bs_dot(h, 0, 0, None, None, o.data_ptr(), s) == 0
+    assert float(to_host(o)[0]) == 0.0
+    with pytest.raises(bs.BSError):
+        bs.bs_copy(ctx, x, x)
