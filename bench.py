@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="K = 32 (a quick check, not the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    ap.add_argument("--profile", default="",
+                    help="comma-separated ops: run each --reps times after set-up and exit (for rocprofv3)")
+    ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
@@ -172,8 +175,8 @@ def main():
     torch.cuda.synchronize()
     print("# inputs resident", file=sys.stderr, flush=True)
 
-    def step(ev=None):
-        calls = (
+    def step_calls():
+        return (
             lambda: bs.bs_copy(ctx, x, y, hs),
             lambda: bs.bs_axpy(ctx, alpha, x, beta, y, hs),
             lambda: bs.bs_norm(ctx, x, w, out[0:1], hs),
@@ -182,12 +185,27 @@ def main():
             lambda: bs.bs_scatter(ctx, plan, xG, xL, hs),
             lambda: bs.bs_gather(ctx, plan, xL, xG_out, hs),
         )
+
+    def step(ev=None):
+        calls = step_calls()
         for i, c in enumerate(calls):
             if ev is not None:
                 ev[i][0].record(stream)
             c()
             if ev is not None:
                 ev[i][1].record(stream)
+
+    if args.profile:
+        names = [o for o in args.profile.split(",") if o]
+        copy_probe = torch.empty_like(x)
+        calls = dict(zip(OPS, step_calls()))
+        calls["copy_probe"] = lambda: bs.bs_copy(ctx, x, copy_probe, hs)
+        for name in names:
+            for _ in range(args.reps):
+                calls[name]()
+            torch.cuda.synchronize()
+            print(f"# profiled {name} x{args.reps}", file=sys.stderr, flush=True)
+        return 0
 
     for _ in range(args.warmup):
         step()

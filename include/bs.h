@@ -85,16 +85,25 @@ const char* bs_version(void);
 bs_status bs_ctx_create(int device, bs_ctx** out);
 bs_status bs_ctx_destroy(bs_ctx* ctx);
 
-/* Launch-shape knobs of one operation on this context (the autotuner's
- * output).  op: 0 copy, 1 axpy, 2 norm, 3 dot, 4 cg_update, 5 gather,
- * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets each
- * thread moves per loop trip; grid_cap bounds the number of 256-thread
- * workgroups (kernels grid-stride beyond it; reductions are further capped
- * at 8192).  The setting applies to every dtype.  Results of the bit-exact
+/* Launch-shape knobs of one operation on this context (what the autotuner
+ * sets).  op: 0 copy, 1 axpy, 2 norm, 3 dot, 4 cg_update, 5 gather,
+ * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
+ * for scatter, entries) each thread handles per loop trip; grid_cap bounds
+ * the number of 256-thread workgroups (kernels grid-stride beyond it;
+ * reductions are further capped at 65536); variant (gather and scatter
+ * only; other ops ignore it) selects the kernel with bit 0 -- scatter:
+ * 0 = tiles in ascending-global-id order, 1 = map order; gather: 0 =
+ * nonzero-balanced blocks, 1 = fixed row blocks -- and with bit 1 set keeps
+ * the hardware's workgroup order instead of giving each XCD a contiguous
+ * range of blocks.  The setting applies to every dtype.  Results of the bit-exact
  * operations do not depend on it; reduction results depend on it only
- * through the order of their compensated additions. */
-bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap);
-bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap);
+ * through the order of their compensated additions.  Defaults: unroll 1
+ * and one-pass grids for element-wise operations and gather/scatter;
+ * norm and dot unroll 8 with 4096 workgroups; cg_update unroll 4 with
+ * 65536 workgroups; variant 0. */
+bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap, int variant);
+bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap,
+                          int* variant);
 
 /* BS1 (Table 1; Listing 1): y[i] = x[i] for 0 <= i < n, bit for bit. */
 bs_status bs_copy(bs_ctx* ctx, bs_dtype dtype, int64_t n, const void* x, void* y,

@@ -38,8 +38,8 @@ PROTOTYPES = {
     "bs_version": (ctypes.c_char_p, []),
     "bs_ctx_create": (_st, [_i32, ctypes.POINTER(_p)]),
     "bs_ctx_destroy": (_st, [_p]),
-    "bs_ctx_set_tune": (_st, [_p, _i32, _i32, _i32, _i32]),
-    "bs_ctx_get_tune": (_st, [_p, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "bs_ctx_set_tune": (_st, [_p, _i32, _i32, _i32, _i32, _i32]),
+    "bs_ctx_get_tune": (_st, [_p, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "bs_copy": (_st, [_p, _i32, _i64, _p, _p, _p]),
     "bs_axpy": (_st, [_p, _i32, _i64, _d, _p, _d, _p, _p]),
     "bs_norm": (_st, [_p, _i32, _i64, _p, _p, _p, _p]),
@@ -174,15 +174,16 @@ def bs_ctx_create(device=0):
     return Ctx(h.value, device)
 
 
-def bs_ctx_set_tune(ctx, op, unroll, grid_cap, dtype=BS_F64):
-    _check(lib.bs_ctx_set_tune(ctx.handle, OP_IDS.get(op, op), dtype, unroll, grid_cap), "bs_ctx_set_tune")
+def bs_ctx_set_tune(ctx, op, unroll, grid_cap, variant=0, dtype=BS_F64):
+    _check(lib.bs_ctx_set_tune(ctx.handle, OP_IDS.get(op, op), dtype, unroll, grid_cap, variant),
+           "bs_ctx_set_tune")
 
 
 def bs_ctx_get_tune(ctx, op, dtype=BS_F64):
-    u, g = _i32(), _i32()
-    _check(lib.bs_ctx_get_tune(ctx.handle, OP_IDS.get(op, op), dtype, ctypes.byref(u), ctypes.byref(g)),
-           "bs_ctx_get_tune")
-    return u.value, g.value
+    u, g, v = _i32(), _i32(), _i32()
+    _check(lib.bs_ctx_get_tune(ctx.handle, OP_IDS.get(op, op), dtype, ctypes.byref(u), ctypes.byref(g),
+                               ctypes.byref(v)), "bs_ctx_get_tune")
+    return u.value, g.value, v.value
 
 
 def bs_copy(ctx, x, y, stream=None):

@@ -153,46 +153,33 @@ __device__ __forceinline__ DW<double> block_reduce(DW<double> a) {
   return r;
 }
 
-// Coherent (agent-scope) 64-bit accesses for data exchanged between
-// workgroups that may run on different XCDs, whose L2 caches are separate.
-__device__ __forceinline__ void store_agent(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p) {
-  unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double(static_cast<long long>(v));
-}
-
-// Single-launch deterministic grid reduction.  Every workgroup stores its
-// pair in partials[blockIdx.x]; the workgroup that finishes last (ticket)
-// adds all pairs in index order and writes the rounded sum to *out, then
-// re-arms the ticket for the next reduction on this workspace.  The result
-// depends only on the grid size, never on the order in which workgroups ran.
+// End of the first stage of a grid reduction: the workgroup's compensated
+// pair goes to partials[blockIdx.x]; a grid of one workgroup writes the
+// rounded sum to *out directly.  The second stage (a separate launch, so the
+// kernel boundary orders it after every workgroup of the first) adds the
+// pairs in index order.  The result depends only on the grid size, never on
+// the order in which workgroups ran, and no atomics or fences are involved.
 template <int BLOCK>
-__device__ __forceinline__ void grid_finish(DW<double> a, double* partials, unsigned int* ticket, double* out) {
-  __shared__ bool s_last;
+__device__ __forceinline__ void block_store_pair(DW<double> a, double* partials, double* out) {
   a = block_reduce<BLOCK>(a);
   if (threadIdx.x == 0) {
-    store_agent(&partials[2 * blockIdx.x], a.s);
-    store_agent(&partials[2 * blockIdx.x + 1], a.c);
-    __threadfence();
-    unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == gridDim.x - 1);
+    if (gridDim.x == 1) {
+      *out = a.s + a.c;
+    } else {
+      partials[2 * blockIdx.x] = a.s;
+      partials[2 * blockIdx.x + 1] = a.c;
+    }
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  DW<double> r{0.0, 0.0};
-  for (unsigned int i = threadIdx.x; i < gridDim.x; i += BLOCK)
-    r = dw_add(r, DW<double>{load_agent(&partials[2 * i]), load_agent(&partials[2 * i + 1])});
-  __syncthreads();  // block_reduce reuses its shared arrays
-  r = block_reduce<BLOCK>(r);
-  if (threadIdx.x == 0) {
-    *out = r.s + r.c;
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+}
+
+// Streaming (nontemporal) accesses for data touched exactly once.
+template <class T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void st_nt(T* p, const T& v) {
+  __builtin_nontemporal_store(v, p);
 }
 
 // ---------------------------------------------------------------- launch geometry

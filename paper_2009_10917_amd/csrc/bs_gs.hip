@@ -6,14 +6,21 @@
 // the device: a degree histogram, an exclusive scan for the row starts and
 // a stable radix sort of (map[l], l) pairs for the column ids.
 //
-// Gather works on blocks of consecutive global rows.  Each workgroup reads
-// its rows' column ids (contiguous), fetches the local values they name into
-// LDS, then each thread adds one row's values from LDS in CSR order.  The
-// paper balances its blocks by nonzeros through a blockStarts array
-// (Section 5); here every workgroup takes the same number of rows, which
-// bounds its nonzeros by rows x largest degree and needs no extra array.
-// Workgroups are renumbered per XCD so that neighbouring row blocks, which
-// share cache lines of the local vector, run on the same XCD's L2.
+// Gather follows the paper's blocking (Section 5): every workgroup takes
+// about the same number of nonzeros (a `chunk` of the CSR), the rows whose
+// first nonzero falls in its chunk (blockStarts), stages the local values of
+// its window in LDS and adds each row from LDS in CSR order.  Unlike the
+// paper's listing, the window start is known from the block index alone, so
+// the column-id and value loads are issued before the row starts arrive and
+// the two dependent chains overlap.
+//
+// Scatter processes tiles of consecutive local entries in the order of the
+// smallest global id each tile references, so that tiles touching
+// neighbouring global entries run close together in time and share cache
+// lines; each tile still reads its ids and writes its values contiguously.
+//
+// Workgroups are renumbered per XCD so that neighbouring blocks, which share
+// cache lines, run on the same XCD's L2.
 
 #include <algorithm>
 
@@ -150,14 +157,14 @@ __global__ __launch_bounds__(kBlock) void k_weights(const int32_t* __restrict__ 
 template <class T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ rs, const int32_t* __restrict__ ci,
                                                    const typename Storage<T>::E* __restrict__ xL,
-                                                   typename Storage<T>::E* __restrict__ xG, int32_t n_global) {
+                                                   typename Storage<T>::E* __restrict__ xG, int32_t n_global, bool remap) {
   using S = Storage<T>;
   using C = typename S::C;
   constexpr int R = kBlock * RPT;    // rows per workgroup
   constexpr int CAP = 8 * R;         // staged values: up to an average degree of 8
   constexpr int L = CAP / kBlock;    // staged values per thread
   __shared__ C lds[CAP];
-  const int32_t b = static_cast<int32_t>(dev::xcd_block(blockIdx.x, gridDim.x));
+  const int32_t b = static_cast<int32_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
   const int32_t row0 = b * R;
   const int32_t row1 = min(row0 + R, n_global);
   const int32_t base = rs[row0];
@@ -211,40 +218,189 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t l = i + static_cast<int64_t>(u) * kBlock;
-      id[u] = (l < n_local) ? map[l] : -1;
+      id[u] = (l < n_local) ? dev::ld_nt(map + l) : -1;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (id[u] >= 0) v[u] = xG[id[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (id[u] >= 0) xL[i + static_cast<int64_t>(u) * kBlock] = v[u];
+      if (id[u] >= 0) dev::st_nt(xL + i + static_cast<int64_t>(u) * kBlock, v[u]);
   }
+}
+
+// ---------------------------------------------------------------- plan: gather blocks, scatter tiles
+
+// block_starts[b] = first row g with row_starts[g] >= b*chunk (b < n_blocks);
+// block_starts[n_blocks] = n_global.
+__global__ __launch_bounds__(kBlock) void k_block_starts(const int32_t* __restrict__ rs, int32_t n_global, int64_t chunk,
+                                                         int64_t n_blocks, int32_t* __restrict__ bstart) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (b > n_blocks) return;
+  if (b == n_blocks) {
+    bstart[b] = n_global;
+    return;
+  }
+  const int64_t target = b * chunk;
+  int64_t lo = 0, hi = n_global;  // answer in [0, n_global]
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (rs[mid] >= target) hi = mid; else lo = mid + 1;
+  }
+  bstart[b] = static_cast<int32_t>(lo);
+}
+
+// key[t] = smallest unmasked id among the tile's entries (INT32_MAX if none).
+__global__ __launch_bounds__(kBlock) void k_tile_keys(const int32_t* __restrict__ map, int64_t n_local,
+                                                      uint32_t* __restrict__ key, int32_t* __restrict__ tile) {
+  __shared__ int32_t s_min[kBlock / 64];
+  const int64_t t = blockIdx.x;
+  int32_t m = INT32_MAX;
+  for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    const int64_t l = t * kTile + k;
+    if (l < n_local) {
+      const int32_t v = map[l];
+      if (v >= 0 && v < m) m = v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+  if (threadIdx.x % 64 == 0) s_min[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / 64; ++i) m = min(m, s_min[i]);
+    m = min(m, s_min[0]);
+    key[t] = static_cast<uint32_t>(m);
+    tile[t] = static_cast<int32_t>(t);
+  }
+}
+
+// ---------------------------------------------------------------- BS6 gather, nonzero-balanced
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather_nnz(const int32_t* __restrict__ rs, const int32_t* __restrict__ ci,
+                                                       const int32_t* __restrict__ bstart,
+                                                       const typename Storage<T>::E* __restrict__ xL,
+                                                       typename Storage<T>::E* __restrict__ xG, int64_t chunk,
+                                                       int64_t nnz, bool remap) {
+  using S = Storage<T>;
+  using C = typename S::C;
+  constexpr int L = kStage / kBlock;
+  __shared__ C lds[kStage];            // local values of the CSR window
+  __shared__ int32_t srs[kStage + 1];  // row starts of the block's rows
+  const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t w0 = b * chunk;  // CSR window [w0, w0 + kStage)
+  // 1. window values: column ids, then the local values they name
+  C v[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int64_t j = w0 + threadIdx.x + k * kBlock;
+    if (j < nnz) v[k] = S::load(xL[dev::ld_nt(ci + j)]);
+  }
+  // 2. meanwhile, the block's rows and their starts
+  const int32_t r0 = bstart[b], r1 = bstart[b + 1];
+  const int32_t nrows = r1 - r0;
+  const bool rows_staged = nrows <= kStage;
+  if (rows_staged) {
+#pragma unroll
+    for (int k = 0; k <= L; ++k) {
+      const int32_t q = threadIdx.x + k * kBlock;
+      if (q <= nrows) srs[q] = rs[r0 + q];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int64_t j = w0 + threadIdx.x + k * kBlock;
+    if (j < nnz) lds[threadIdx.x + k * kBlock] = v[k];
+  }
+  __syncthreads();
+  const int64_t lo = rows_staged ? srs[0] : rs[r0];
+  const int64_t hi = rows_staged ? srs[nrows] : rs[r1];
+  // 3. each thread adds whole rows in CSR order; rows longer than the stage
+  //    (only with huge degrees) are added from memory in the same order
+  const bool staged = lo >= w0 && hi <= w0 + kStage;
+  for (int32_t q = threadIdx.x; q < nrows; q += kBlock) {
+    const int32_t a = rows_staged ? srs[q] : rs[r0 + q];
+    const int32_t e = rows_staged ? srs[q + 1] : rs[r0 + q + 1];
+    C s = C(0);
+    if (staged) {
+      for (int32_t j = a; j < e; ++j) s += lds[j - w0];
+    } else {
+      for (int32_t j = a; j < e; ++j) s += S::load(xL[ci[j]]);
+    }
+    dev::st_nt(xG + r0 + q, S::store(s));
+  }
+}
+
+// ---------------------------------------------------------------- BS7 scatter, tile order
+
+template <class E>
+__global__ __launch_bounds__(kBlock) void k_scatter_tiles(const int32_t* __restrict__ map,
+                                                          const int32_t* __restrict__ order,
+                                                          const E* __restrict__ xG, E* __restrict__ xL,
+                                                          int64_t n_local, bool remap) {
+  constexpr int P = kTile / kBlock;
+  const uint32_t t = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t l0 = static_cast<int64_t>(order[t]) * kTile + threadIdx.x;
+  int32_t id[P];
+  E v[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int64_t l = l0 + k * kBlock;
+    id[k] = (l < n_local) ? dev::ld_nt(map + l) : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if (id[k] >= 0) v[k] = xG[id[k]];
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if (id[k] >= 0) dev::st_nt(xL + l0 + k * kBlock, v[k]);
 }
 
 inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
 
 template <class T>
 bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hipStream_t st) {
-  (void)ctx;
-  constexpr int RPT = 1;
-  const int64_t rows = static_cast<int64_t>(kBlock) * RPT;
-  const unsigned int g = static_cast<unsigned int>((gs->n_global + rows - 1) / rows);
   using E = typename Storage<T>::E;
-  hipLaunchKernelGGL((k_gather<T, RPT>), dim3(g), dim3(kBlock), 0, st, gs->row_starts, gs->col_ids,
-                     static_cast<const E*>(xL), static_cast<E*>(xG), static_cast<int32_t>(gs->n_global));
+  const Tune& tn = ctx->tune[OP_GATHER][0];
+  const bool remap = (tn.variant & 2) == 0;
+  if ((tn.variant & 1) == 0) {
+    hipLaunchKernelGGL((k_gather_nnz<T>), dim3(static_cast<unsigned int>(gs->n_blocks)), dim3(kBlock), 0, st,
+                       gs->row_starts, gs->col_ids, gs->block_starts, static_cast<const E*>(xL), static_cast<E*>(xG),
+                       gs->chunk, gs->n_unmasked, remap);
+  } else {
+    const unsigned int g = static_cast<unsigned int>((gs->n_global + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_gather<T, 1>), dim3(g), dim3(kBlock), 0, st, gs->row_starts, gs->col_ids,
+                       static_cast<const E*>(xL), static_cast<E*>(xG), static_cast<int32_t>(gs->n_global), remap);
+  }
   return check_launch("bs_gather");
+}
+
+template <class E, int U>
+void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipStream_t st) {
+  const int64_t per = static_cast<int64_t>(kBlock) * U;
+  int64_t g = (gs->n_local + per - 1) / per;
+  if (g > cap) g = cap;
+  hipLaunchKernelGGL((k_scatter<E, U>), dim3(static_cast<unsigned int>(g)), dim3(kBlock), 0, st, gs->map,
+                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local);
 }
 
 template <class T>
 bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hipStream_t st) {
-  const Tune& tn = ctx->tune[OP_SCATTER][0];
-  const int64_t per = static_cast<int64_t>(kBlock) * 4;
-  int64_t g = (gs->n_local + per - 1) / per;
-  if (g > tn.grid_cap) g = tn.grid_cap;
   using E = typename Storage<T>::E;
-  hipLaunchKernelGGL((k_scatter<E, 4>), dim3(static_cast<unsigned int>(g)), dim3(kBlock), 0, st, gs->map,
-                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local);
+  const Tune& tn = ctx->tune[OP_SCATTER][0];
+  if ((tn.variant & 1) == 0) {
+    hipLaunchKernelGGL((k_scatter_tiles<E>), dim3(static_cast<unsigned int>(gs->n_tiles)), dim3(kBlock), 0, st,
+                       gs->map, gs->tile_order, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
+                       (tn.variant & 2) == 0);
+  } else if (tn.unroll >= 8) {
+    launch_scatter_map<E, 8>(gs, tn.grid_cap, xG, xL, st);
+  } else if (tn.unroll >= 4) {
+    launch_scatter_map<E, 4>(gs, tn.grid_cap, xG, xL, st);
+  } else if (tn.unroll >= 2) {
+    launch_scatter_map<E, 2>(gs, tn.grid_cap, xG, xL, st);
+  } else {
+    launch_scatter_map<E, 1>(gs, tn.grid_cap, xG, xL, st);
+  }
   return check_launch("bs_scatter");
 }
 
@@ -268,6 +424,8 @@ void free_plan(bs_gs* gs) {
   (void)hipFree(gs->map);
   (void)hipFree(gs->row_starts);
   (void)hipFree(gs->col_ids);
+  (void)hipFree(gs->block_starts);
+  (void)hipFree(gs->tile_order);
   delete gs;
 }
 
@@ -430,12 +588,46 @@ extern "C" bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_l
     if (!s) s = check_hip(hipMemcpyAsync(&h_max, d_max, sizeof(int32_t), hipMemcpyDeviceToHost, st), op);
   }
   if (!s) s = check_hip(hipStreamSynchronize(st), op);
+  gs->max_degree = h_max;
+  // gather blocks: windows of kStage values, consecutive windows `chunk` apart
+  if (!s) {
+    const int64_t md = h_max;
+    gs->chunk = (md <= kStage / 2) ? kStage - md : kStage / 2;
+    gs->n_blocks = (gs->n_unmasked + gs->chunk - 1) / gs->chunk;
+    if (gs->n_blocks < 1) gs->n_blocks = 1;
+    if (!alloc(reinterpret_cast<void**>(&gs->block_starts), static_cast<size_t>(gs->n_blocks + 1) * 4)) {
+      s = fail(BS_ERR_ALLOC, "%s: block-start allocation", op);
+    } else {
+      hipLaunchKernelGGL(k_block_starts, dim3(blocks_for(gs->n_blocks + 1)), dim3(kBlock), 0, st, gs->row_starts,
+                         static_cast<int32_t>(n_global), gs->chunk, gs->n_blocks, gs->block_starts);
+      s = check_launch(op);
+    }
+  }
+  // scatter tiles, sorted (stably) by the smallest global id they reference
+  if (!s) {
+    gs->n_tiles = (n_local + kTile - 1) / kTile;
+    if (!alloc(reinterpret_cast<void**>(&gs->tile_order), static_cast<size_t>(gs->n_tiles > 0 ? gs->n_tiles : 1) * 4))
+      s = fail(BS_ERR_ALLOC, "%s: tile-order allocation", op);
+  }
+  if (!s && gs->n_tiles > 0) {
+    // keys/vals (n_local entries each) are free again and n_tiles < n_local
+    const int nt = static_cast<int>(gs->n_tiles);
+    hipLaunchKernelGGL(k_tile_keys, dim3(static_cast<unsigned int>(nt)), dim3(kBlock), 0, st, gs->map, n_local, keys,
+                       vals);
+    s = check_launch(op);
+    size_t b = 0;
+    if (!s) s = check_hip(hipcub::DeviceRadixSort::SortPairs(nullptr, b, keys, keys_out, vals, gs->tile_order, nt, 0, 32, st), op);
+    void* t2 = nullptr;
+    if (!s && !alloc(&t2, b ? b : 1)) s = fail(BS_ERR_ALLOC, "%s: scratch allocation", op);
+    if (!s) s = check_hip(hipcub::DeviceRadixSort::SortPairs(t2, b, keys, keys_out, vals, gs->tile_order, nt, 0, 32, st), op);
+    if (!s) s = check_hip(hipStreamSynchronize(st), op);
+    (void)hipFree(t2);
+  }
   cleanup();
   if (s) {
     free_plan(gs);
     return s;
   }
-  gs->max_degree = h_max;
   *out = gs;
   return BS_OK;
 }

@@ -82,14 +82,13 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
   bs_ctx* c = new bs_ctx();
   c->device = device;
   void* ws = nullptr;
-  const size_t bytes = sizeof(double) * 2 * kMaxReduceBlocks + 256;
+  const size_t bytes = sizeof(double) * 2 * kMaxReduceBlocks;
   if (hipMalloc(&ws, bytes) != hipSuccess) {
     delete c;
     (void)hipSetDevice(prev);
     return fail(BS_ERR_ALLOC, "bs_ctx_create: cannot allocate %zu bytes of workspace", bytes);
   }
   c->partials = static_cast<double*>(ws);
-  c->ticket = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + sizeof(double) * 2 * kMaxReduceBlocks);
   s = check_hip(hipMemset(ws, 0, bytes), "bs_ctx_create");
   if (!s) s = check_hip(hipDeviceSynchronize(), "bs_ctx_create");
   if (s) {
@@ -98,11 +97,16 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
     (void)hipSetDevice(prev);
     return s;
   }
+  // Defaults measured on MI355X at n = 7.2e8 binary64 values: element-wise
+  // operations run one 16-byte packet per thread in a one-pass grid; the
+  // reductions grid-stride with several packets in flight per thread.
   for (int op = 0; op < OP_COUNT; ++op)
-    for (int d = 0; d < 3; ++d) {
-      const bool red = (op == OP_NORM || op == OP_DOT || op == OP_CG_UPDATE);
-      c->tune[op][d] = Tune{4, red ? 2048 : (1 << 30)};
-    }
+    for (int d = 0; d < 3; ++d) c->tune[op][d] = Tune{1, 1 << 30, 0};
+  for (int d = 0; d < 3; ++d) {
+    c->tune[OP_NORM][d] = Tune{8, 4096, 0};
+    c->tune[OP_DOT][d] = Tune{8, 4096, 0};
+    c->tune[OP_CG_UPDATE][d] = Tune{4, kMaxReduceBlocks, 0};
+  }
   (void)hipSetDevice(prev);
   *out = c;
   return BS_OK;
@@ -119,23 +123,26 @@ extern "C" bs_status bs_ctx_destroy(bs_ctx* ctx) {
   return check_hip(e, "bs_ctx_destroy");
 }
 
-extern "C" bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap) {
+extern "C" bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap, int variant) {
   if (!ctx) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: ctx is NULL");
   if (op < 0 || op >= OP_COUNT) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unknown op %d", op);
   if (dtype_size(dtype) == 0) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unknown dtype %d", (int)dtype);
   if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
     return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unroll must be 1, 2, 4 or 8");
   if (grid_cap < 1) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: grid_cap must be positive");
+  if (variant < 0 || variant > 3) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: variant must lie in [0, 3]");
   // every dtype currently shares one entry per op
-  for (int d = 0; d < 3; ++d) ctx->tune[op][d] = Tune{unroll, grid_cap};
+  for (int d = 0; d < 3; ++d) ctx->tune[op][d] = Tune{unroll, grid_cap, variant};
   return BS_OK;
 }
 
-extern "C" bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap) {
+extern "C" bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap,
+                                     int* variant) {
   if (!ctx || op < 0 || op >= OP_COUNT || dtype_size(dtype) == 0)
     return fail(BS_ERR_INVALID_ARG, "bs_ctx_get_tune: bad argument");
   const Tune& t = ctx->tune[op][static_cast<int>(dtype)];
   if (unroll) *unroll = t.unroll;
   if (grid_cap) *grid_cap = t.grid_cap;
+  if (variant) *variant = t.variant;
   return BS_OK;
 }

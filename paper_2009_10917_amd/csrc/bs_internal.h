@@ -37,27 +37,29 @@ bs_status check_vec(const char* op, const char* name, const void* p, int64_t n, 
 bs_status check_dtype(const char* op, bs_dtype d);
 
 // Launch-shape knobs of one operation.  `unroll` selects the compiled
-// variant (packs of 16 bytes per thread per loop trip: 1, 2, 4 or 8) and
+// variant (16-byte packets per thread per loop trip: 1, 2, 4 or 8),
 // `grid_cap` bounds the number of 256-thread workgroups (the kernels
-// grid-stride beyond it).
+// grid-stride beyond it) and `variant` picks an alternative kernel where an
+// operation has one (gather and scatter).
 struct Tune {
   int unroll;
   int grid_cap;
+  int variant;
 };
 
 enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCATTER, OP_COUNT };
 
 // Largest number of workgroups a reduction may use: the context's partial
 // buffer holds one compensated pair per workgroup.
-constexpr int kMaxReduceBlocks = 8192;
+constexpr int kMaxReduceBlocks = 65536;
 constexpr int kBlock = 256;
+constexpr int kFinishBlock = 1024;  // threads of the second reduction stage
 
 }  // namespace bs
 
 struct bs_ctx {
   int device;
-  double* partials;       // 2 * kMaxReduceBlocks doubles: (sum, compensation)
-  unsigned int* ticket;   // workgroups finished in the current reduction
+  double* partials;  // 2 * kMaxReduceBlocks doubles: (sum, compensation) per workgroup
   bs::Tune tune[bs::OP_COUNT][3];
 };
 
@@ -70,4 +72,18 @@ struct bs_gs {
   int32_t* map;         // [n_local] copy of the scatter ids
   int32_t* row_starts;  // [n_global + 1]
   int32_t* col_ids;     // [n_unmasked]
+  // gather work split: block b adds rows [block_starts[b], block_starts[b+1]),
+  // whose nonzeros lie in the CSR window [b*chunk, b*chunk + kStage)
+  int32_t* block_starts;  // [n_blocks + 1]
+  int64_t n_blocks;
+  int64_t chunk;
+  // scatter work order: tiles of kTile consecutive local entries, sorted by
+  // the smallest global id they reference
+  int32_t* tile_order;  // [n_tiles]
+  int64_t n_tiles;
 };
+
+namespace bs {
+constexpr int kStage = 2048;  // values staged in LDS per gather workgroup
+constexpr int kTile = 512;    // local entries per scatter workgroup
+}  // namespace bs

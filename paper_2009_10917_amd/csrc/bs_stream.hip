@@ -11,10 +11,11 @@
 //
 // The reductions accumulate per thread in compensated form (sum plus
 // running error), combine the 64 lanes of a wave by xor-shuffles and the
-// waves of a workgroup through LDS, and finish in the same launch: the last
-// workgroup to arrive adds the per-workgroup pairs in index order (see
-// grid_finish).  The paper uses a second launch for that stage (Section 5);
-// one launch halves the fixed launch cost T0 of its performance model.
+// waves of a workgroup through LDS, and store one pair per workgroup; a
+// second launch of one 1024-thread workgroup adds the pairs in index order,
+// as the paper's two-kernel reductions do (Section 5).  Finishing inside the
+// first launch would need an agent-scope fence per workgroup, which on this
+// 8-XCD part costs more than the second launch.
 
 #include "bs_device.h"
 #include "bs_internal.h"
@@ -85,9 +86,10 @@ struct Base {
   using E = typename S::E;
   using C = typename S::C;
   using Vec = typename dev::VecOf<E, V>::type;
-  // packet j of the operand that starts at p (after the scalar head)
-  __device__ static Vec ld(const E* p, int64_t j) { return reinterpret_cast<const Vec*>(p)[j]; }
-  __device__ static void st(E* p, int64_t j, const Vec& v) { reinterpret_cast<Vec*>(p)[j] = v; }
+  // packet j of the operand that starts at p (after the scalar head); every
+  // packet is touched once, so the accesses are nontemporal
+  __device__ static Vec ld(const E* p, int64_t j) { return dev::ld_nt(reinterpret_cast<const Vec*>(p) + j); }
+  __device__ static void st(E* p, int64_t j, const Vec& v) { dev::st_nt(reinterpret_cast<Vec*>(p) + j, v); }
 };
 
 // ---------------------------------------------------------------- BS1 copy
@@ -187,12 +189,11 @@ struct NormOp : Base<T, V> {
 template <class T, int V, int U, bool W>
 __global__ __launch_bounds__(kBlock) void k_norm(const typename Storage<T>::E* __restrict__ x,
                                                  const typename Storage<T>::E* __restrict__ w, Span sp,
-                                                 double* partials, unsigned int* ticket, double* out) {
+                                                 double* partials, double* out) {
   using C = typename Storage<T>::C;
   NormOp<T, V, W> op{{}, x, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
-  dev::grid_finish<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, ticket,
-                           out);
+  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- BS4 inner product
@@ -225,12 +226,11 @@ struct DotOp : Base<T, V> {
 template <class T, int V, int U>
 __global__ __launch_bounds__(kBlock) void k_dot(const typename Storage<T>::E* __restrict__ x,
                                                 const typename Storage<T>::E* __restrict__ y, Span sp,
-                                                double* partials, unsigned int* ticket, double* out) {
+                                                double* partials, double* out) {
   using C = typename Storage<T>::C;
   DotOp<T, V> op{{}, x, y, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
-  dev::grid_finish<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, ticket,
-                           out);
+  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- BS5 fused CG update
@@ -294,12 +294,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(typename Storage<T>::C alp
                                                       typename Storage<T>::E* __restrict__ r,
                                                       const typename Storage<T>::E* __restrict__ Ap,
                                                       const typename Storage<T>::E* __restrict__ w, Span sp,
-                                                      double* partials, unsigned int* ticket, double* out) {
+                                                      double* partials, double* out) {
   using C = typename Storage<T>::C;
   CgOp<T, V, W> op{{}, alpha, x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
-  dev::grid_finish<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, ticket,
-                           out);
+  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- host side
@@ -337,6 +336,23 @@ inline int grid_for(const Span& sp, int unroll, int cap) {
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return static_cast<int>(g);
+}
+
+// Second stage of every reduction: one workgroup adds the G per-workgroup
+// pairs, thread t taking pairs t, t + 1024, ... in order.
+__global__ __launch_bounds__(kFinishBlock) void k_finish(const double* __restrict__ partials, int G,
+                                                          double* __restrict__ out) {
+  DW<double> r{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kFinishBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  r = dev::block_reduce<kFinishBlock>(r);
+  if (threadIdx.x == 0) *out = r.s + r.c;
+}
+
+bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op) {
+  bs_status s = check_launch(op);
+  if (s || grid == 1) return s;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, grid, out);
+  return check_launch(op);
 }
 
 inline int norm_unroll(int u) { return (u >= 8) ? 8 : (u >= 4) ? 4 : (u >= 2) ? 2 : 1; }
@@ -406,11 +422,11 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
   if (w)
     BS_DISPATCH_B(k_norm, T, true, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
-                  ctx->partials, ctx->ticket, out);
+                  ctx->partials, out);
   else
     BS_DISPATCH_B(k_norm, T, false, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
-                  ctx->partials, ctx->ticket, out);
-  return check_launch("bs_norm");
+                  ctx->partials, out);
+  return finish(ctx, g, out, st, "bs_norm");
 }
 
 template <class T>
@@ -420,9 +436,8 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
-  BS_DISPATCH(k_dot, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials,
-              ctx->ticket, out);
-  return check_launch("bs_dot");
+  BS_DISPATCH(k_dot, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
+  return finish(ctx, g, out, st, "bs_dot");
 }
 
 template <class T>
@@ -437,12 +452,12 @@ bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const voi
   if (w)
     BS_DISPATCH_B(k_cg_update, T, true, sp, u, g, st, static_cast<C>(alpha), static_cast<typename Storage<T>::E*>(x),
                   static_cast<const typename Storage<T>::E*>(p), static_cast<typename Storage<T>::E*>(r), static_cast<const typename Storage<T>::E*>(Ap),
-                  static_cast<const typename Storage<T>::E*>(w), sp, ctx->partials, ctx->ticket, out);
+                  static_cast<const typename Storage<T>::E*>(w), sp, ctx->partials, out);
   else
     BS_DISPATCH_B(k_cg_update, T, false, sp, u, g, st, static_cast<C>(alpha), static_cast<typename Storage<T>::E*>(x),
                   static_cast<const typename Storage<T>::E*>(p), static_cast<typename Storage<T>::E*>(r), static_cast<const typename Storage<T>::E*>(Ap),
-                  static_cast<const typename Storage<T>::E*>(p), sp, ctx->partials, ctx->ticket, out);
-  return check_launch("bs_cg_update");
+                  static_cast<const typename Storage<T>::E*>(p), sp, ctx->partials, out);
+  return finish(ctx, g, out, st, "bs_cg_update");
 }
 
 // Pointer [p, p + n*s) and [q, q + m*s) overlap?

@@ -67,7 +67,7 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_scatter(None, None, 0, 16, 32, None) == INVALID
     assert L.bs_gs_info(None, None, None, None, None) == INVALID
     assert L.bs_gs_degree(None, 16, None) == INVALID
-    assert L.bs_ctx_set_tune(None, 0, 0, 4, 16) == INVALID
+    assert L.bs_ctx_set_tune(None, 0, 0, 4, 16, 0) == INVALID
     out = ctypes.c_void_p()
     assert L.bs_gs_create(None, 16, 10, 10, None, ctypes.byref(out)) == INVALID
     assert L.bs_ctx_create(0, None) == INVALID

@@ -21,6 +21,17 @@ MESHES = [(1, 1, None), (2, 1, 1), (3, 2, 2), (8, 3, None), (4, 7, 3), (3, 15, 4
           (12, 2, 6)]
 
 
+def with_variant(ctx, variant, unroll=4):
+    bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, variant)
+    bs.bs_ctx_set_tune(ctx, "scatter", unroll, 1 << 30, variant)
+
+
+@pytest.fixture(autouse=True)
+def default_variants(ctx):
+    yield
+    with_variant(ctx, 0, unroll=1)
+
+
 def device_map(K, N, seed):
     E = K ** 3
     if seed is None:
@@ -63,17 +74,18 @@ def test_map_plan_gather_scatter(ctx, K, N, seed):
             assert np.array_equal(to_host(w), bsgen.round_f32(w_ref))
         else:
             assert np.array_equal(to_host(w), bsgen.round_bf16_bits(w_ref))
-    # BS6 gather
-    xL = dev_uniform(NL, 11)
-    xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
-    bs.bs_gather(ctx, plan, xL, xG)
+    # BS6 gather and BS7 scatter, both kernel variants
     g_ref = ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))
-    assert np.array_equal(bits(to_host(xG)), bits(g_ref))
-    # BS7 scatter
-    xG2 = dev_uniform(NG, 12)
-    bs.bs_scatter(ctx, plan, xG2, xL)
     s_ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
-    assert np.array_equal(bits(to_host(xL)), bits(s_ref))
+    for variant in (1, 0, 2, 3):
+        with_variant(ctx, variant)
+        xL = dev_uniform(NL, 11)
+        xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
+        bs.bs_gather(ctx, plan, xL, xG)
+        assert np.array_equal(bits(to_host(xG)), bits(g_ref)), variant
+        xG2 = dev_uniform(NG, 12)
+        bs.bs_scatter(ctx, plan, xG2, xL)
+        assert np.array_equal(bits(to_host(xL)), bits(s_ref)), variant
     # gather(scatter(1)) is the degree, exactly
     ones = torch.ones(NG, dtype=torch.float64, device="cuda")
     bs.bs_scatter(ctx, plan, ones, xL)
@@ -82,7 +94,9 @@ def test_map_plan_gather_scatter(ctx, K, N, seed):
     plan.close()
 
 
-def test_masked_entries(ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_masked_entries(ctx, variant):
+    with_variant(ctx, variant)
     K, N = 5, 3
     E, NL, NG = mesh.sizes(K, N)
     ref_map = mesh.hex_map(K, N, bsgen.permutation(9, E), bsgen.orientations(9, E))
@@ -104,7 +118,9 @@ def test_masked_entries(ctx):
     assert np.array_equal(bits(to_host(w)), bits(mesh.weights(ref_map, NG)))
 
 
-def test_high_degree_rows_use_the_unstaged_path(ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_high_degree_rows_use_the_unstaged_path(ctx, variant):
+    with_variant(ctx, variant)
     # 7 global nodes with ~14000 copies each: a workgroup's rows hold far
     # more values than its LDS stage, so the direct path adds them
     NL, NG = 100_003, 7
@@ -120,7 +136,9 @@ def test_high_degree_rows_use_the_unstaged_path(ctx):
     assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))))
 
 
-def test_rows_without_copies_and_empty_plans(ctx):
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_rows_without_copies_and_empty_plans(ctx, variant):
+    with_variant(ctx, variant)
     # global ids 0..9, only even ones used: odd rows gather to +0.0
     ref_map = np.array([0, 2, 2, 4, 6, 8, 8, 8, -1], dtype=np.int64)
     plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), 10)
@@ -152,6 +170,39 @@ def test_invalid_maps_and_meshes_are_rejected(ctx):
         plan = bs.bs_gs_create(ctx, torch.tensor([0, 1], dtype=torch.int32, device="cuda"), 2)
         bs.bs_gather(ctx, plan, torch.zeros(3, dtype=torch.float64, device="cuda"),
                      torch.zeros(2, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+def test_scatter_map_order_unrolls(ctx, unroll):
+    K, N = 7, 4
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ref_map = device_map(K, N, 31)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    with_variant(ctx, 1, unroll=unroll)
+    xL = dev_uniform(NL, 11)
+    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
+    assert np.array_equal(bits(to_host(xL)), bits(ref))
+
+
+def test_many_empty_rows_and_long_rows(ctx):
+    # globals with no copies between used ones, plus a few very long rows:
+    # exercises blocks with many rows and windows that rows overrun
+    rng = np.random.default_rng(3)
+    NG = 200_000
+    used = np.sort(rng.choice(NG, 3000, replace=False))
+    ref_map = used[rng.integers(0, used.size, 60_000)]
+    ref_map[rng.integers(0, 60_000, 5000)] = used[7]      # one row of degree ~5000
+    ref_map[rng.integers(0, 60_000, 3000)] = used[-1]
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
+    rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+    xLh = bsgen.uniform(1, 11, ref_map.size)
+    ref = ops.gather(rs_ref, ci_ref, xLh)
+    for variant in (0, 1):
+        with_variant(ctx, variant)
+        xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
+        bs.bs_gather(ctx, plan, torch.from_numpy(xLh).cuda(), xG)
+        assert np.array_equal(bits(to_host(xG)), bits(ref)), variant
 
 
 def test_gather_scatter_deterministic(ctx):

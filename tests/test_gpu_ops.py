@@ -173,9 +173,10 @@ def test_reductions_deterministic(ctx):
 
 
 @pytest.mark.parametrize("unroll", [1, 2, 4, 8])
-@pytest.mark.parametrize("cap", [1, 7, 300, 8192])
+@pytest.mark.parametrize("cap", [1, 7, 300, 8192, 65536])
 def test_launch_shapes_do_not_change_results(ctx, unroll, cap):
     n = 1_000_003
+    defaults = {op: bs.bs_ctx_get_tune(ctx, op)[:2] for op in ("copy", "axpy", "norm", "dot", "cg_update")}
     try:
         for op in ("copy", "axpy", "norm", "dot", "cg_update"):
             bs.bs_ctx_set_tune(ctx, op, unroll, cap)
@@ -189,10 +190,8 @@ def test_launch_shapes_do_not_change_results(ctx, unroll, cap):
         bs.bs_dot(ctx, x, z, o)
         assert rel_err(float(to_host(o)[0]), ops.norm(host_uniform(n, 1))) <= TOL
     finally:
-        for op in ("copy", "axpy"):
-            bs.bs_ctx_set_tune(ctx, op, 4, 1 << 30)
-        for op in ("norm", "dot", "cg_update"):
-            bs.bs_ctx_set_tune(ctx, op, 4, 2048)
+        for op, (u, g) in defaults.items():
+            bs.bs_ctx_set_tune(ctx, op, u, g)
 
 
 def test_error_paths(ctx):
@@ -213,8 +212,9 @@ def test_error_paths(ctx):
     assert L.bs_dot(h, 0, 10, x.data_ptr(), y.data_ptr(), o.data_ptr() + 4, s) == INVALID
     assert L.bs_cg_update(h, 0, 10, 1.0, x.data_ptr(), y.data_ptr(), x.data_ptr(), y.data_ptr(), None,
                           o.data_ptr(), s) == INVALID  # r aliases x
-    assert L.bs_ctx_set_tune(h, 0, 0, 3, 16) == INVALID
-    assert L.bs_ctx_set_tune(h, 99, 0, 4, 16) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 3, 16, 0) == INVALID
+    assert L.bs_ctx_set_tune(h, 99, 0, 4, 16, 0) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 4) == INVALID
     # n == 0 with NULL pointers is a valid no-op; reductions write 0
     assert L.bs_copy(h, 0, 0, None, None, s) == 0
     assert L.bs_dot(h, 0, 0, None, None, o.data_ptr(), s) == 0
