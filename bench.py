@@ -120,7 +120,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--profile", default="",
-                    help="comma-separated ops: run each --reps times after set-up and exit (for rocprofv3)")
+                    help="comma-separated ops (op or op@variant): run each --reps times after set-up and exit "
+                         "(for rocprofv3)")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -201,8 +202,12 @@ def main():
         calls = dict(zip(OPS, step_calls()))
         calls["copy_probe"] = lambda: bs.bs_copy(ctx, x, copy_probe, hs)
         for name in names:
+            op, _, variant = name.partition("@")
+            if variant:
+                u, g, _ = bs.bs_ctx_get_tune(ctx, op)
+                bs.bs_ctx_set_tune(ctx, op, u, g, int(variant))
             for _ in range(args.reps):
-                calls[name]()
+                calls[op]()
             torch.cuda.synchronize()
             print(f"# profiled {name} x{args.reps}", file=sys.stderr, flush=True)
         return 0

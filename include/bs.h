@@ -91,16 +91,19 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
  * the number of 256-thread workgroups (kernels grid-stride beyond it;
  * reductions are further capped at 65536); variant (gather and scatter
- * only; other ops ignore it) selects the kernel with bit 0 -- scatter:
- * 0 = tiles in ascending-global-id order, 1 = map order; gather: 0 =
- * nonzero-balanced blocks, 1 = fixed row blocks -- and with bit 1 set keeps
- * the hardware's workgroup order instead of giving each XCD a contiguous
- * range of blocks.  The setting applies to every dtype.  Results of the bit-exact
+ * only; other ops ignore it) is a kernel choice plus 4 to keep the
+ * hardware's workgroup order instead of giving each XCD a contiguous range
+ * of blocks.  Gather: 0 = rows grouped by the scatter tiles that hold their
+ * copies (falls back to 1 when a degree exceeds 255), 1 = rows in global
+ * order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
+ * entries visited in order of their smallest global id, values read in
+ * ascending global id and turned around in LDS, 1 = the same tiles read in
+ * local order, 2 = local order with `unroll` entries per thread.  The setting applies to every dtype.  Results of the bit-exact
  * operations do not depend on it; reduction results depend on it only
  * through the order of their compensated additions.  Defaults: unroll 1
  * and one-pass grids for element-wise operations and gather/scatter;
  * norm and dot unroll 8 with 4096 workgroups; cg_update unroll 4 with
- * 65536 workgroups; variant 0. */
+ * 65536 workgroups; gather and scatter variant 1. */
 bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap, int variant);
 bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap,
                           int* variant);

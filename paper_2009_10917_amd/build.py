@@ -31,7 +31,8 @@ COMMON = [
 
 LIBS = {
     os.path.join(PKG, "libbs.so"): [
-        os.path.join(PKG, "csrc", f) for f in ("bs_host.hip", "bs_stream.hip", "bs_gs.hip")
+        os.path.join(PKG, "csrc", f)
+        for f in ("bs_host.hip", "bs_stream.hip", "bs_mesh.hip", "bs_plan.hip", "bs_gs.hip")
     ],
     os.path.join(ROOT, "bsgen", "libbsgen.so"): [os.path.join(ROOT, "bsgen", "csrc", "bsgen.hip")],
 }

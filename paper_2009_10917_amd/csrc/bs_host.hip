@@ -106,6 +106,9 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
     c->tune[OP_NORM][d] = Tune{8, 4096, 0};
     c->tune[OP_DOT][d] = Tune{8, 4096, 0};
     c->tune[OP_CG_UPDATE][d] = Tune{4, kMaxReduceBlocks, 0};
+    // gather: rows in global order; scatter: tiles read in local order
+    c->tune[OP_GATHER][d] = Tune{1, 1 << 30, 1};
+    c->tune[OP_SCATTER][d] = Tune{1, 1 << 30, 1};
   }
   (void)hipSetDevice(prev);
   *out = c;
@@ -130,7 +133,8 @@ extern "C" bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int un
   if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
     return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unroll must be 1, 2, 4 or 8");
   if (grid_cap < 1) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: grid_cap must be positive");
-  if (variant < 0 || variant > 3) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: variant must lie in [0, 3]");
+  if (variant < 0 || variant > 7 || (variant & kVariantMask) == 3)
+    return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: variant must be 0, 1 or 2, optionally plus 4");
   // every dtype currently shares one entry per op
   for (int d = 0; d < 3; ++d) ctx->tune[op][d] = Tune{unroll, grid_cap, variant};
   return BS_OK;

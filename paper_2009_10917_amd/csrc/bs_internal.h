@@ -70,20 +70,53 @@ struct bs_gs {
   int64_t n_unmasked;
   int64_t max_degree;
   int32_t* map;         // [n_local] copy of the scatter ids
-  int32_t* row_starts;  // [n_global + 1]
+  int32_t* row_starts;  // [n_global + 1] CSR of Z^T (rows in global order)
   int32_t* col_ids;     // [n_unmasked]
-  // gather work split: block b adds rows [block_starts[b], block_starts[b+1]),
-  // whose nonzeros lie in the CSR window [b*chunk, b*chunk + kStage)
+
+  // Gather, rows in global order, nonzero-balanced: block b adds rows
+  // [block_starts[b], block_starts[b+1]), whose nonzeros lie in the CSR
+  // window [b*chunk, b*chunk + kStage).
   int32_t* block_starts;  // [n_blocks + 1]
   int64_t n_blocks;
   int64_t chunk;
-  // scatter work order: tiles of kTile consecutive local entries, sorted by
-  // the smallest global id they reference
-  int32_t* tile_order;  // [n_tiles]
+
+  // Scatter: tiles of kTile consecutive local entries, visited in the order
+  // of the smallest global id each references (tile_order); within tile t,
+  // entry k of tile_gid/tile_loc is the k-th smallest (global id, local
+  // offset) pair, masked entries excluded (tile_count[t] valid pairs).
+  int32_t* tile_order;   // [n_tiles]
+  int32_t* tile_gid;     // [n_tiles * kTile]
+  uint16_t* tile_loc;    // [n_tiles * kTile]
+  int32_t* tile_count;   // [n_tiles]
   int64_t n_tiles;
+
+  // Gather, rows in visiting order: rows grouped by the first tile (in
+  // tile_order) that holds one of their copies; perm_rows lists rows with
+  // copies first (perm_deg copies each, columns in perm_cols, ascending local
+  // index per row), then rows without copies.  Nonzero-balanced blocks as
+  // above (perm_bstart, with perm_bnz0[b] the CSR offset of the block's first
+  // row).  Built only when every degree fits in a byte (has_perm).
+  bool has_perm;
+  int32_t* perm_rows;    // [n_global]
+  uint8_t* perm_deg;     // [n_nzrows]
+  int32_t* perm_cols;    // [n_unmasked]
+  int32_t* perm_bstart;  // [n_pblocks + 1]
+  int32_t* perm_bnz0;    // [n_pblocks]
+  int64_t n_nzrows;
+  int64_t n_pblocks;
 };
 
 namespace bs {
 constexpr int kStage = 2048;  // values staged in LDS per gather workgroup
 constexpr int kTile = 512;    // local entries per scatter workgroup
+static_assert(kTile == 2 * kBlock, "scatter tiles hold two entries per thread");
+static_assert(kStage == 8 * kBlock, "gather stages eight values per thread");
+
+// Kernel choice for gather and scatter (Tune::variant & kVariantMask), and
+// the flag that keeps the hardware's workgroup order instead of giving each
+// XCD a contiguous range of blocks.
+constexpr int kVariantMask = 3;
+constexpr int kNoXcdRemap = 4;
+
+void free_plan(bs_gs* gs);
 }  // namespace bs

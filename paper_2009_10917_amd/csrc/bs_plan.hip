@@ -1,0 +1,586 @@
+// Gather/scatter plan: everything BS6 and BS7 need, built once per map on
+// the device (Section 5: the mesh set-up that stores Z as an id array and
+// Z^T in CSR form without values, plus the blockStarts offsets).
+//
+//   CSR of Z^T        degree histogram, exclusive scan (row starts), stable
+//                     radix sort of (map[l], l) pairs (column ids)
+//   gather blocks     rows in global order, split so that every workgroup
+//                     takes about the same number of nonzeros
+//   scatter tiles     tiles of kTile local entries, visited in order of the
+//                     smallest global id each references; inside a tile the
+//                     entries sorted by global id (bitonic sort in LDS)
+//   gather order      rows grouped by the first visited tile holding one of
+//                     their copies, as a permuted CSR with byte degrees
+//
+// The last two are orderings of work only: no vector is renumbered, and the
+// results of gather and scatter are the same bits whichever order is used.
+
+#include <hipcub/hipcub.hpp>
+
+#include "bs_device.h"
+#include "bs_internal.h"
+
+namespace bs {
+namespace {
+
+inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
+
+// Device memory owned until released.
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  bool alloc(size_t bytes) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return hipMalloc(&p, bytes ? bytes : 1) == hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* release() {
+    T* q = static_cast<T*>(p);
+    p = nullptr;
+    return q;
+  }
+};
+
+// ---------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = static_cast<int32_t>(i);
+}
+
+// Copy the map, count ids >= n_global, build sort keys (masked entries get
+// key n_global, after every row) and the degree histogram.
+__global__ __launch_bounds__(kBlock) void k_plan_prepare(const int32_t* __restrict__ map, int64_t n_local,
+                                                         int32_t n_global, int32_t* __restrict__ map_copy,
+                                                         uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                         int32_t* __restrict__ deg, int* __restrict__ bad) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (l >= n_local) return;
+  const int32_t m = map[l];
+  map_copy[l] = m;
+  vals[l] = static_cast<int32_t>(l);
+  if (m >= n_global) {
+    atomicOr(bad, 1);
+    keys[l] = static_cast<uint32_t>(n_global);
+  } else if (m < 0) {
+    keys[l] = static_cast<uint32_t>(n_global);
+  } else {
+    keys[l] = static_cast<uint32_t>(m);
+    atomicAdd(&deg[m], 1);
+  }
+}
+
+// Largest degree and number of rows without copies.
+__global__ __launch_bounds__(kBlock) void k_degree_stats(const int32_t* __restrict__ deg, int64_t n,
+                                                         int* __restrict__ max_deg, unsigned long long* __restrict__ zeros) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  int d = (i < n) ? deg[i] : 0;
+  int z = (i < n && deg[i] == 0) ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) {
+    d = max(d, __shfl_xor(d, off, 64));
+    z += __shfl_xor(z, off, 64);
+  }
+  if (threadIdx.x % 64 == 0) {
+    atomicMax(max_deg, d);
+    if (z) atomicAdd(zeros, static_cast<unsigned long long>(z));
+  }
+}
+
+// bstart[b] = first index k in [0, n_rows] with starts[k] >= b*chunk
+// (b < n_blocks); bstart[n_blocks] = n_rows; optionally bnz0[b] = starts[bstart[b]].
+__global__ __launch_bounds__(kBlock) void k_block_starts(const int32_t* __restrict__ starts, int64_t n_rows,
+                                                         int64_t chunk, int64_t n_blocks, int32_t* __restrict__ bstart,
+                                                         int32_t* __restrict__ bnz0) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (b > n_blocks) return;
+  if (b == n_blocks) {
+    bstart[b] = static_cast<int32_t>(n_rows);
+    return;
+  }
+  const int64_t target = b * chunk;
+  int64_t lo = 0, hi = n_rows;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (starts[mid] >= target) hi = mid; else lo = mid + 1;
+  }
+  bstart[b] = static_cast<int32_t>(lo);
+  if (bnz0) bnz0[b] = starts[lo];
+}
+
+// Per tile: smallest unmasked id (key for the visiting order) and the tile's
+// entries sorted by (id, local offset), masked and padding entries last.
+__global__ __launch_bounds__(kBlock) void k_tile_sort(const int32_t* __restrict__ map, int64_t n_local,
+                                                      uint32_t* __restrict__ tkey, int32_t* __restrict__ tidx,
+                                                      int32_t* __restrict__ tgid, uint16_t* __restrict__ tloc,
+                                                      int32_t* __restrict__ tcnt) {
+  __shared__ uint64_t key[kTile];
+  __shared__ int s_cnt;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile;
+  for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    const int64_t l = base + k;
+    const int32_t g = (l < n_local) ? map[l] : -1;
+    const uint64_t hi = (g >= 0) ? static_cast<uint64_t>(static_cast<uint32_t>(g)) : 0xFFFFFFFFull;
+    key[k] = (hi << 16) | static_cast<uint64_t>(k);
+  }
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  // bitonic sorting network over kTile keys (all distinct: the low bits hold k)
+  for (int size = 2; size <= kTile; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < kTile; i += kBlock) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const uint64_t a = key[i], b = key[j];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int mine = 0;
+  for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    const uint64_t v = key[k];
+    const uint32_t g = static_cast<uint32_t>(v >> 16);
+    const bool valid = g != 0xFFFFFFFFu;
+    tgid[base + k] = valid ? static_cast<int32_t>(g) : -1;
+    tloc[base + k] = static_cast<uint16_t>(v & 0xFFFFu);
+    mine += valid;
+  }
+  atomicAdd(&s_cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tcnt[blockIdx.x] = s_cnt;
+    tkey[blockIdx.x] = static_cast<uint32_t>(key[0] >> 16);  // 0xFFFFFFFF when the tile has no valid entry
+    tidx[blockIdx.x] = static_cast<int32_t>(blockIdx.x);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert(const int32_t* __restrict__ order, int64_t n,
+                                                   int32_t* __restrict__ rank) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) rank[order[i]] = static_cast<int32_t>(i);
+}
+
+// key[g] = smallest visiting rank of a tile holding a copy of row g.
+__global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t* __restrict__ map, int64_t n_local,
+                                                     const int32_t* __restrict__ tile_rank, uint32_t* __restrict__ key) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (l >= n_local) return;
+  const int32_t g = map[l];
+  if (g >= 0) atomicMin(&key[g], static_cast<uint32_t>(tile_rank[l / kTile]));
+}
+
+// Degrees of the rows in visiting order (byte and int copies).
+__global__ __launch_bounds__(kBlock) void k_perm_degrees(const int32_t* __restrict__ rows, int64_t n_nzrows,
+                                                         const int32_t* __restrict__ rs, uint8_t* __restrict__ d8,
+                                                         int32_t* __restrict__ d32) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (k > n_nzrows) return;
+  if (k == n_nzrows) {
+    d32[k] = 0;  // so that the exclusive scan's last entry is the total
+    return;
+  }
+  const int32_t g = rows[k];
+  const int32_t d = rs[g + 1] - rs[g];
+  d8[k] = static_cast<uint8_t>(d);
+  d32[k] = d;
+}
+
+// Columns of the rows in visiting order.
+__global__ __launch_bounds__(kBlock) void k_perm_cols(const int32_t* __restrict__ rows, int64_t n_nzrows,
+                                                      const int32_t* __restrict__ rs, const int32_t* __restrict__ ci,
+                                                      const int32_t* __restrict__ prs, int32_t* __restrict__ pcols) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= n_nzrows) return;
+  const int32_t g = rows[k];
+  const int32_t a = rs[g], e = rs[g + 1], o = prs[k];
+  for (int32_t j = a; j < e; ++j) pcols[o + (j - a)] = ci[j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_degree(const int32_t* __restrict__ rs, int32_t n_global,
+                                                   int32_t* __restrict__ deg) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (g < n_global) deg[g] = rs[g + 1] - rs[g];
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_weights(const int32_t* __restrict__ map, const int32_t* __restrict__ rs,
+                                                    int64_t n_local, typename dev::Storage<T>::E* __restrict__ w) {
+  using S = dev::Storage<T>;
+  using C = typename S::C;
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (l >= n_local) return;
+  const int32_t m = map[l];
+  if (m < 0) {
+    w[l] = S::store(C(0));
+  } else {
+    const double d = static_cast<double>(rs[m + 1] - rs[m]);
+    w[l] = S::store(static_cast<C>(1.0 / d));
+  }
+}
+
+// ---------------------------------------------------------------- host helpers
+
+struct Builder {
+  const char* op;
+  hipStream_t st;
+  bs_status s = BS_OK;
+
+  bool ok() const { return s == BS_OK; }
+  void hip(hipError_t e) {
+    if (s == BS_OK && e != hipSuccess) s = check_hip(e, op);
+  }
+  void launched() {
+    if (s == BS_OK) s = check_launch(op);
+  }
+  void need(DevBuf& b, size_t bytes, const char* what) {
+    if (s == BS_OK && !b.alloc(bytes)) s = fail(BS_ERR_ALLOC, "%s: cannot allocate %zu bytes (%s)", op, bytes, what);
+  }
+  template <class T>
+  T read(const T* d) {
+    T h{};
+    hip(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, st));
+    hip(hipStreamSynchronize(st));
+    return h;
+  }
+  // hipcub call with its own scratch allocation
+  template <class F>
+  void cub(F f) {
+    if (!ok()) return;
+    size_t bytes = 0;
+    hip(f(nullptr, bytes));
+    DevBuf tmp;
+    need(tmp, bytes, "scratch");
+    if (ok()) hip(f(tmp.p, bytes));
+    hip(hipStreamSynchronize(st));  // the scratch is freed on return
+  }
+};
+
+int sort_bits(uint64_t max_key) {
+  int bits = 1;
+  while (bits < 32 && (static_cast<uint64_t>(1) << bits) <= max_key) ++bits;
+  return bits;
+}
+
+// CSR of Z^T, degrees; validates the map.
+void build_csr(Builder& B, bs_gs* gs, const int32_t* d_map) {
+  const int64_t nl = gs->n_local, ng = gs->n_global;
+  DevBuf map, rs, keys, keys_out, vals, vals_out, deg, flags;
+  B.need(map, nl * 4, "map");
+  B.need(rs, (ng + 1) * 4, "row starts");
+  B.need(keys, nl * 4, "keys");
+  B.need(keys_out, nl * 4, "keys");
+  B.need(vals, nl * 4, "values");
+  B.need(vals_out, nl * 4, "values");
+  B.need(deg, (ng + 1) * 4, "degrees");
+  B.need(flags, 64, "flags");
+  if (!B.ok()) return;
+  B.hip(hipMemsetAsync(flags.p, 0, 64, B.st));
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng + 1)), dim3(kBlock), 0, B.st, deg.as<int32_t>(), ng + 1, 0);
+  if (nl > 0)
+    hipLaunchKernelGGL(k_plan_prepare, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, d_map, nl,
+                       static_cast<int32_t>(ng), map.as<int32_t>(), keys.as<uint32_t>(), vals.as<int32_t>(),
+                       deg.as<int32_t>(), flags.as<int>());
+  B.launched();
+  if (B.ok() && B.read(flags.as<int>())) {
+    B.s = fail(BS_ERR_INVALID_ARG, "%s: map entry >= n_global (%lld)", B.op, static_cast<long long>(ng));
+    return;
+  }
+  int32_t* dg = deg.as<int32_t>();
+  int32_t* rsp = rs.as<int32_t>();
+  B.cub([&](void* t, size_t& b) {
+    return hipcub::DeviceScan::ExclusiveSum(t, b, dg, rsp, static_cast<int>(ng + 1), B.st);
+  });
+  if (nl > 0) {
+    const int bits = sort_bits(static_cast<uint64_t>(ng));
+    uint32_t* k0 = keys.as<uint32_t>();
+    uint32_t* k1 = keys_out.as<uint32_t>();
+    int32_t* v0 = vals.as<int32_t>();
+    int32_t* v1 = vals_out.as<int32_t>();
+    B.cub([&](void* t, size_t& b) {
+      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(nl), 0, bits, B.st);
+    });
+  }
+  if (!B.ok()) return;
+  gs->n_unmasked = B.read(rsp + ng);
+  // degree statistics
+  B.hip(hipMemsetAsync(flags.p, 0, 64, B.st));
+  if (ng > 0)
+    hipLaunchKernelGGL(k_degree_stats, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, dg, ng, flags.as<int>(),
+                       reinterpret_cast<unsigned long long*>(flags.as<char>() + 8));
+  B.launched();
+  if (!B.ok()) return;
+  gs->max_degree = B.read(flags.as<int>());
+  DevBuf ci;
+  B.need(ci, gs->n_unmasked * 4, "column ids");
+  if (gs->n_unmasked > 0)
+    B.hip(hipMemcpyAsync(ci.p, vals_out.p, gs->n_unmasked * 4, hipMemcpyDeviceToDevice, B.st));
+  B.hip(hipStreamSynchronize(B.st));
+  if (!B.ok()) return;
+  gs->map = map.release<int32_t>();
+  gs->row_starts = rs.release<int32_t>();
+  gs->col_ids = ci.release<int32_t>();
+}
+
+// Rows in global order, nonzero-balanced blocks.
+void build_gather_blocks(Builder& B, bs_gs* gs) {
+  gs->chunk = (gs->max_degree <= kStage / 2) ? kStage - gs->max_degree : kStage / 2;
+  gs->n_blocks = (gs->n_unmasked + gs->chunk - 1) / gs->chunk;
+  if (gs->n_blocks < 1) gs->n_blocks = 1;
+  DevBuf bstart;
+  B.need(bstart, (gs->n_blocks + 1) * 4, "block starts");
+  if (!B.ok()) return;
+  hipLaunchKernelGGL(k_block_starts, dim3(blocks_for(gs->n_blocks + 1)), dim3(kBlock), 0, B.st, gs->row_starts,
+                     gs->n_global, gs->chunk, gs->n_blocks, bstart.as<int32_t>(), static_cast<int32_t*>(nullptr));
+  B.launched();
+  B.hip(hipStreamSynchronize(B.st));
+  if (B.ok()) gs->block_starts = bstart.release<int32_t>();
+}
+
+// Sorted tiles and their visiting order.
+void build_scatter_tiles(Builder& B, bs_gs* gs) {
+  const int64_t nt = (gs->n_local + kTile - 1) / kTile;
+  gs->n_tiles = nt;
+  DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx;
+  B.need(tgid, nt * kTile * 4, "tile ids");
+  B.need(tloc, nt * kTile * 2, "tile offsets");
+  B.need(tcnt, nt * 4, "tile counts");
+  B.need(order, nt * 4, "tile order");
+  B.need(tkey, nt * 4, "tile keys");
+  B.need(tkey_out, nt * 4, "tile keys");
+  B.need(tidx, nt * 4, "tile indices");
+  if (!B.ok()) return;
+  if (nt > 0) {
+    hipLaunchKernelGGL(k_tile_sort, dim3(static_cast<unsigned int>(nt)), dim3(kBlock), 0, B.st, gs->map, gs->n_local,
+                       tkey.as<uint32_t>(), tidx.as<int32_t>(), tgid.as<int32_t>(), tloc.as<uint16_t>(),
+                       tcnt.as<int32_t>());
+    B.launched();
+    uint32_t* k0 = tkey.as<uint32_t>();
+    uint32_t* k1 = tkey_out.as<uint32_t>();
+    int32_t* v0 = tidx.as<int32_t>();
+    int32_t* v1 = order.as<int32_t>();
+    B.cub([&](void* t, size_t& b) {
+      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(nt), 0, 32, B.st);
+    });
+  }
+  B.hip(hipStreamSynchronize(B.st));
+  if (!B.ok()) return;
+  gs->tile_gid = tgid.release<int32_t>();
+  gs->tile_loc = tloc.release<uint16_t>();
+  gs->tile_count = tcnt.release<int32_t>();
+  gs->tile_order = order.release<int32_t>();
+}
+
+// Rows in visiting order (needs the tile order and the CSR).
+void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows) {
+  gs->has_perm = false;
+  if (gs->max_degree > 255) return;  // degrees are stored in bytes
+  const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
+  const int64_t nz = ng - n_zero_rows;  // rows with copies
+  DevBuf rank, rkey, rkey_out, rows0, rows, d8, d32, prs, pcols, bstart, bnz0;
+  B.need(rank, nt * 4, "tile ranks");
+  B.need(rkey, ng * 4, "row keys");
+  B.need(rkey_out, ng * 4, "row keys");
+  B.need(rows0, ng * 4, "rows");
+  B.need(rows, ng * 4, "row order");
+  B.need(d8, nz, "degrees");
+  B.need(d32, (nz + 1) * 4, "degrees");
+  B.need(prs, (nz + 1) * 4, "row starts");
+  B.need(pcols, gs->n_unmasked * 4, "columns");
+  if (!B.ok()) return;
+  if (nt > 0)
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
+  if (nl > 0)
+    hipLaunchKernelGGL(k_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, rank.as<int32_t>(),
+                       rkey.as<uint32_t>());
+  B.launched();
+  if (ng > 0) {
+    uint32_t* k0 = rkey.as<uint32_t>();
+    uint32_t* k1 = rkey_out.as<uint32_t>();
+    int32_t* v0 = rows0.as<int32_t>();
+    int32_t* v1 = rows.as<int32_t>();
+    B.cub([&](void* t, size_t& b) {
+      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(ng), 0, 32, B.st);
+    });
+  }
+  hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(nz + 1)), dim3(kBlock), 0, B.st, rows.as<int32_t>(), nz,
+                     gs->row_starts, d8.as<uint8_t>(), d32.as<int32_t>());
+  B.launched();
+  int32_t* dp = d32.as<int32_t>();
+  int32_t* pp = prs.as<int32_t>();
+  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, dp, pp, static_cast<int>(nz + 1), B.st); });
+  if (nz > 0)
+    hipLaunchKernelGGL(k_perm_cols, dim3(blocks_for(nz)), dim3(kBlock), 0, B.st, rows.as<int32_t>(), nz,
+                       gs->row_starts, gs->col_ids, prs.as<int32_t>(), pcols.as<int32_t>());
+  B.launched();
+  const int64_t nb = (gs->n_unmasked + gs->chunk - 1) / gs->chunk;
+  B.need(bstart, (nb + 1) * 4, "block starts");
+  B.need(bnz0, (nb > 0 ? nb : 1) * 4, "block offsets");
+  if (!B.ok()) return;
+  hipLaunchKernelGGL(k_block_starts, dim3(blocks_for(nb + 1)), dim3(kBlock), 0, B.st, prs.as<int32_t>(), nz, gs->chunk,
+                     nb, bstart.as<int32_t>(), bnz0.as<int32_t>());
+  B.launched();
+  B.hip(hipStreamSynchronize(B.st));
+  if (!B.ok()) return;
+  gs->perm_rows = rows.release<int32_t>();
+  gs->perm_deg = d8.release<uint8_t>();
+  gs->perm_cols = pcols.release<int32_t>();
+  gs->perm_bstart = bstart.release<int32_t>();
+  gs->perm_bnz0 = bnz0.release<int32_t>();
+  gs->n_nzrows = nz;
+  gs->n_pblocks = nb;
+  gs->has_perm = true;
+}
+
+}  // namespace
+
+void free_plan(bs_gs* gs) {
+  if (!gs) return;
+  for (void* p : {static_cast<void*>(gs->map), static_cast<void*>(gs->row_starts), static_cast<void*>(gs->col_ids),
+                  static_cast<void*>(gs->block_starts), static_cast<void*>(gs->tile_order),
+                  static_cast<void*>(gs->tile_gid), static_cast<void*>(gs->tile_loc),
+                  static_cast<void*>(gs->tile_count), static_cast<void*>(gs->perm_rows),
+                  static_cast<void*>(gs->perm_deg), static_cast<void*>(gs->perm_cols),
+                  static_cast<void*>(gs->perm_bstart), static_cast<void*>(gs->perm_bnz0)})
+    if (p) (void)hipFree(p);
+  delete gs;
+}
+
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_local, int64_t n_global, void* stream,
+                                  bs_gs** out) {
+  const char* op = "bs_gs_create";
+  bs_status s;
+  if (!out) return fail(BS_ERR_INVALID_ARG, "%s: out is NULL", op);
+  *out = nullptr;
+  if ((s = check_ctx(ctx, op))) return s;
+  if (n_local < 0 || n_global < 0 || n_local >= 2147483647LL || n_global >= 2147483647LL)
+    return fail(BS_ERR_INVALID_ARG, "%s: sizes must lie in [0, 2^31 - 1)", op);
+  if (n_local > 0 && !d_map) return fail(BS_ERR_INVALID_ARG, "%s: d_map is NULL", op);
+  if (d_map && !aligned_to(d_map, 4)) return fail(BS_ERR_INVALID_ARG, "%s: d_map is not 4-byte aligned", op);
+  bs_gs* gs = new bs_gs();
+  gs->device = ctx->device;
+  gs->n_local = n_local;
+  gs->n_global = n_global;
+  Builder B{op, static_cast<hipStream_t>(stream)};
+  build_csr(B, gs, d_map);
+  // rows without copies, for the gather order
+  int64_t zero_rows = 0;
+  if (B.ok()) {
+    DevBuf deg, cnt;
+    B.need(deg, n_global * 4, "degrees");
+    B.need(cnt, 64, "counter");
+    if (B.ok()) {
+      B.hip(hipMemsetAsync(cnt.p, 0, 64, B.st));
+      if (n_global > 0) {
+        hipLaunchKernelGGL(k_degree, dim3(blocks_for(n_global)), dim3(kBlock), 0, B.st, gs->row_starts,
+                           static_cast<int32_t>(n_global), deg.as<int32_t>());
+        hipLaunchKernelGGL(k_degree_stats, dim3(blocks_for(n_global)), dim3(kBlock), 0, B.st, deg.as<int32_t>(),
+                           n_global, cnt.as<int>(), reinterpret_cast<unsigned long long*>(cnt.as<char>() + 8));
+      }
+      B.launched();
+      if (B.ok()) zero_rows = static_cast<int64_t>(B.read(reinterpret_cast<unsigned long long*>(cnt.as<char>() + 8)));
+    }
+  }
+  if (B.ok()) build_gather_blocks(B, gs);
+  if (B.ok()) build_scatter_tiles(B, gs);
+  if (B.ok()) build_gather_order(B, gs, zero_rows);
+  if (!B.ok()) {
+    free_plan(gs);
+    return B.s;
+  }
+  *out = gs;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_gs_destroy(bs_gs* gs) {
+  if (!gs) return BS_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(gs->device);
+  free_plan(gs);
+  (void)hipSetDevice(prev);
+  return BS_OK;
+}
+
+extern "C" bs_status bs_gs_info(const bs_gs* gs, int64_t* n_local, int64_t* n_global, int64_t* n_unmasked,
+                                int64_t* max_degree) {
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "bs_gs_info: plan is NULL");
+  if (n_local) *n_local = gs->n_local;
+  if (n_global) *n_global = gs->n_global;
+  if (n_unmasked) *n_unmasked = gs->n_unmasked;
+  if (max_degree) *max_degree = gs->max_degree;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_gs_csr(const bs_gs* gs, int32_t* d_row_starts, int32_t* d_col_ids, void* stream) {
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "bs_gs_csr: plan is NULL");
+  if (!d_row_starts || (gs->n_unmasked > 0 && !d_col_ids)) return fail(BS_ERR_INVALID_ARG, "bs_gs_csr: output is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bs_status s = check_hip(hipMemcpyAsync(d_row_starts, gs->row_starts, static_cast<size_t>(gs->n_global + 1) * 4,
+                                         hipMemcpyDeviceToDevice, st),
+                          "bs_gs_csr");
+  if (!s && gs->n_unmasked > 0)
+    s = check_hip(hipMemcpyAsync(d_col_ids, gs->col_ids, static_cast<size_t>(gs->n_unmasked) * 4,
+                                 hipMemcpyDeviceToDevice, st),
+                  "bs_gs_csr");
+  return s;
+}
+
+extern "C" bs_status bs_gs_degree(const bs_gs* gs, int32_t* d_deg, void* stream) {
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "bs_gs_degree: plan is NULL");
+  if (gs->n_global == 0) return BS_OK;
+  if (!d_deg || !aligned_to(d_deg, 4)) return fail(BS_ERR_INVALID_ARG, "bs_gs_degree: d_deg is NULL or misaligned");
+  hipLaunchKernelGGL(k_degree, dim3(blocks_for(gs->n_global)), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
+                     gs->row_starts, static_cast<int32_t>(gs->n_global), d_deg);
+  return check_launch("bs_gs_degree");
+}
+
+extern "C" bs_status bs_gs_weights(const bs_gs* gs, bs_dtype dtype, void* d_wL, void* stream) {
+  bs_status s;
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "bs_gs_weights: plan is NULL");
+  if ((s = check_dtype("bs_gs_weights", dtype)) || (s = check_vec("bs_gs_weights", "d_wL", d_wL, gs->n_local, dtype)))
+    return s;
+  if (gs->n_local == 0) return BS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 g(blocks_for(gs->n_local));
+  switch (dtype) {
+    case BS_F64:
+      hipLaunchKernelGGL(k_weights<double>, g, dim3(kBlock), 0, st, gs->map, gs->row_starts, gs->n_local,
+                         static_cast<double*>(d_wL));
+      break;
+    case BS_F32:
+      hipLaunchKernelGGL(k_weights<float>, g, dim3(kBlock), 0, st, gs->map, gs->row_starts, gs->n_local,
+                         static_cast<float*>(d_wL));
+      break;
+    case BS_BF16:
+      hipLaunchKernelGGL(k_weights<dev::bf16>, g, dim3(kBlock), 0, st, gs->map, gs->row_starts, gs->n_local,
+                         static_cast<uint16_t*>(d_wL));
+      break;
+  }
+  return check_launch("bs_gs_weights");
+}

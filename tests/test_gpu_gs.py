@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 import paper_2009_10917_amd as bs  # noqa: E402
 from gpu_util import bits, dev_uniform, host_uniform, to_host  # noqa: E402
 
+VARIANTS = [0, 1, 2, 4, 5, 6]  # kernel choice, plus 4 = hardware workgroup order
 MESHES = [(1, 1, None), (2, 1, 1), (3, 2, 2), (8, 3, None), (4, 7, 3), (3, 15, 4), (6, 5, 5), (5, 4, None),
           (12, 2, 6)]
 
@@ -28,8 +29,10 @@ def with_variant(ctx, variant, unroll=4):
 
 @pytest.fixture(autouse=True)
 def default_variants(ctx):
+    saved = {op: bs.bs_ctx_get_tune(ctx, op) for op in ("gather", "scatter")}
     yield
-    with_variant(ctx, 0, unroll=1)
+    for op, (u, g, v) in saved.items():
+        bs.bs_ctx_set_tune(ctx, op, u, g, v)
 
 
 def device_map(K, N, seed):
@@ -77,7 +80,7 @@ def test_map_plan_gather_scatter(ctx, K, N, seed):
     # BS6 gather and BS7 scatter, both kernel variants
     g_ref = ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))
     s_ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
-    for variant in (1, 0, 2, 3):
+    for variant in VARIANTS:
         with_variant(ctx, variant)
         xL = dev_uniform(NL, 11)
         xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
@@ -94,7 +97,7 @@ def test_map_plan_gather_scatter(ctx, K, N, seed):
     plan.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_masked_entries(ctx, variant):
     with_variant(ctx, variant)
     K, N = 5, 3
@@ -118,7 +121,7 @@ def test_masked_entries(ctx, variant):
     assert np.array_equal(bits(to_host(w)), bits(mesh.weights(ref_map, NG)))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_high_degree_rows_use_the_unstaged_path(ctx, variant):
     with_variant(ctx, variant)
     # 7 global nodes with ~14000 copies each: a workgroup's rows hold far
@@ -136,7 +139,7 @@ def test_high_degree_rows_use_the_unstaged_path(ctx, variant):
     assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_rows_without_copies_and_empty_plans(ctx, variant):
     with_variant(ctx, variant)
     # global ids 0..9, only even ones used: odd rows gather to +0.0
@@ -178,7 +181,7 @@ def test_scatter_map_order_unrolls(ctx, unroll):
     E, NL, NG = mesh.sizes(K, N)
     d_map, ref_map = device_map(K, N, 31)
     plan = bs.bs_gs_create(ctx, d_map, NG)
-    with_variant(ctx, 1, unroll=unroll)
+    with_variant(ctx, 2, unroll=unroll)
     xL = dev_uniform(NL, 11)
     bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
@@ -198,7 +201,7 @@ def test_many_empty_rows_and_long_rows(ctx):
     rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
     xLh = bsgen.uniform(1, 11, ref_map.size)
     ref = ops.gather(rs_ref, ci_ref, xLh)
-    for variant in (0, 1):
+    for variant in VARIANTS:
         with_variant(ctx, variant)
         xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
         bs.bs_gather(ctx, plan, torch.from_numpy(xLh).cuda(), xG)

@@ -214,7 +214,8 @@ def test_error_paths(ctx):
                           o.data_ptr(), s) == INVALID  # r aliases x
     assert L.bs_ctx_set_tune(h, 0, 0, 3, 16, 0) == INVALID
     assert L.bs_ctx_set_tune(h, 99, 0, 4, 16, 0) == INVALID
-    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 4) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 3) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 8) == INVALID
     # n == 0 with NULL pointers is a valid no-op; reductions write 0
     assert L.bs_copy(h, 0, 0, None, None, s) == 0
     assert L.bs_dot(h, 0, 0, None, None, o.data_ptr(), s) == 0
