@@ -109,6 +109,142 @@ def cpu_baseline(n_sample, K_mesh, N_mesh, seed):
     }
 
 
+def _time_calls(fn, reps, torch):
+    """The paper's protocol: `reps` back-to-back calls timed as one block
+    (HIP events on the launch stream, and the host clock around a sync)."""
+    fn()
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    h0 = time.perf_counter()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    host = (time.perf_counter() - h0) / reps
+    return a.elapsed_time(b) * 1e-3 / reps, host
+
+
+def sweep(args, K_max):
+    import numpy as np
+    import torch
+
+    import bsgen
+    import paper_2009_10917_amd as bs
+    from paper_2009_10917_amd import perfmodel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = bs.bs_ctx_create(0)
+    S = bsgen.STREAM
+    n_max = (7 * K_max + 1) ** 3
+    vec = {}
+    for k in ("x", "y", "p", "r", "Ap", "w"):
+        t = torch.empty(n_max, dtype=torch.float64, device=dev)
+        bsgen.device_uniform(t, args.seed, S[k], lo=0.0 if k == "w" else -1.0)
+        vec[k] = t
+    out = torch.zeros(4, dtype=torch.float64, device=dev)
+    reps = 20
+    results = []
+    Ks = list(range(2, K_max + 1, 2))
+    for op in ("copy", "axpy", "norm", "dot", "cg_update"):
+        pts = []
+        for K in Ks:
+            n = (7 * K + 1) ** 3
+            v = {k: t[:n] for k, t in vec.items()}
+            calls = {
+                "copy": lambda: bs.bs_copy(ctx, v["x"], v["y"]),
+                "axpy": lambda: bs.bs_axpy(ctx, 0.5, v["x"], 0.5, v["y"]),
+                "norm": lambda: bs.bs_norm(ctx, v["x"], v["w"], out[0:1]),
+                "dot": lambda: bs.bs_dot(ctx, v["x"], v["y"], out[1:2]),
+                "cg_update": lambda: bs.bs_cg_update(ctx, 1e-9, v["x"], v["p"], v["r"], v["Ap"], v["w"], out[2:3]),
+            }
+            t_dev, t_host = _time_calls(calls[op], reps, torch)
+            B = alg_bytes(n, 0, 0)[op]
+            pts.append({"K": K, "n": n, "bytes": B, "t_event_s": t_dev, "t_host_s": t_host,
+                        "GB_s": B / t_dev / 1e9, "GB_s_host": B / t_host / 1e9})
+        print(f"# swept {op}", file=sys.stderr, flush=True)
+        results.append(_fit_record(op, pts, perfmodel))
+    del vec
+    torch.cuda.empty_cache()
+    # gather / scatter on N = 7 meshes, K = 2, 4, ..., K_gs
+    K_gs = min(64, K_max)
+    pts = [_mesh_points(K, 7, args.seed, ctx, bs, bsgen, torch, np, reps) for K in range(2, K_gs + 1, 2)]
+    print("# swept gather/scatter over K", file=sys.stderr, flush=True)
+    for op in ("scatter", "gather"):
+        results.append(_fit_record(op + " (N=7)", [p[op] for p in pts], perfmodel))
+    # gather / scatter at about 5e7 local nodes for N = 1..15
+    pts = [_mesh_points(round(368.4 / (N + 1)), N, args.seed, ctx, bs, bsgen, torch, np, reps) for N in range(1, 16)]
+    for op in ("scatter", "gather"):
+        rec = {"op": op + " (N-sweep, ~5e7 local nodes)", "points": [p[op] for p in pts]}
+        print(json.dumps(rec))
+        results.append(rec)
+    if args.sweep_out:
+        _write_sweep_md(args.sweep_out, results, K_max)
+    return 0
+
+
+def _mesh_points(K, N, seed, ctx, bs, bsgen, torch, np, reps):
+    E = K ** 3
+    NL, NG = E * (N + 1) ** 3, (K * N + 1) ** 3
+    perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
+    orient = torch.from_numpy(bsgen.orientations(seed, E).astype(np.uint8)).cuda()
+    d_map = torch.empty(NL, dtype=torch.int32, device="cuda")
+    bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    del d_map, perm, orient
+    xL = torch.empty(NL, dtype=torch.float64, device="cuda")
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bsgen.device_uniform(xL, seed, bsgen.STREAM["xL"])
+    bsgen.device_uniform(xG, seed, bsgen.STREAM["xG"])
+    out = {}
+    for op, fn in (("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL)),
+                   ("gather", lambda: bs.bs_gather(ctx, plan, xL, xG))):
+        t_dev, t_host = _time_calls(fn, reps, torch)
+        B = alg_bytes(0, NL, NG)[op]
+        out[op] = {"K": K, "N": N, "n_local": NL, "n_global": NG, "bytes": B, "t_event_s": t_dev,
+                   "t_host_s": t_host, "GB_s": B / t_dev / 1e9, "GB_s_host": B / t_host / 1e9}
+    plan.close()
+    return out
+
+
+def _fit_record(op, pts, perfmodel):
+    rec = {"op": op, "points": pts}
+    for tag, sel in (("all", pts), ("ge_1GB", [p for p in pts if p["bytes"] >= 1e9])):
+        if len(sel) >= 2:
+            t0, w = perfmodel.fit_time_model([p["bytes"] for p in sel], [p["t_event_s"] for p in sel])
+            rec["fit_" + tag] = {"T0_us": t0 * 1e6, "W_max_GB_s": w / 1e9,
+                                 "B08_MB": perfmodel.fischer_brown_bytes(t0, w) / 1e6, "points": len(sel)}
+    print(json.dumps(rec))
+    return rec
+
+
+def _write_sweep_md(path, results, K_max):
+    lines = ["# Length and mesh sweeps with the launch-latency + bandwidth fit", "",
+             "Command (from the repository root on the GPU host):", "",
+             f"    python3 bench.py --sweep --K {K_max} --sweep-out <this file>", "",
+             "20 back-to-back calls per size, timed with HIP events (host-clock figures in the JSON).",
+             "Fit: least squares T = T0 + B/W_max (paper Section 4) over all sizes and over sizes >= 1 GB",
+             "(smaller working sets stay in the 256 MB Infinity Cache between calls).", "",
+             "| operation | T0 (us) | W_max (GB/s) | B_0.8 (MB) | T0 >=1GB (us) | W_max >=1GB (GB/s) | best GB/s (size) |",
+             "|---|---|---|---|---|---|---|"]
+    for r in results:
+        best = max(r["points"], key=lambda p: p["GB_s"])
+        fa, fg = r.get("fit_all"), r.get("fit_ge_1GB")
+        cell = lambda f, k, fmt: (fmt % f[k]) if f else "-"
+        lines.append(f"| {r['op']} | {cell(fa, 'T0_us', '%.2f')} | {cell(fa, 'W_max_GB_s', '%.0f')} | "
+                     f"{cell(fa, 'B08_MB', '%.1f')} | {cell(fg, 'T0_us', '%.2f')} | {cell(fg, 'W_max_GB_s', '%.0f')} | "
+                     f"{best['GB_s']:.0f} ({best['bytes'] / 1e9:.3g} GB) |")
+    lines += ["", "Per-size bandwidth (GB/s, events):", ""]
+    for r in results:
+        lines.append(f"- {r['op']}: " + ", ".join(
+            f"{p['bytes'] / 1e6:.3g} MB: {p['GB_s']:.0f}" for p in r["points"]))
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +259,10 @@ def main():
                     help="comma-separated ops (op or op@variant): run each --reps times after set-up and exit "
                          "(for rocprofv3)")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--sweep", action="store_true",
+                    help="length sweep of BS1-BS5 (n = (7K+1)^3, K = 2, 4, ..., --K) and mesh sweeps of BS6/BS7; "
+                         "prints one JSON line per operation with the launch-latency + bandwidth fit")
+    ap.add_argument("--sweep-out", default="", help="also write a markdown summary of the sweep here")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
@@ -130,6 +270,8 @@ def main():
         return 2
     K = 32 if args.small else args.K
     N = 7
+    if args.sweep:
+        return sweep(args, K)
 
     import numpy as np
     import torch
