@@ -109,6 +109,31 @@ def cpu_baseline(n_sample, K_mesh, N_mesh, seed):
     }
 
 
+def _time_graph(fn, reps, torch):
+    """`reps` calls captured in one HIP graph; seconds per call of a replay.
+    Removes the host's per-call cost, leaving the device's launch latency."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    del g
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
 def _time_calls(fn, reps, torch):
     """The paper's protocol: `reps` back-to-back calls timed as one block
     (HIP events on the launch stream, and the host clock around a sync)."""
@@ -162,9 +187,10 @@ def sweep(args, K_max):
                 "cg_update": lambda: bs.bs_cg_update(ctx, 1e-9, v["x"], v["p"], v["r"], v["Ap"], v["w"], out[2:3]),
             }
             t_dev, t_host = _time_calls(calls[op], reps, torch)
+            t_graph = _time_graph(calls[op], reps, torch)
             B = alg_bytes(n, 0, 0)[op]
-            pts.append({"K": K, "n": n, "bytes": B, "t_event_s": t_dev, "t_host_s": t_host,
-                        "GB_s": B / t_dev / 1e9, "GB_s_host": B / t_host / 1e9})
+            pts.append({"K": K, "n": n, "bytes": B, "t_event_s": t_dev, "t_host_s": t_host, "t_graph_s": t_graph,
+                        "GB_s": B / t_dev / 1e9, "GB_s_host": B / t_host / 1e9, "GB_s_graph": B / t_graph / 1e9})
         print(f"# swept {op}", file=sys.stderr, flush=True)
         results.append(_fit_record(op, pts, perfmodel))
     del vec
@@ -203,18 +229,22 @@ def _mesh_points(K, N, seed, ctx, bs, bsgen, torch, np, reps):
     for op, fn in (("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL)),
                    ("gather", lambda: bs.bs_gather(ctx, plan, xL, xG))):
         t_dev, t_host = _time_calls(fn, reps, torch)
+        t_graph = _time_graph(fn, reps, torch)
         B = alg_bytes(0, NL, NG)[op]
         out[op] = {"K": K, "N": N, "n_local": NL, "n_global": NG, "bytes": B, "t_event_s": t_dev,
-                   "t_host_s": t_host, "GB_s": B / t_dev / 1e9, "GB_s_host": B / t_host / 1e9}
+                   "t_host_s": t_host, "t_graph_s": t_graph, "GB_s": B / t_dev / 1e9,
+                   "GB_s_host": B / t_host / 1e9, "GB_s_graph": B / t_graph / 1e9}
     plan.close()
     return out
 
 
 def _fit_record(op, pts, perfmodel):
     rec = {"op": op, "points": pts}
-    for tag, sel in (("all", pts), ("ge_1GB", [p for p in pts if p["bytes"] >= 1e9])):
+    fits = (("all", "t_event_s", pts), ("ge_1GB", "t_event_s", [p for p in pts if p["bytes"] >= 1e9]),
+            ("graph_all", "t_graph_s", pts), ("graph_le_256MB", "t_graph_s", [p for p in pts if p["bytes"] <= 256e6]))
+    for tag, key, sel in fits:
         if len(sel) >= 2:
-            t0, w = perfmodel.fit_time_model([p["bytes"] for p in sel], [p["t_event_s"] for p in sel])
+            t0, w = perfmodel.fit_time_model([p["bytes"] for p in sel], [p[key] for p in sel])
             rec["fit_" + tag] = {"T0_us": t0 * 1e6, "W_max_GB_s": w / 1e9,
                                  "B08_MB": perfmodel.fischer_brown_bytes(t0, w) / 1e6, "points": len(sel)}
     print(json.dumps(rec))
@@ -228,14 +258,18 @@ def _write_sweep_md(path, results, K_max):
              "20 back-to-back calls per size, timed with HIP events (host-clock figures in the JSON).",
              "Fit: least squares T = T0 + B/W_max (paper Section 4) over all sizes and over sizes >= 1 GB",
              "(smaller working sets stay in the 256 MB Infinity Cache between calls).", "",
-             "| operation | T0 (us) | W_max (GB/s) | B_0.8 (MB) | T0 >=1GB (us) | W_max >=1GB (GB/s) | best GB/s (size) |",
-             "|---|---|---|---|---|---|---|"]
+             "Graph columns: the 20 calls captured in one HIP graph and replayed, which removes the host's",
+             "per-call cost (Python binding and launch) and leaves the device's own launch latency.", "",
+             "| operation | T0 (us) | W_max (GB/s) | B_0.8 (MB) | W_max >=1GB (GB/s) | graph T0 (us) | graph W_max (GB/s) | graph T0, <=256MB (us) | best GB/s (size) |",
+             "|---|---|---|---|---|---|---|---|---|"]
     for r in results:
         best = max(r["points"], key=lambda p: p["GB_s"])
         fa, fg = r.get("fit_all"), r.get("fit_ge_1GB")
+        ga, gs = r.get("fit_graph_all"), r.get("fit_graph_le_256MB")
         cell = lambda f, k, fmt: (fmt % f[k]) if f else "-"
         lines.append(f"| {r['op']} | {cell(fa, 'T0_us', '%.2f')} | {cell(fa, 'W_max_GB_s', '%.0f')} | "
-                     f"{cell(fa, 'B08_MB', '%.1f')} | {cell(fg, 'T0_us', '%.2f')} | {cell(fg, 'W_max_GB_s', '%.0f')} | "
+                     f"{cell(fa, 'B08_MB', '%.1f')} | {cell(fg, 'W_max_GB_s', '%.0f')} | {cell(ga, 'T0_us', '%.2f')} | "
+                     f"{cell(ga, 'W_max_GB_s', '%.0f')} | {cell(gs, 'T0_us', '%.2f')} | "
                      f"{best['GB_s']:.0f} ({best['bytes'] / 1e9:.3g} GB) |")
     lines += ["", "Per-size bandwidth (GB/s, events):", ""]
     for r in results:
