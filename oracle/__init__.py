@@ -15,6 +15,8 @@ kernels I: Streaming Operations"):
   model  -- the launch-latency + bandwidth model, its least-squares fit and
             the Fischer-Brown point (eqs. time_model, perf_model,
             Fischer-Brown)
+  cg     -- conjugate gradients (Algorithm 1) on a 7-point operator, and
+            mixed-precision iterative refinement around it
 """
 
-from . import ops, mesh, model  # noqa: F401
+from . import cg, mesh, model, ops  # noqa: F401
