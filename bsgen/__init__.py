@@ -181,7 +181,7 @@ def _devlib():
         import torch  # noqa: F401  (bind to torch's HIP runtime, loaded first)
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbsgen.so")
         if not os.path.exists(path):
-            raise ImportError(f"{path} is not built (python -m paper_2009_10917_amd.build)")
+            raise ImportError(f"{path} is not built (python paper_2009_10917_amd/build.py)")
         lib = ctypes.CDLL(path)
         lib.bsgen_uniform.restype = ctypes.c_int
         lib.bsgen_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,

@@ -201,6 +201,55 @@ bs_status bs_gather(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xL
 bs_status bs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
                      void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Conjugate gradients built from the operations above (Algorithm 1), on the
+ * 7-point finite-difference operator
+ *   (A x)_ijk = (6 + shift) x_ijk - x_(i-1)jk - x_(i+1)jk - x_i(j-1)k
+ *               - x_i(j+1)k - x_ij(k-1) - x_ij(k+1)
+ * on an m x m x m grid of unknowns, index i + m*(j + m*k), with zero
+ * Dirichlet ghost values.  The additions run in exactly that order (absent
+ * neighbours skipped), with 6 + shift computed in binary64 and rounded once
+ * to the working precision, so the binary64 operator is reproducible bit
+ * for bit.
+ * ------------------------------------------------------------------------- */
+
+/* y = A x on the m^3 grid (x, y of `dtype`, m^3 entries each; binary32
+ * arithmetic for the narrow dtypes).  Asynchronous like the seven ops. */
+bs_status bs_stencil7(bs_ctx* ctx, bs_dtype dtype, int64_t m, double shift, const void* x, void* y,
+                      void* stream);
+
+typedef struct {
+  int64_t iterations;       /* CG iterations (all inner iterations for IR)       */
+  int64_t outer_iterations; /* refinement steps (0 for bs_cg_solve)              */
+  int64_t restarts;         /* restarts from the true residual (bs_cg_solve)     */
+  double rel_residual;      /* ||b - A x||_2 / ||b||_2 at exit, binary64, true   */
+  double seconds;           /* wall time of the call                             */
+} bs_cg_result;
+
+/* Solve A x = b in binary64 by CG, starting from the given x (d_b, d_x:
+ * binary64[m^3] device vectors; x is overwritten).  Stops when the true
+ * relative residual ||b - Ax|| / ||b|| <= tol (iteration stops on the
+ * recursive residual r.r first, then the true residual is recomputed and CG
+ * restarts from it if needed), or after max_iter iterations in total.  The
+ * scalars of each iteration stay on the device and batches of iterations
+ * run as one captured HIP graph.  Allocates its workspace (3 vectors) and
+ * synchronises `stream`; returns BS_ERR_NO_CONVERGENCE if tol is not met.
+ * m^3 must stay below 2^31. */
+bs_status bs_cg_solve(bs_ctx* ctx, int64_t m, double shift, const double* d_b, double* d_x, double tol,
+                      int64_t max_iter, bs_cg_result* res, void* stream);
+
+/* Mixed-precision iterative refinement: binary64 residual r = b - A x,
+ * ||r|| and update x += ||r|| d; the correction d solves A d = r/||r|| by CG
+ * with vectors stored in `inner` (BS_F32 or BS_BF16; BS_F64 is accepted)
+ * and binary32 arithmetic, to relative residual inner_tol or max_inner
+ * iterations.  Stops when the true relative residual <= tol, after
+ * max_outer refinement steps, or when the outer residual fails to halve over
+ * three steps (BS_ERR_NO_CONVERGENCE, with res still filled in).  x starts
+ * from its given value.  Allocates its workspace and synchronises `stream`. */
+bs_status bs_cg_ir_solve(bs_ctx* ctx, bs_dtype inner, int64_t m, double shift, const double* d_b, double* d_x,
+                         double tol, double inner_tol, int64_t max_inner, int64_t max_outer, bs_cg_result* res,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ calls, raises ``BSError`` on a non-OK status, and launches on
 ``torch.cuda.current_stream()`` unless a stream handle is given.
 
 Importing this package fails with ImportError if libbs.so has not been
-built (``python -m paper_2009_10917_amd.build``); there is no fallback path.
+built (``python paper_2009_10917_amd/build.py``); there is no fallback path.
 """
 
 import ctypes
@@ -56,7 +56,18 @@ PROTOTYPES = {
     "bs_gs_weights": (_st, [_p, _i32, _p, _p]),
     "bs_gather": (_st, [_p, _p, _i32, _p, _p, _p]),
     "bs_scatter": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "bs_stencil7": (_st, [_p, _i32, _i64, _d, _p, _p, _p]),
+    "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
+    "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
 }
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("outer_iterations", ctypes.c_int64),
+                ("restarts", ctypes.c_int64), ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class BSError(RuntimeError):
@@ -72,7 +83,7 @@ def _load():
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is not built; run `python -m paper_2009_10917_amd.build` "
+            f"{LIB_PATH} is not built; run `python paper_2009_10917_amd/build.py` "
             "(the streaming operations have no non-HIP implementation)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in PROTOTYPES.items():
@@ -292,3 +303,45 @@ def bs_scatter(ctx, plan, xG, xL, stream=None):
     plan.expect(xG, plan.n_global, "bs_scatter xG")
     _check(lib.bs_scatter(ctx.handle, plan.handle, _dtype_id(xG), _ptr(xG), _ptr(xL), _stream(stream)),
            "bs_scatter")
+
+
+def bs_stencil7(ctx, m, shift, x, y, stream=None):
+    _same(x, y, "bs_stencil7")
+    if x.numel() != m ** 3:
+        raise ValueError("bs_stencil7: vectors must have m^3 entries")
+    _check(lib.bs_stencil7(ctx.handle, _dtype_id(x), m, float(shift), _ptr(x), _ptr(y), _stream(stream)),
+           "bs_stencil7")
+
+
+def _solver_vectors(m, b, x, what):
+    import torch
+    for v in (b, x):
+        if v.dtype != torch.float64 or v.numel() != m ** 3:
+            raise ValueError(f"{what}: b and x must be float64 with m^3 entries")
+
+
+def bs_cg_solve(ctx, m, shift, b, x, tol=1e-10, max_iter=100000, stream=None, check=True):
+    """Binary64 CG on the 7-point operator; returns the result record as a dict."""
+    _solver_vectors(m, b, x, "bs_cg_solve")
+    res = CgResult()
+    st = lib.bs_cg_solve(ctx.handle, m, float(shift), _ptr(b), _ptr(x), float(tol), int(max_iter),
+                         ctypes.byref(res), _stream(stream))
+    if check:
+        _check(st, "bs_cg_solve")
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return out
+
+
+def bs_cg_ir_solve(ctx, inner_dtype, m, shift, b, x, tol=1e-10, inner_tol=1e-4, max_inner=400, max_outer=50,
+                   stream=None, check=True):
+    """Mixed-precision iterative refinement; inner_dtype is BS_F32, BS_BF16 or BS_F64."""
+    _solver_vectors(m, b, x, "bs_cg_ir_solve")
+    res = CgResult()
+    st = lib.bs_cg_ir_solve(ctx.handle, int(inner_dtype), m, float(shift), _ptr(b), _ptr(x), float(tol),
+                            float(inner_tol), int(max_inner), int(max_outer), ctypes.byref(res), _stream(stream))
+    if check:
+        _check(st, "bs_cg_ir_solve")
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return out

@@ -1,10 +1,14 @@
 """Compile the HIP sources for gfx950 into in-tree shared libraries.
 
-    python -m paper_2009_10917_amd.build
+    python paper_2009_10917_amd/build.py
 
 builds ``paper_2009_10917_amd/libbs.so`` (the streaming-operation library)
 and ``bsgen/libbsgen.so`` (the device form of the seeded input generator).
 Objects go to ``_build/``; every call recompiles.
+
+Run it as a file (or load it by path): importing it through the package
+would first load the library it is about to rebuild, which fails when the
+library is missing or older than the header.
 """
 
 import os
@@ -32,7 +36,7 @@ COMMON = [
 LIBS = {
     os.path.join(PKG, "libbs.so"): [
         os.path.join(PKG, "csrc", f)
-        for f in ("bs_host.hip", "bs_stream.hip", "bs_mesh.hip", "bs_plan.hip", "bs_gs.hip")
+        for f in ("bs_host.hip", "bs_stream.hip", "bs_mesh.hip", "bs_plan.hip", "bs_gs.hip", "bs_cg.hip")
     ],
     os.path.join(ROOT, "bsgen", "libbsgen.so"): [os.path.join(ROOT, "bsgen", "csrc", "bsgen.hip")],
 }

@@ -1,0 +1,538 @@
+// Conjugate gradients (Algorithm 1) built from the streaming operations, on
+// the 7-point finite-difference operator, and mixed-precision iterative
+// refinement around it.
+//
+// Operator: y = (6 + shift) x - (the six neighbours), unit spacing, on an
+// m^3 grid of unknowns (index i + m(j + m k)) with zero Dirichlet ghosts.
+// The additions run in a fixed order: centre term, then the neighbours at
+// i-1, i+1, j-1, j+1, k-1, k+1 (absent neighbours skipped), with the diagonal
+// computed in binary64 and rounded once to the working precision.  Each
+// wave of 64 lanes sweeps one grid row; the j and k neighbours come from L2.
+//
+// One CG iteration is five launches on the device:
+//   Ap = A p with the compensated partial sums of p.Ap      (operator + BS4)
+//   alpha = r.r / p.Ap                                       (1 workgroup)
+//   x += alpha p, r -= alpha Ap, partial sums of r.r         (BS5)
+//   beta = r'.r' / r.r, convergence test                     (1 workgroup)
+//   p = r + beta p                                           (BS2)
+// The scalars live in a device-side state, so nothing returns to the host
+// inside an iteration; once the state says done, the remaining kernels of a
+// batch return at once.  Batches of iterations are captured into one HIP
+// graph and replayed; the host reads the state once per batch.
+//
+// Iterative refinement (binary64 outer loop, inner CG in binary32 or
+// bfloat16 storage with binary32 arithmetic): r = b - A x and ||r|| in
+// binary64; inner CG on A d = r/||r|| to a relative residual inner_tol (or
+// max_inner iterations); x += ||r|| d in binary64; stop when the true
+// relative residual ||b - A x|| / ||b|| <= tol.
+
+#include <chrono>
+#include <cmath>
+
+#include "bs_stream_ops.h"
+
+namespace bs {
+namespace {
+
+using namespace ops;
+
+constexpr int kRowsPerBlock = kBlock / 64;  // one grid row per wave
+constexpr int kMaxDotBlocks = 16384;
+constexpr int kBatch = 16;                  // iterations per captured graph
+
+inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
+
+template <class T> struct DtypeOf;
+template <> struct DtypeOf<double> { static constexpr bs_dtype v = BS_F64; };
+template <> struct DtypeOf<float> { static constexpr bs_dtype v = BS_F32; };
+template <> struct DtypeOf<dev::bf16> { static constexpr bs_dtype v = BS_BF16; };
+template <class T>
+constexpr bs_dtype dtype_of() {
+  return DtypeOf<T>::v;
+}
+
+// First stage of a reduction whose second stage is a separate launch.
+__device__ __forceinline__ void store_partial(DW<double> a, double* partials) {
+  a = dev::block_reduce<kBlock>(a);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = a.s;
+    partials[2 * blockIdx.x + 1] = a.c;
+  }
+}
+
+__device__ __forceinline__ double sum_partials(const double* partials, int G) {
+  DW<double> r{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kFinishBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  r = dev::block_reduce<kFinishBlock>(r);
+  return r.s + r.c;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------- the operator
+
+template <class T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_stencil(int32_t m, typename Storage<T>::C c,
+                                                    const typename Storage<T>::E* __restrict__ x,
+                                                    typename Storage<T>::E* __restrict__ y, double* partials,
+                                                    const int32_t* done) {
+  using S = Storage<T>;
+  using C = typename S::C;
+  using E = typename S::E;
+  if (done && *done) return;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t plane = static_cast<int64_t>(m) * m;
+  DW<C> acc{C(0), C(0)};
+  for (int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave; row < plane;
+       row += static_cast<int64_t>(gridDim.x) * kRowsPerBlock) {
+    const int32_t j = static_cast<int32_t>(row % m), k = static_cast<int32_t>(row / m);
+    const int64_t base = row * m;
+    for (int32_t i = lane; i < m; i += 64) {
+      const int64_t g = base + i;
+      const C xc = S::load(x[g]);
+      C s = c * xc;
+      if (i > 0) s -= S::load(x[g - 1]);
+      if (i < m - 1) s -= S::load(x[g + 1]);
+      if (j > 0) s -= S::load(x[g - m]);
+      if (j < m - 1) s -= S::load(x[g + m]);
+      if (k > 0) s -= S::load(x[g - plane]);
+      if (k < m - 1) s -= S::load(x[g + plane]);
+      const E ys = S::store(s);
+      y[g] = ys;
+      if (DOT) dev::dw_acc_prod(acc, xc, S::load(ys));
+    }
+  }
+  if (DOT) store_partial(DW<double>{static_cast<double>(acc.s), static_cast<double>(acc.c)}, partials);
+}
+
+template <class T>
+bs_status launch_stencil(int64_t m, double shift, const void* x, void* y, hipStream_t st) {
+  using S = Storage<T>;
+  using C = typename S::C;
+  using E = typename S::E;
+  const int64_t rows = m * m;
+  const unsigned int g = static_cast<unsigned int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
+  hipLaunchKernelGGL((k_stencil<T, false>), dim3(g), dim3(kBlock), 0, st, static_cast<int32_t>(m),
+                     static_cast<C>(6.0 + shift), static_cast<const E*>(x), static_cast<E*>(y),
+                     static_cast<double*>(nullptr), static_cast<const int32_t*>(nullptr));
+  return check_launch("bs_stencil7");
+}
+
+// ---------------------------------------------------------------- device-side CG state
+
+struct CgState {
+  double rr;       // r.r of the current residual
+  double pAp;      // p.Ap of the current direction
+  double alpha;
+  double beta;
+  double stop_rr;  // iterate while rr > stop_rr
+  int32_t done;    // 0 running, 1 converged or out of iterations, 2 breakdown
+  int32_t iters;
+  int32_t max_iters;
+  int32_t pad;
+};
+
+__global__ void k_cg_init(CgState* st, const double* rr, double stop_rr, int32_t max_iters) {
+  if (threadIdx.x == 0) {
+    st->rr = *rr;
+    st->stop_rr = stop_rr;
+    st->iters = 0;
+    st->max_iters = max_iters;
+    st->done = (*rr <= stop_rr || max_iters <= 0) ? 1 : 0;
+    st->alpha = st->beta = st->pAp = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kFinishBlock) void k_after_pAp(const double* __restrict__ partials, int G,
+                                                             CgState* st) {
+  if (st->done) return;
+  const double pAp = sum_partials(partials, G);
+  if (threadIdx.x == 0) {
+    st->pAp = pAp;
+    if (pAp > 0.0) {
+      st->alpha = st->rr / pAp;
+    } else {
+      st->done = 2;  // A is not positive definite on p (or p vanished)
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFinishBlock) void k_after_update(const double* __restrict__ partials, int G,
+                                                                CgState* st) {
+  if (st->done) return;
+  const double rr_new = sum_partials(partials, G);
+  if (threadIdx.x == 0) {
+    st->beta = rr_new / st->rr;
+    st->rr = rr_new;
+    st->iters += 1;
+    if (!__builtin_isfinite(rr_new))
+      st->done = 2;  // overflow or NaN: further iterations cannot recover
+    else if (rr_new <= st->stop_rr || st->iters >= st->max_iters)
+      st->done = 1;
+  }
+}
+
+template <class T, int V, int U>
+__global__ __launch_bounds__(kBlock) void k_cg_step(const CgState* st, typename Storage<T>::E* __restrict__ x,
+                                                    const typename Storage<T>::E* __restrict__ p,
+                                                    typename Storage<T>::E* __restrict__ r,
+                                                    const typename Storage<T>::E* __restrict__ Ap, Span sp,
+                                                    double* partials) {
+  using C = typename Storage<T>::C;
+  if (st->done) return;
+  CgOp<T, V, false> op{{}, static_cast<C>(st->alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
+  stream_loop<U>(op, sp);
+  store_partial(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials);
+}
+
+template <class T, int V, int U>
+__global__ __launch_bounds__(kBlock) void k_direction(const CgState* st, const typename Storage<T>::E* __restrict__ r,
+                                                      typename Storage<T>::E* __restrict__ p, Span sp) {
+  using C = typename Storage<T>::C;
+  if (st->done) return;
+  AxpyOp<T, V> op{{}, C(1), static_cast<C>(st->beta), r, p, sp.head};
+  stream_loop<U>(op, sp);
+}
+
+// ---------------------------------------------------------------- precision changes
+
+// out = round(r * s) in the narrow storage (binary64 -> binary32 -> bfloat16)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scale_to(const double* __restrict__ r, double s, int64_t n,
+                                                     typename Storage<T>::E* __restrict__ out) {
+  using S = Storage<T>;
+  using C = typename S::C;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) out[i] = S::store(static_cast<C>(r[i] * s));
+}
+
+// x = x + s * d  (binary64 x, narrow d)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_add_scaled(double* __restrict__ x, double s,
+                                                       const typename Storage<T>::E* __restrict__ d, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) x[i] = x[i] + s * static_cast<double>(Storage<T>::load(d[i]));
+}
+
+template <class E>
+__global__ __launch_bounds__(kBlock) void k_zero(E* __restrict__ p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = E{};
+}
+
+// ---------------------------------------------------------------- host-side CG engine
+
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Runs CG iterations in dtype T on vectors owned by the caller.
+template <class T>
+struct CgEngine {
+  using S = Storage<T>;
+  using E = typename S::E;
+  using C = typename S::C;
+
+  bs_ctx* ctx;
+  hipStream_t st;
+  int64_t m, n;
+  double shift;
+  E *x, *r, *p, *Ap;
+  CgState* state;
+  double* rr_dev;  // scratch scalar
+  Span sp;
+  int g_dot = 1, g_upd = 1;
+  hipGraphExec_t exec = nullptr;
+
+  ~CgEngine() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+
+  void enqueue_iteration() {
+    hipLaunchKernelGGL((k_stencil<T, true>), dim3(g_dot), dim3(kBlock), 0, st, static_cast<int32_t>(m),
+                       static_cast<C>(6.0 + shift), static_cast<const E*>(p), Ap, ctx->partials,
+                       reinterpret_cast<const int32_t*>(&state->done));
+    hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g_dot, state);
+    if (sp.vwidth == 1)
+      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p, r, Ap, sp, ctx->partials);
+    else
+      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p, r, Ap, sp,
+                         ctx->partials);
+    hipLaunchKernelGGL(k_after_update, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g_upd, state);
+    const unsigned int g_dir = static_cast<unsigned int>(grid_for(sp, 1, 1 << 30));
+    if (sp.vwidth == 1)
+      hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+    else
+      hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+  }
+
+  bs_status prepare() {
+    sp = make_span<T>(n, {x, r, p, Ap});
+    const int64_t rows = m * m;
+    int64_t gd = (rows + kRowsPerBlock - 1) / kRowsPerBlock;
+    g_dot = static_cast<int>(gd < kMaxDotBlocks ? gd : kMaxDotBlocks);
+    g_upd = grid_for(sp, 4, kMaxReduceBlocks);
+    // capture kBatch iterations into one graph
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager fallback
+    for (int i = 0; i < kBatch; ++i) enqueue_iteration();
+    const hipError_t e1 = hipStreamEndCapture(st, &graph);
+    if (e1 != hipSuccess || !graph) {
+      (void)hipGetLastError();
+      return BS_OK;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      exec = nullptr;
+      (void)hipGetLastError();
+    }
+    return BS_OK;
+  }
+
+  // Iterate until the state reports done; returns the final state.
+  bs_status run(double stop_rr, int32_t max_iters, CgState* out) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, st, state, rr_dev, stop_rr, max_iters);
+    bs_status s = check_launch("cg");
+    while (!s) {
+      if (exec) {
+        s = check_hip(hipGraphLaunch(exec, st), "cg graph launch");
+      } else {
+        for (int i = 0; i < kBatch; ++i) enqueue_iteration();
+        s = check_launch("cg");
+      }
+      if (!s) s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
+      if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
+      if (!s && out->done) break;
+    }
+    return s;
+  }
+};
+
+// Solver workspace: one allocation, carved into aligned pieces.
+struct Workspace {
+  DevMem mem;
+  char* cur = nullptr;
+  size_t left = 0;
+  bool alloc(size_t bytes) {
+    if (hipMalloc(&mem.p, bytes) != hipSuccess) return false;
+    cur = static_cast<char*>(mem.p);
+    left = bytes;
+    return true;
+  }
+  template <class X>
+  X* take(int64_t count) {
+    const size_t bytes = (static_cast<size_t>(count) * sizeof(X) + 255) & ~static_cast<size_t>(255);
+    X* q = reinterpret_cast<X*>(cur);
+    cur += bytes;
+    left -= bytes;
+    return q;
+  }
+};
+
+inline size_t padded(size_t bytes) { return (bytes + 255) & ~static_cast<size_t>(255); }
+
+bs_status check_solver_args(const char* op, bs_ctx* ctx, int64_t m, const double* b, const double* x, double tol) {
+  bs_status s;
+  if ((s = check_ctx(ctx, op))) return s;
+  if (m < 1 || m > 4096 || m * m * m >= (int64_t(1) << 31))
+    return fail(BS_ERR_INVALID_ARG, "%s: grid size m must lie in [1, 1290]", op);
+  if (!b || !x) return fail(BS_ERR_INVALID_ARG, "%s: b or x is NULL", op);
+  if (!aligned_to(b, 8) || !aligned_to(x, 8)) return fail(BS_ERR_INVALID_ARG, "%s: misaligned vector", op);
+  if (!(tol > 0.0)) return fail(BS_ERR_INVALID_ARG, "%s: tolerance must be positive", op);
+  return BS_OK;
+}
+
+// r = b - A x (binary64); returns r.r in *rr_host
+bs_status residual(bs_ctx* ctx, int64_t m, double shift, const double* b, const double* x, double* r, double* rr_dev,
+                   double* rr_host, hipStream_t st) {
+  const int64_t n = m * m * m;
+  bs_status s = launch_stencil<double>(m, shift, x, r, st);
+  if (!s) s = bs_axpy(ctx, BS_F64, n, 1.0, b, -1.0, r, st);
+  if (!s) s = bs_norm(ctx, BS_F64, n, r, nullptr, rr_dev, st);
+  if (!s) s = check_hip(hipMemcpyAsync(rr_host, rr_dev, sizeof(double), hipMemcpyDeviceToHost, st), "residual");
+  if (!s) s = check_hip(hipStreamSynchronize(st), "residual");
+  return s;
+}
+
+struct OwnStream {
+  hipStream_t s = nullptr;
+  ~OwnStream() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+template <class T>
+bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double* x, double tol, double inner_tol,
+                   int64_t max_inner, int64_t max_outer, bs_cg_result* res, hipStream_t caller) {
+  using E = typename Storage<T>::E;
+  const char* op = "bs_cg_ir_solve";
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = m * m * m;
+  bs_status s = check_hip(hipStreamSynchronize(caller), op);
+  if (s) return s;
+  OwnStream own;
+  if ((s = check_hip(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking), op))) return s;
+  hipStream_t st = own.s;
+  Workspace ws;
+  const size_t bytes = padded(n * 8) + 4 * padded(n * sizeof(E)) + 2 * padded(sizeof(CgState)) + 1024;
+  if (!ws.alloc(bytes)) return fail(BS_ERR_ALLOC, "%s: cannot allocate %zu bytes of workspace", op, bytes);
+  double* r64 = ws.take<double>(n);
+  E* rl = ws.take<E>(n);
+  E* d = ws.take<E>(n);
+  E* p = ws.take<E>(n);
+  E* Ap = ws.take<E>(n);
+  CgState* state = ws.take<CgState>(1);
+  double* scal = ws.take<double>(8);
+
+  CgEngine<T> eng{ctx, st, m, n, shift, d, rl, p, Ap, state, scal};
+  if ((s = eng.prepare())) return s;
+
+  double bb = 0.0;
+  if ((s = bs_norm(ctx, BS_F64, n, b, nullptr, scal + 1, st))) return s;
+  if ((s = check_hip(hipMemcpyAsync(&bb, scal + 1, 8, hipMemcpyDeviceToHost, st), op))) return s;
+  if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+  const double stop = tol * tol * bb;
+  double hist[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  int64_t outer = 0, inner = 0;
+  double rr = 0.0;
+  bool stagnated = false;
+  while (true) {
+    if ((s = residual(ctx, m, shift, b, x, r64, scal + 2, &rr, st))) return s;
+    if (rr <= stop || outer >= max_outer) break;
+    // outer residual must halve within three refinement steps
+    if (outer >= 3 && std::sqrt(rr) > 0.5 * std::sqrt(hist[(outer - 3) % 4])) {
+      stagnated = true;
+      break;
+    }
+    hist[outer % 4] = rr;
+    const double nr = std::sqrt(rr);
+    hipLaunchKernelGGL((k_scale_to<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, r64, 1.0 / nr, n, rl);
+    hipLaunchKernelGGL((k_zero<E>), dim3(blocks_for(n)), dim3(kBlock), 0, st, d, n);
+    if ((s = check_launch(op))) return s;
+    if ((s = bs_copy(ctx, dtype_of<T>(), n, rl, p, st))) return s;
+    if ((s = bs_norm(ctx, dtype_of<T>(), n, rl, nullptr, scal, st))) return s;
+    double rr0 = 0.0;
+    if ((s = check_hip(hipMemcpyAsync(&rr0, scal, 8, hipMemcpyDeviceToHost, st), op))) return s;
+    if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+    CgState fin{};
+    if ((s = eng.run(inner_tol * inner_tol * rr0, static_cast<int32_t>(max_inner), &fin))) return s;
+    inner += fin.iters;
+    hipLaunchKernelGGL((k_add_scaled<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, x, nr, static_cast<const E*>(d), n);
+    if ((s = check_launch(op))) return s;
+    ++outer;
+  }
+  if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+  if (res) {
+    res->iterations = inner;
+    res->outer_iterations = outer;
+    res->restarts = 0;
+    res->rel_residual = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (stagnated || rr > stop)
+    return fail(BS_ERR_NO_CONVERGENCE, "%s: relative residual %.3e after %lld refinement steps", op,
+                bb > 0.0 ? std::sqrt(rr / bb) : 0.0, static_cast<long long>(outer));
+  return BS_OK;
+}
+
+}  // namespace
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" bs_status bs_stencil7(bs_ctx* ctx, bs_dtype dtype, int64_t m, double shift, const void* x, void* y,
+                                 void* stream) {
+  bs_status s;
+  const char* op = "bs_stencil7";
+  if ((s = check_ctx(ctx, op)) || (s = check_dtype(op, dtype))) return s;
+  if (m < 0 || m > 46340 || (m > 0 && m * m * m >= (int64_t(1) << 40)))
+    return fail(BS_ERR_INVALID_ARG, "%s: bad grid size %lld", op, static_cast<long long>(m));
+  const int64_t n = m * m * m;
+  if ((s = check_vec(op, "x", x, n, dtype)) || (s = check_vec(op, "y", y, n, dtype))) return s;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
+  const uintptr_t nb = static_cast<uintptr_t>(n) * dtype_size(dtype);
+  if (n && a < b + nb && b < a + nb) return fail(BS_ERR_INVALID_ARG, "%s: y overlaps x", op);
+  if (n == 0) return BS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case BS_F64: return launch_stencil<double>(m, shift, x, y, st);
+    case BS_F32: return launch_stencil<float>(m, shift, x, y, st);
+    case BS_BF16: return launch_stencil<dev::bf16>(m, shift, x, y, st);
+  }
+  return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype", op);
+}
+
+extern "C" bs_status bs_cg_solve(bs_ctx* ctx, int64_t m, double shift, const double* d_b, double* d_x, double tol,
+                                 int64_t max_iter, bs_cg_result* res, void* stream) {
+  const char* op = "bs_cg_solve";
+  bs_status s;
+  if ((s = check_solver_args(op, ctx, m, d_b, d_x, tol))) return s;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = m * m * m;
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  if ((s = check_hip(hipStreamSynchronize(caller), op))) return s;
+  OwnStream own;
+  if ((s = check_hip(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking), op))) return s;
+  hipStream_t st = own.s;
+  Workspace ws;
+  const size_t bytes = 3 * padded(n * 8) + padded(sizeof(CgState)) + 1024;
+  if (!ws.alloc(bytes)) return fail(BS_ERR_ALLOC, "%s: cannot allocate %zu bytes of workspace", op, bytes);
+  double* r = ws.take<double>(n);
+  double* p = ws.take<double>(n);
+  double* Ap = ws.take<double>(n);
+  CgState* state = ws.take<CgState>(1);
+  double* scal = ws.take<double>(8);
+  CgEngine<double> eng{ctx, st, m, n, shift, d_x, r, p, Ap, state, scal};
+  if ((s = eng.prepare())) return s;
+  double bb = 0.0;
+  if ((s = bs_norm(ctx, BS_F64, n, d_b, nullptr, scal + 1, st))) return s;
+  if ((s = check_hip(hipMemcpyAsync(&bb, scal + 1, 8, hipMemcpyDeviceToHost, st), op))) return s;
+  if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+  const double stop = tol * tol * bb;
+  int64_t iters = 0, restarts = 0;
+  double rr = 0.0;
+  bool breakdown = false;
+  while (true) {
+    // (re)start from the true residual
+    if ((s = residual(ctx, m, shift, d_b, d_x, r, scal, &rr, st))) return s;
+    if (rr <= stop || iters >= max_iter || breakdown) break;
+    if ((s = bs_copy(ctx, BS_F64, n, r, p, st))) return s;
+    CgState fin{};
+    const int64_t left = max_iter - iters;
+    if ((s = eng.run(stop, static_cast<int32_t>(left < INT32_MAX ? left : INT32_MAX), &fin))) return s;
+    iters += fin.iters;
+    breakdown = fin.done == 2;
+    ++restarts;
+  }
+  if (res) {
+    res->iterations = iters;
+    res->outer_iterations = 0;
+    res->restarts = restarts > 0 ? restarts - 1 : 0;
+    res->rel_residual = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (rr > stop)
+    return fail(BS_ERR_NO_CONVERGENCE, "%s: relative residual %.3e after %lld iterations", op,
+                bb > 0.0 ? std::sqrt(rr / bb) : 0.0, static_cast<long long>(iters));
+  return BS_OK;
+}
+
+extern "C" bs_status bs_cg_ir_solve(bs_ctx* ctx, bs_dtype inner, int64_t m, double shift, const double* d_b,
+                                    double* d_x, double tol, double inner_tol, int64_t max_inner, int64_t max_outer,
+                                    bs_cg_result* res, void* stream) {
+  const char* op = "bs_cg_ir_solve";
+  bs_status s;
+  if ((s = check_solver_args(op, ctx, m, d_b, d_x, tol)) || (s = check_dtype(op, inner))) return s;
+  if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(BS_ERR_INVALID_ARG, "%s: inner_tol must lie in (0, 1)", op);
+  if (max_inner < 1 || max_inner > INT32_MAX || max_outer < 0)
+    return fail(BS_ERR_INVALID_ARG, "%s: bad iteration limits", op);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (inner) {
+    case BS_F64: return ir_solve<double>(ctx, m, shift, d_b, d_x, tol, inner_tol, max_inner, max_outer, res, st);
+    case BS_F32: return ir_solve<float>(ctx, m, shift, d_b, d_x, tol, inner_tol, max_inner, max_outer, res, st);
+    case BS_BF16: return ir_solve<dev::bf16>(ctx, m, shift, d_b, d_x, tol, inner_tol, max_inner, max_outer, res, st);
+  }
+  return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype", op);
+}

@@ -17,8 +17,8 @@ LIB = os.path.join(ROOT, "paper_2009_10917_amd", "libbs.so")
 
 def _ensure_built():
     if not os.path.exists(LIB):
-        from paper_2009_10917_amd import build
-        build.build()
+        import __graft_entry__
+        __graft_entry__._builder().build()
 
 
 _ensure_built()
@@ -70,6 +70,9 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_ctx_set_tune(None, 0, 0, 4, 16, 0) == INVALID
     out = ctypes.c_void_p()
     assert L.bs_gs_create(None, 16, 10, 10, None, ctypes.byref(out)) == INVALID
+    assert L.bs_stencil7(None, 0, 3, 0.01, 16, 32, None) == INVALID
+    assert L.bs_cg_solve(None, 3, 0.01, 16, 32, 1e-10, 10, None, None) == INVALID
+    assert L.bs_cg_ir_solve(None, 1, 3, 0.01, 16, 32, 1e-10, 1e-4, 10, 10, None, None) == INVALID
     assert L.bs_ctx_create(0, None) == INVALID
     # destroying NULL handles is a no-op
     assert L.bs_ctx_destroy(None) == 0 and L.bs_gs_destroy(None) == 0
