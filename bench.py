@@ -279,6 +279,54 @@ def _write_sweep_md(path, results, K_max):
         fh.write("\n".join(lines) + "\n")
 
 
+def mixed_cg(ctx, bs, bsgen, torch, seed, reps, m=225, shift=0.01, tol=1e-10):
+    """Time-to-solution of CG on the shifted 7-point operator (m^3 unknowns).
+
+    Forms: binary64 CG; iterative refinement (binary64 outer) around CG in
+    binary32 storage and in bfloat16 storage.  Each solve starts from x = 0
+    and ends on a true relative residual <= tol recomputed in binary64; its
+    time is host wall clock around the whole call (workspace, graph capture
+    and every refinement step included).  The effective GDOF/s of a form is
+    n * (binary64 CG iterations) / t, so the speedup of a mixed form is
+    t_f64 / t_mixed.
+    """
+    n = m ** 3
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    bsgen.device_uniform(b, seed, bsgen.STREAM["b"])
+    x = torch.zeros_like(b)
+    forms = (("f64", None, None), ("ir_f32", bs.BS_F32, 1e-4), ("ir_bf16", bs.BS_BF16, 0.1))
+    out = {"m": m, "n": n, "shift": shift, "tol": tol}
+    for name, inner, inner_tol in forms:
+        times, rec = [], None
+        for k in range(reps + 1):  # the first solve warms up code and allocator
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if inner is None:
+                rec = bs.bs_cg_solve(ctx, m, shift, b, x, tol=tol, check=False)
+            else:
+                rec = bs.bs_cg_ir_solve(ctx, inner, m, shift, b, x, tol=tol, inner_tol=inner_tol, max_outer=40,
+                                        check=False)
+            torch.cuda.synchronize()
+            if k:
+                times.append(time.perf_counter() - t0)
+        t = min(times)
+        out[name] = {"status": rec["status"], "ms": round(t * 1e3, 3), "iterations": rec["iterations"],
+                     "outer": rec["outer_iterations"], "restarts": rec["restarts"],
+                     "true_rel_residual": rec["rel_residual"], "inner_tol": inner_tol,
+                     "ms_per_inner_iteration": round(t * 1e3 / max(rec["iterations"], 1), 4)}
+        print(f"# cg {name}: {out[name]}", file=sys.stderr, flush=True)
+    it64 = out["f64"]["iterations"]
+    for name, _, _ in forms:
+        f = out[name]
+        ok = f["status"] == "BS_OK"
+        f["GDOF_s_effective"] = round(n * it64 / (f["ms"] * 1e-3) / 1e9, 3) if ok else None
+        f["GDOF_s_ceed"] = round(n * f["iterations"] / (f["ms"] * 1e-3) / 1e9, 3)
+        f["speedup_vs_f64"] = round(out["f64"]["ms"] / f["ms"], 3) if ok else None
+    del b, x
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +345,9 @@ def main():
                     help="length sweep of BS1-BS5 (n = (7K+1)^3, K = 2, 4, ..., --K) and mesh sweeps of BS6/BS7; "
                          "prints one JSON line per operation with the launch-latency + bandwidth fit")
     ap.add_argument("--sweep-out", default="", help="also write a markdown summary of the sweep here")
+    ap.add_argument("--cg-only", action="store_true",
+                    help="only the mixed-precision CG time-to-solution (225^3 shifted 7-point operator)")
+    ap.add_argument("--no-cg", action="store_true", help="skip the mixed-precision CG section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
@@ -321,6 +372,9 @@ def main():
     stream = torch.cuda.current_stream()
     hs = stream.cuda_stream
     ctx = bs.bs_ctx_create(0)
+    if args.cg_only:
+        print(json.dumps({"metric": METRIC, "mixed_cg": mixed_cg(ctx, bs, bsgen, torch, args.seed, args.reps)}))
+        return 0
 
     E = K ** 3
     n = (K * N + 1) ** 3
@@ -441,6 +495,8 @@ def main():
     del x, y, p, r, Ap, w, xL, xG, xG_out
     plan.close()
     torch.cuda.synchronize()
+    if not args.no_cg:
+        result["mixed_cg"] = mixed_cg(ctx, bs, bsgen, torch, args.seed, args.reps)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample, 16, N, args.seed)
     print(json.dumps(result))

@@ -1,44 +1,55 @@
 // Conjugate gradients (Algorithm 1) built from the streaming operations, on
 // the 7-point finite-difference operator, and mixed-precision iterative
-// refinement around it.
+// refinement around it.  The operator kernels live in bs_stencil.h.
 //
-// Operator: y = (6 + shift) x - (the six neighbours), unit spacing, on an
-// m^3 grid of unknowns (index i + m(j + m k)) with zero Dirichlet ghosts.
-// The additions run in a fixed order: centre term, then the neighbours at
-// i-1, i+1, j-1, j+1, k-1, k+1 (absent neighbours skipped), with the diagonal
-// computed in binary64 and rounded once to the working precision.  Each
-// wave of 64 lanes sweeps one grid row; the j and k neighbours come from L2.
+// One CG iteration runs on the device without returning to the host:
+//   Ap = A p with the partial sums of p.Ap               (operator + BS4)
+//   alpha = r.r / p.Ap                                   (1 workgroup)
+//   x += alpha p, r -= alpha Ap, partial sums of r.r     (BS5)
+//   beta = r'.r' / r.r, convergence test                 (1 workgroup)
+//   p = r + beta p                                       (BS2)
+// For binary32 and bfloat16 storage the direction update is folded into the
+// next operator application: that kernel reads r and the old p, forms the new
+// p with the same rounded operations the AXPY uses, writes it to a second
+// buffer (p alternates between two buffers) and applies the operator to it;
+// the first iteration runs with beta = 0 on p = r.  In binary64 the four
+// vectors of the fused kernel outgrow the 256 MB last-level cache on the
+// benchmark grid, and its halo re-reads then cost more than the separate
+// AXPY, so binary64 keeps the five-launch form.
 //
-// One CG iteration is five launches on the device:
-//   Ap = A p with the compensated partial sums of p.Ap      (operator + BS4)
-//   alpha = r.r / p.Ap                                       (1 workgroup)
-//   x += alpha p, r -= alpha Ap, partial sums of r.r         (BS5)
-//   beta = r'.r' / r.r, convergence test                     (1 workgroup)
-//   p = r + beta p                                           (BS2)
-// The scalars live in a device-side state, so nothing returns to the host
-// inside an iteration; once the state says done, the remaining kernels of a
-// batch return at once.  Batches of iterations are captured into one HIP
-// graph and replayed; the host reads the state once per batch.
+// The scalars live in a device-side state; once it says done, the remaining
+// kernels of a batch return at once.  Batches of iterations are captured into
+// one HIP graph and replayed; the host reads the state once per batch.
 //
 // Iterative refinement (binary64 outer loop, inner CG in binary32 or
 // bfloat16 storage with binary32 arithmetic): r = b - A x and ||r|| in
-// binary64; inner CG on A d = r/||r|| to a relative residual inner_tol (or
+// binary64; inner CG on A d = r/||r|| to a relative residual theta (or
 // max_inner iterations); x += ||r|| d in binary64; stop when the true
-// relative residual ||b - A x|| / ||b|| <= tol.
+// relative residual ||b - A x|| / ||b|| <= tol.  theta is inner_tol, or the
+// looser 0.5 tol ||b|| / ||r|| when that already meets the outer target, so
+// the last refinement step is not solved further than needed.
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
+#include "bs_stencil.h"
 #include "bs_stream_ops.h"
 
 namespace bs {
 namespace {
 
 using namespace ops;
+using stencil::CgState;
+using stencil::Op7;
+using stencil::store_partial;
 
-constexpr int kRowsPerBlock = kBlock / 64;  // one grid row per wave
-constexpr int kMaxDotBlocks = 16384;
-constexpr int kBatch = 16;                  // iterations per captured graph
+constexpr int kBatch = 16;  // iterations per captured graph (even)
+
+// Storage types whose CG folds the direction update into the operator.
+template <class T>
+constexpr bool kFuseDirection = !std::is_same<T, double>::value;
 
 inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
 
@@ -51,15 +62,6 @@ constexpr bs_dtype dtype_of() {
   return DtypeOf<T>::v;
 }
 
-// First stage of a reduction whose second stage is a separate launch.
-__device__ __forceinline__ void store_partial(DW<double> a, double* partials) {
-  a = dev::block_reduce<kBlock>(a);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = a.s;
-    partials[2 * blockIdx.x + 1] = a.c;
-  }
-}
-
 __device__ __forceinline__ double sum_partials(const double* partials, int G) {
   DW<double> r{0.0, 0.0};
   for (int i = threadIdx.x; i < G; i += kFinishBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
@@ -67,68 +69,18 @@ __device__ __forceinline__ double sum_partials(const double* partials, int G) {
   return r.s + r.c;  // valid in thread 0
 }
 
-// ---------------------------------------------------------------- the operator
-
-template <class T, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_stencil(int32_t m, typename Storage<T>::C c,
-                                                    const typename Storage<T>::E* __restrict__ x,
-                                                    typename Storage<T>::E* __restrict__ y, double* partials,
-                                                    const int32_t* done) {
-  using S = Storage<T>;
-  using C = typename S::C;
-  using E = typename S::E;
-  if (done && *done) return;
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int64_t plane = static_cast<int64_t>(m) * m;
-  DW<C> acc{C(0), C(0)};
-  for (int64_t row = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock + wave; row < plane;
-       row += static_cast<int64_t>(gridDim.x) * kRowsPerBlock) {
-    const int32_t j = static_cast<int32_t>(row % m), k = static_cast<int32_t>(row / m);
-    const int64_t base = row * m;
-    for (int32_t i = lane; i < m; i += 64) {
-      const int64_t g = base + i;
-      const C xc = S::load(x[g]);
-      C s = c * xc;
-      if (i > 0) s -= S::load(x[g - 1]);
-      if (i < m - 1) s -= S::load(x[g + 1]);
-      if (j > 0) s -= S::load(x[g - m]);
-      if (j < m - 1) s -= S::load(x[g + m]);
-      if (k > 0) s -= S::load(x[g - plane]);
-      if (k < m - 1) s -= S::load(x[g + plane]);
-      const E ys = S::store(s);
-      y[g] = ys;
-      if (DOT) dev::dw_acc_prod(acc, xc, S::load(ys));
-    }
-  }
-  if (DOT) store_partial(DW<double>{static_cast<double>(acc.s), static_cast<double>(acc.c)}, partials);
-}
-
 template <class T>
 bs_status launch_stencil(int64_t m, double shift, const void* x, void* y, hipStream_t st) {
-  using S = Storage<T>;
-  using C = typename S::C;
-  using E = typename S::E;
-  const int64_t rows = m * m;
-  const unsigned int g = static_cast<unsigned int>((rows + kRowsPerBlock - 1) / kRowsPerBlock);
-  hipLaunchKernelGGL((k_stencil<T, false>), dim3(g), dim3(kBlock), 0, st, static_cast<int32_t>(m),
-                     static_cast<C>(6.0 + shift), static_cast<const E*>(x), static_cast<E*>(y),
-                     static_cast<double*>(nullptr), static_cast<const int32_t*>(nullptr));
+  using E = typename Storage<T>::E;
+  int device = 0;
+  if (bs_status s = check_hip(hipGetDevice(&device), "bs_stencil7")) return s;
+  Op7<T, false, false> op;
+  if (!op.prepare(m, device)) return fail(BS_ERR_INVALID_ARG, "bs_stencil7: grid side %lld is too large", static_cast<long long>(m));
+  op.enqueue(st, shift, static_cast<const E*>(x), nullptr, nullptr, static_cast<E*>(y), nullptr, nullptr);
   return check_launch("bs_stencil7");
 }
 
-// ---------------------------------------------------------------- device-side CG state
-
-struct CgState {
-  double rr;       // r.r of the current residual
-  double pAp;      // p.Ap of the current direction
-  double alpha;
-  double beta;
-  double stop_rr;  // iterate while rr > stop_rr
-  int32_t done;    // 0 running, 1 converged or out of iterations, 2 breakdown
-  int32_t iters;
-  int32_t max_iters;
-  int32_t pad;
-};
+// ---------------------------------------------------------------- scalar steps
 
 __global__ void k_cg_init(CgState* st, const double* rr, double stop_rr, int32_t max_iters) {
   if (threadIdx.x == 0) {
@@ -227,56 +179,65 @@ struct DevMem {
   }
 };
 
-// Runs CG iterations in dtype T on vectors owned by the caller.
+// Runs CG iterations in dtype T on vectors owned by the caller.  With the
+// direction update folded into the operator, p alternates between p and p2:
+// iteration i reads the old direction from one and writes the new one to
+// the other.  Batches hold an even number of iterations, so the current
+// direction is back in p after every batch.
 template <class T>
 struct CgEngine {
   using S = Storage<T>;
   using E = typename S::E;
   using C = typename S::C;
+  static constexpr bool kFuse = kFuseDirection<T>;
 
   bs_ctx* ctx;
   hipStream_t st;
   int64_t m, n;
   double shift;
-  E *x, *r, *p, *Ap;
+  E *x, *r, *p, *p2, *Ap;  // p2 is used only when the direction update is fused
   CgState* state;
   double* rr_dev;  // scratch scalar
   Span sp;
-  int g_dot = 1, g_upd = 1;
+  Op7<T, true, kFuse> op;
+  int g_upd = 1, g_dir = 1;
   hipGraphExec_t exec = nullptr;
 
   ~CgEngine() {
     if (exec) (void)hipGraphExecDestroy(exec);
   }
 
-  void enqueue_iteration() {
-    hipLaunchKernelGGL((k_stencil<T, true>), dim3(g_dot), dim3(kBlock), 0, st, static_cast<int32_t>(m),
-                       static_cast<C>(6.0 + shift), static_cast<const E*>(p), Ap, ctx->partials,
-                       reinterpret_cast<const int32_t*>(&state->done));
-    hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g_dot, state);
+  void enqueue_iteration(int parity) {
+    E* p_old = (kFuse && parity) ? p2 : p;
+    E* p_cur = kFuse ? (parity ? p : p2) : p;
+    op.enqueue(st, shift, p_old, r, p_cur, Ap, ctx->partials, state);
+    hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, static_cast<int>(op.blocks),
+                       state);
     if (sp.vwidth == 1)
-      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p, r, Ap, sp, ctx->partials);
+      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p_cur, r, Ap, sp,
+                         ctx->partials);
     else
-      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p, r, Ap, sp,
+      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p_cur, r, Ap, sp,
                          ctx->partials);
     hipLaunchKernelGGL(k_after_update, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g_upd, state);
-    const unsigned int g_dir = static_cast<unsigned int>(grid_for(sp, 1, 1 << 30));
-    if (sp.vwidth == 1)
-      hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
-    else
-      hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+    if constexpr (!kFuse) {
+      if (sp.vwidth == 1)
+        hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+      else
+        hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+    }
   }
 
   bs_status prepare() {
-    sp = make_span<T>(n, {x, r, p, Ap});
-    const int64_t rows = m * m;
-    int64_t gd = (rows + kRowsPerBlock - 1) / kRowsPerBlock;
-    g_dot = static_cast<int>(gd < kMaxDotBlocks ? gd : kMaxDotBlocks);
+    sp = make_span<T>(n, {x, r, p, p2, Ap});
+    if (!op.prepare(m, ctx->device))
+      return fail(BS_ERR_INVALID_ARG, "cg: grid side %lld is too large", static_cast<long long>(m));
     g_upd = grid_for(sp, 4, kMaxReduceBlocks);
+    g_dir = grid_for(sp, 1, 1 << 30);
     // capture kBatch iterations into one graph
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager fallback
-    for (int i = 0; i < kBatch; ++i) enqueue_iteration();
+    for (int i = 0; i < kBatch; ++i) enqueue_iteration(i & 1);
     const hipError_t e1 = hipStreamEndCapture(st, &graph);
     if (e1 != hipSuccess || !graph) {
       (void)hipGetLastError();
@@ -299,7 +260,7 @@ struct CgEngine {
       if (exec) {
         s = check_hip(hipGraphLaunch(exec, st), "cg graph launch");
       } else {
-        for (int i = 0; i < kBatch; ++i) enqueue_iteration();
+        for (int i = 0; i < kBatch; ++i) enqueue_iteration(i & 1);
         s = check_launch("cg");
       }
       if (!s) s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
@@ -376,17 +337,19 @@ bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double
   if ((s = check_hip(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking), op))) return s;
   hipStream_t st = own.s;
   Workspace ws;
-  const size_t bytes = padded(n * 8) + 4 * padded(n * sizeof(E)) + 2 * padded(sizeof(CgState)) + 1024;
+  const int vecs = kFuseDirection<T> ? 5 : 4;  // rl, d, p, Ap (+ p2)
+  const size_t bytes = padded(n * 8) + vecs * padded(n * sizeof(E)) + 2 * padded(sizeof(CgState)) + 1024;
   if (!ws.alloc(bytes)) return fail(BS_ERR_ALLOC, "%s: cannot allocate %zu bytes of workspace", op, bytes);
   double* r64 = ws.take<double>(n);
   E* rl = ws.take<E>(n);
   E* d = ws.take<E>(n);
   E* p = ws.take<E>(n);
+  E* p2 = kFuseDirection<T> ? ws.take<E>(n) : nullptr;
   E* Ap = ws.take<E>(n);
   CgState* state = ws.take<CgState>(1);
   double* scal = ws.take<double>(8);
 
-  CgEngine<T> eng{ctx, st, m, n, shift, d, rl, p, Ap, state, scal};
+  CgEngine<T> eng{ctx, st, m, n, shift, d, rl, p, p2, Ap, state, scal};
   if ((s = eng.prepare())) return s;
 
   double bb = 0.0;
@@ -416,8 +379,10 @@ bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double
     double rr0 = 0.0;
     if ((s = check_hip(hipMemcpyAsync(&rr0, scal, 8, hipMemcpyDeviceToHost, st), op))) return s;
     if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+    // the last step need not go below what the outer target asks for
+    const double theta = std::max(inner_tol, 0.5 * std::sqrt(stop / rr));
     CgState fin{};
-    if ((s = eng.run(inner_tol * inner_tol * rr0, static_cast<int32_t>(max_inner), &fin))) return s;
+    if ((s = eng.run(theta * theta * rr0, static_cast<int32_t>(max_inner), &fin))) return s;
     inner += fin.iters;
     hipLaunchKernelGGL((k_add_scaled<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, x, nr, static_cast<const E*>(d), n);
     if ((s = check_launch(op))) return s;
@@ -484,7 +449,7 @@ extern "C" bs_status bs_cg_solve(bs_ctx* ctx, int64_t m, double shift, const dou
   double* Ap = ws.take<double>(n);
   CgState* state = ws.take<CgState>(1);
   double* scal = ws.take<double>(8);
-  CgEngine<double> eng{ctx, st, m, n, shift, d_x, r, p, Ap, state, scal};
+  CgEngine<double> eng{ctx, st, m, n, shift, d_x, r, p, nullptr, Ap, state, scal};
   if ((s = eng.prepare())) return s;
   double bb = 0.0;
   if ((s = bs_norm(ctx, BS_F64, n, d_b, nullptr, scal + 1, st))) return s;

@@ -44,12 +44,8 @@ template <> struct Storage<bf16> {
   static constexpr int V = 8;
   __device__ static float load(uint16_t x) { return __uint_as_float(static_cast<uint32_t>(x) << 16); }
   // binary32 -> bfloat16, round to nearest, ties to even; NaN stays NaN.
-  __device__ static uint16_t store(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x0040u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-  }
+  // gfx950 converts in one instruction (v_cvt_pk_bf16_f32).
+  __device__ static uint16_t store(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 };
 
 // Register packet of V storage elements: a native vector, so that a full

@@ -81,6 +81,21 @@ def test_cg_binary64_matches_algorithm_1(ctx, m):
     assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
+@pytest.mark.parametrize("k", [1, 2, 5, 16, 17, 33])
+def test_cg_iterate_after_k_steps(ctx, k):
+    # stops inside and across the batches of captured iterations, on both
+    # parities of the alternating direction buffers
+    m = 21
+    b = rhs(m, seed=5)
+    x = torch.zeros(m ** 3, dtype=torch.float64, device="cuda")
+    res = bs.bs_cg_solve(ctx, m, SHIFT, torch.from_numpy(b).cuda(), x, tol=1e-30, max_iter=k, check=False)
+    assert res["status"] == "BS_ERR_NO_CONVERGENCE" and res["iterations"] == k and res["restarts"] == 0
+    xo, it, rel = cg.cg(b, m, SHIFT, tol=1e-30, max_iter=k)
+    assert it == k
+    assert np.linalg.norm(to_host(x) - xo) <= 1e-13 * np.linalg.norm(xo)
+    assert abs(res["rel_residual"] - rel) <= 1e-9 * rel
+
+
 def test_cg_eigenvector_one_iteration(ctx):
     m = 17
     v = cg.sine_mode(m, 2, 3, 5)
