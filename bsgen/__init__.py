@@ -39,6 +39,7 @@ DEFAULT_SEED = 10917
 STREAM = {
     "x": 1, "y": 2, "p": 3, "r": 4, "Ap": 5, "w": 6, "scalars": 7,
     "perm": 8, "orient": 9, "b": 10, "xL": 11, "xG": 12,
+    "inst_E": 13, "inst_N": 14,
 }
 
 
@@ -145,6 +146,18 @@ def permutation(seed: int, n: int) -> np.ndarray:
 def orientations(seed: int, n: int) -> np.ndarray:
     """Orientation index in [0, 24) for each of n element slots."""
     return to_int(raw(seed, STREAM["orient"], 0, n), 24)
+
+
+def batch_instances(seed: int, n: int):
+    """Descriptors of n independent instances: element counts E_i and degrees N_i.
+
+    E_i = round(2**(12 u)) with u uniform [0, 1) (log-uniform on [1, 4096]),
+    N_i uniform in {2, ..., 8}.  Returns two int64 arrays.
+    """
+    u = to_unit(raw(seed, STREAM["inst_E"], 0, n))
+    E = np.rint(np.exp2(12.0 * u)).astype(np.int64)
+    N = 2 + to_int(raw(seed, STREAM["inst_N"], 0, n), 7)
+    return E, N
 
 
 def round_f32(x: np.ndarray) -> np.ndarray:

@@ -17,6 +17,8 @@ kernels I: Streaming Operations"):
             Fischer-Brown)
   cg     -- conjugate gradients (Algorithm 1) on a 7-point operator, and
             mixed-precision iterative refinement around it
+  batch  -- one step of the batched workload (the seven operations and one
+            CG iteration) on one box-mesh instance
 """
 
-from . import cg, mesh, model, ops  # noqa: F401
+from . import batch, cg, mesh, model, ops  # noqa: F401

@@ -87,6 +87,29 @@ def hex_map(K, N, perm=None, orient=None):
     return out.ravel()
 
 
+def box_side(E):
+    """Smallest m with m^3 >= E."""
+    m = 1
+    while m ** 3 < E:
+        m += 1
+    return m
+
+
+def box_map(E, N):
+    """Scatter ids of the first E elements of an m^3 box, m = box_side(E).
+
+    Elements are taken in lexicographic order (x fastest), all with the
+    identity orientation; local node (i, j, k) of element (qx, qy, qz) sits on
+    lattice point (N qx + i, N qy + j, N qz + k).  The global nodes are the
+    lattice points some element touches, numbered by rank in lexicographic
+    order (X fastest).  Returns (scatter_ids, n_global).
+    """
+    m = box_side(E)
+    ids = hex_map(m, N, np.arange(E, dtype=np.int64))  # lattice keys X + M(Y + M Z)
+    keys, inv = np.unique(ids, return_inverse=True)
+    return inv.astype(np.int64).ravel(), int(keys.size)
+
+
 def csr_inverse(scatter_ids, n_global):
     """CSR of Z^T without values: (row_starts, col_ids) (Section 5).
 
