@@ -241,14 +241,93 @@ bs_status bs_cg_solve(bs_ctx* ctx, int64_t m, double shift, const double* d_b, d
 /* Mixed-precision iterative refinement: binary64 residual r = b - A x,
  * ||r|| and update x += ||r|| d; the correction d solves A d = r/||r|| by CG
  * with vectors stored in `inner` (BS_F32 or BS_BF16; BS_F64 is accepted)
- * and binary32 arithmetic, to relative residual inner_tol or max_inner
- * iterations.  Stops when the true relative residual <= tol, after
+ * and binary32 arithmetic, to relative residual inner_tol (or the looser
+ * 0.5 tol ||b|| / ||r|| when that already meets the outer target) or
+ * max_inner iterations.  Stops when the true relative residual <= tol, after
  * max_outer refinement steps, or when the outer residual fails to halve over
  * three steps (BS_ERR_NO_CONVERGENCE, with res still filled in).  x starts
  * from its given value.  Allocates its workspace and synchronises `stream`. */
 bs_status bs_cg_ir_solve(bs_ctx* ctx, bs_dtype inner, int64_t m, double shift, const double* d_b, double* d_x,
                          double tol, double inner_tol, int64_t max_inner, int64_t max_outer, bs_cg_result* res,
                          void* stream);
+
+/* ---------------------------------------------------------------- batched instances
+ *
+ * Many independent instances of uneven size run as one batch (the launch
+ * latency + bandwidth model of Section 4: short vectors are dominated by the
+ * per-launch cost, so they are processed together).  Instance i has global
+ * vectors of n_global[i] entries and local vectors of n_local[i] entries;
+ * every vector argument is the concatenation of all instances' vectors in
+ * instance order (offsets from bs_batch_offsets).  The scatter map is the
+ * concatenation of each instance's map, with ids relative to that
+ * instance's own global nodes. */
+
+/* Box mesh of E elements at degree N: the first E elements of the m^3
+ * element box (m the smallest with m^3 >= E) in lexicographic order,
+ * identity orientation; local numbering as bs_mesh_hex_map; the global
+ * nodes are the lattice points the elements touch, numbered by rank in
+ * lattice order (X fastest).  map: host int32[E (N+1)^3]; *n_global gets
+ * the node count.  Host only. */
+bs_status bs_mesh_box_map_host(int64_t E, int N, int32_t* map, int64_t* n_global);
+
+typedef struct bs_batch bs_batch;
+
+/* Build a batch of n_inst instances from host arrays h_n_local[n_inst],
+ * h_n_global[n_inst] and the concatenated device map d_map (int32, sum of
+ * n_local entries).  Totals must stay below 2^31.  Allocates, synchronises
+ * `stream`; BS_ERR_INVALID_ARG if a map id lies outside its instance. */
+bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t* h_n_local, const int64_t* h_n_global,
+                          const int32_t* d_map, void* stream, bs_batch** out);
+bs_status bs_batch_destroy(bs_batch* batch);
+
+/* Totals, chunk counts (chunks of 2048 entries never cross an instance) and
+ * the workgroups of one persistent launch (0: the persistent form is not
+ * available).  Any output pointer may be NULL. */
+bs_status bs_batch_info(const bs_batch* batch, int64_t* n_local, int64_t* n_global, int64_t* n_chunks_local,
+                        int64_t* n_chunks_global, int32_t* persistent_blocks_f64);
+
+/* Host int64[n_inst + 1] prefix offsets of the local and global vectors. */
+bs_status bs_batch_offsets(const bs_batch* batch, int64_t* h_off_local, int64_t* h_off_global);
+
+/* Grid-barrier waits that gave up (always 0: no available form waits on a
+ * grid barrier). */
+bs_status bs_batch_barrier_timeouts(const bs_batch* batch, int32_t* count, void* stream);
+
+/* Concatenated vectors of one batch step (all of the step's dtype): global
+ * x, y, p, r, Ap (written, except that nothing writes x before reading it
+ * in the same phase), local xL, pL (written) and wL (read). */
+typedef struct {
+  void* x;
+  void* y;
+  void* p;
+  void* r;
+  void* Ap;
+  void* xL;
+  void* pL;
+  const void* wL;
+} bs_batch_vectors;
+
+enum {
+  BS_BATCH_PER_INSTANCE = 0, /* eleven launches per instance               */
+  BS_BATCH_PER_PHASE = 1,    /* eleven launches for the whole batch        */
+  BS_BATCH_PERSISTENT = 2    /* one launch; not available (BS_ERR_UNSUPPORTED) */
+};
+
+/* One step on every instance: the seven operations of Table 1 once each,
+ * then one CG iteration (Algorithm 1) with A = Z^T Z:
+ *   y = x;  y = alpha x + beta y;  norm = sum wL xL^2;  dot = x.y;
+ *   x += alpha p, r -= alpha Ap, rr = r.r;  xL = Z x;  y = Z^T xL;
+ *   pL = Z p;  Ap = Z^T pL;  pAp = p.Ap, a = rr/pAp;
+ *   x += a p, r -= a Ap, rr2 = r.r;  p = r + (rr2/rr) p.
+ * d_out: device binary64[n_inst * 8]; instance i gets norm, dot, rr, pAp, a,
+ * rr2, rr2/rr in slots 0..6 (slot 7 untouched).  Reductions are compensated
+ * per chunk and summed per instance in chunk order; the modes run the same
+ * code on the same chunks and give identical bits.  A per-phase step
+ * neither allocates nor synchronises (graph-capturable).
+ * BS_BATCH_PERSISTENT returns BS_ERR_UNSUPPORTED.  Calls on one batch must
+ * not overlap (they share its partial sums). */
+bs_status bs_batch_step(bs_ctx* ctx, bs_batch* batch, bs_dtype dtype, int mode, const bs_batch_vectors* v,
+                        double alpha, double beta, double* d_out, void* stream);
 
 #ifdef __cplusplus
 }

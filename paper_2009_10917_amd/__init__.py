@@ -59,7 +59,23 @@ PROTOTYPES = {
     "bs_stencil7": (_st, [_p, _i32, _i64, _d, _p, _p, _p]),
     "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
+    "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
+    "bs_batch_create": (_st, [_p, _i32, _p, _p, _p, _p, _p]),
+    "bs_batch_destroy": (_st, [_p]),
+    "bs_batch_info": (_st, [_p, _p, _p, _p, _p, _p]),
+    "bs_batch_offsets": (_st, [_p, _p, _p]),
+    "bs_batch_barrier_timeouts": (_st, [_p, _p, _p]),
+    "bs_batch_step": (_st, [_p, _p, _i32, _i32, _p, _d, _d, _p, _p]),
 }
+
+BS_BATCH_PER_INSTANCE, BS_BATCH_PER_PHASE, BS_BATCH_PERSISTENT = 0, 1, 2
+BATCH_GLOBAL = ("x", "y", "p", "r", "Ap")
+BATCH_LOCAL = ("xL", "pL", "wL")
+BATCH_SLOTS = ("norm", "dot", "rr", "pAp", "alpha", "rr2", "beta")
+
+
+class BatchVectors(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in BATCH_GLOBAL + BATCH_LOCAL]
 
 
 class CgResult(ctypes.Structure):
@@ -345,3 +361,78 @@ def bs_cg_ir_solve(ctx, inner_dtype, m, shift, b, x, tol=1e-10, inner_tol=1e-4, 
     out = res.as_dict()
     out["status"] = STATUS_NAMES.get(st, st)
     return out
+
+
+# ---------------------------------------------------------------- batched instances
+
+def bs_mesh_box_map_host(E, N):
+    """Box mesh of E elements at degree N: (int32 numpy map, n_global)."""
+    import numpy as np
+    out = np.empty(int(E) * (int(N) + 1) ** 3, dtype=np.int32)
+    ng = _i64()
+    _check(lib.bs_mesh_box_map_host(int(E), int(N), out.ctypes.data, ctypes.byref(ng)), "bs_mesh_box_map_host")
+    return out, ng.value
+
+
+class Batch:
+    """A bs_batch: instance sizes, offsets and the block-diagonal plan."""
+
+    def __init__(self, handle, n_inst):
+        self.handle = handle
+        self.n_inst = n_inst
+
+    def close(self):
+        if self.handle:
+            lib.bs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bs_batch_create(ctx, n_local, n_global, d_map, stream=None):
+    import numpy as np
+    nl = np.ascontiguousarray(n_local, dtype=np.int64)
+    ng = np.ascontiguousarray(n_global, dtype=np.int64)
+    if nl.size != ng.size or d_map.numel() != int(nl.sum()):
+        raise ValueError("bs_batch_create: sizes and map disagree")
+    h = _p()
+    _check(lib.bs_batch_create(ctx.handle, int(nl.size), nl.ctypes.data, ng.ctypes.data, _ptr(d_map),
+                               _stream(stream), ctypes.byref(h)), "bs_batch_create")
+    b = Batch(h.value, int(nl.size))
+    v = [_i64() for _ in range(4)] + [ctypes.c_int32()]
+    _check(lib.bs_batch_info(b.handle, *[ctypes.byref(a) for a in v]), "bs_batch_info")
+    b.n_local, b.n_global, b.n_chunks_local, b.n_chunks_global, b.persistent_blocks = (a.value for a in v)
+    b.off_local = np.empty(b.n_inst + 1, dtype=np.int64)
+    b.off_global = np.empty(b.n_inst + 1, dtype=np.int64)
+    _check(lib.bs_batch_offsets(b.handle, b.off_local.ctypes.data, b.off_global.ctypes.data), "bs_batch_offsets")
+    return b
+
+
+def bs_batch_barrier_timeouts(batch, stream=None):
+    c = ctypes.c_int32()
+    _check(lib.bs_batch_barrier_timeouts(batch.handle, ctypes.byref(c), _stream(stream)), "bs_batch_barrier_timeouts")
+    return c.value
+
+
+def bs_batch_step(ctx, batch, vectors, alpha, beta, out, mode=BS_BATCH_PER_PHASE, stream=None):
+    """One batch step; vectors maps x, y, p, r, Ap, xL, pL, wL to tensors of one dtype."""
+    dt = None
+    for k in BATCH_GLOBAL + BATCH_LOCAL:
+        t = vectors[k]
+        n = batch.n_global if k in BATCH_GLOBAL else batch.n_local
+        if t.numel() != n:
+            raise ValueError(f"bs_batch_step: {k} needs {n} entries")
+        d = _dtype_id(t)
+        if dt is not None and d != dt:
+            raise ValueError("bs_batch_step: vectors differ in dtype")
+        dt = d
+    _out(out, "bs_batch_step")
+    if out.numel() < 8 * batch.n_inst:
+        raise ValueError("bs_batch_step: out needs 8 doubles per instance")
+    v = BatchVectors(*[_ptr(vectors[k]) for k in BATCH_GLOBAL + BATCH_LOCAL])
+    _check(lib.bs_batch_step(ctx.handle, batch.handle, dt, int(mode), ctypes.byref(v), float(alpha), float(beta),
+                             _ptr(out), _stream(stream)), "bs_batch_step")
