@@ -46,7 +46,7 @@ def alg_bytes(n, nl, ng, s=8, idx=4):
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("bs_device.h", "bs_stream.hip"):
+    for f in ("bs_device.h", "bs_stream_ops.h", "bs_stream.hip"):
         with open(os.path.join(ROOT, "paper_2009_10917_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
