@@ -327,6 +327,60 @@ def mixed_cg(ctx, bs, bsgen, torch, seed, reps, m=225, shift=0.01, tol=1e-10):
     return out
 
 
+GATHER_TILE = 96  # lattice tile (points per side) of the gather's row order; fastest in a sweep at K = 128, N = 7
+
+
+def gather_sweep(args, np, torch, bs, bsgen):
+    """Gather on the K^3, N = 7 mesh in each row order: global order
+    (variant 1), the scatter tiles' visiting order (variant 0), and
+    lattice tiles of the given sizes (variant 0 after bs_gs_order_rows),
+    with and without the XCD renumbering.  --mesh chooses the element
+    layout: random (permuted and oriented, the benchmark's), orient
+    (lexicographic, oriented) or ident (lexicographic, unrotated).  One
+    JSON line per order; every output is checked against variant 1 bit for
+    bit."""
+    K, N, seed = args.K, 7, args.seed
+    E, M = K ** 3, K * N + 1
+    NL, NG = E * (N + 1) ** 3, M ** 3
+    ctx = bs.bs_ctx_create(0)
+    perm = orient = None
+    if args.mesh == "random":
+        perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
+    if args.mesh in ("random", "orient"):
+        orient = torch.from_numpy(bsgen.orientations(seed, E).astype(np.uint8)).cuda()
+    d_map = torch.empty(NL, dtype=torch.int32, device="cuda")
+    bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    del d_map, perm, orient
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    xL = torch.empty(NL, dtype=torch.float64, device="cuda")
+    bsgen.device_uniform(xL, seed, 11)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    alg = alg_bytes(0, NL, NG)["gather"]
+
+    def run(variant):
+        bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, variant)
+        ms = _time_calls(lambda: bs.bs_gather(ctx, plan, xL, xG), args.reps, torch)[0] * 1e3
+        return ms
+
+    def emit(order, variant, ms, same):
+        print(json.dumps({"gather_order": order, "variant": variant, "mesh": args.mesh, "K": K, "ms": round(ms, 4),
+                          "GB_s": round(alg / (ms * 1e-3) / 1e9, 1), "bit_equal_to_global_order": same}), flush=True)
+
+    ms = run(1)
+    ref = xG.clone()
+    emit("global", 1, ms, True)
+    ms = run(0)
+    emit("visiting", 0, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
+    for tile in [int(t) for t in args.gather_sweep.split(",") if t]:
+        bs.bs_gs_order_rows(plan, M, M, M, tile)
+        for v in (0, 4):
+            ms = run(v)
+            emit(f"lattice tiles {tile}", v, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
+    return 0
+
+
 BATCH_STREAMS = {"x": 1, "y": 2, "p": 3, "r": 4, "Ap": 5, "xL": 11, "pL": 12, "wL": 6}
 
 
@@ -420,6 +474,9 @@ def main():
                     help="only the mixed-precision CG time-to-solution (225^3 shifted 7-point operator)")
     ap.add_argument("--no-cg", action="store_true", help="skip the mixed-precision CG section")
     ap.add_argument("--batch-only", action="store_true", help="only the batched step over 1024 box-mesh instances")
+    ap.add_argument("--gather-sweep", default="", help="comma-separated lattice tile sizes: time the gather's row orders")
+    ap.add_argument("--mesh", default="random", choices=("random", "orient", "ident"),
+                    help="element layout for --gather-sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -440,6 +497,8 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
+    if args.gather_sweep:
+        return gather_sweep(args, np, torch, bs, bsgen)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -474,6 +533,10 @@ def main():
     bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
     plan = bs.bs_gs_create(ctx, d_map, n)
     del d_map, perm, orient
+    # plan set-up: rows of the gather in lattice tiles (same bits, better cache reuse)
+    M = K * N + 1
+    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE)
+    bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, 0)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     xL = vec(S["xL"], size=NL)
@@ -564,6 +627,7 @@ def main():
                                 f"weights uniform[0,1)); BS7 scatter and BS6 gather on the N=7, E={K}^3 hex mesh "
                                 f"(N_L={NL}, N_G={n}; elements permuted and oriented from the seed)"),
                    "n": n, "n_local": NL, "n_global": n, "mesh_K": K, "degree_N": N, "seed": args.seed,
+                   "gather_row_order": f"lattice tiles of {GATHER_TILE}^3 points",
                    "alpha": alpha, "beta": beta},
         "per_op": per_op,
         "roofline": roofline,

@@ -93,9 +93,10 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * reductions are further capped at 65536); variant (gather and scatter
  * only; other ops ignore it) is a kernel choice plus 4 to keep the
  * hardware's workgroup order instead of giving each XCD a contiguous range
- * of blocks.  Gather: 0 = rows grouped by the scatter tiles that hold their
- * copies (falls back to 1 when a degree exceeds 255), 1 = rows in global
- * order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
+ * of blocks.  Gather: 0 = rows in the plan's permuted order (by default
+ * grouped by the scatter tiles that hold their copies; bs_gs_order_rows
+ * replaces it with lattice tiles; falls back to 1 when a degree exceeds
+ * 255), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
  * entries visited in order of their smallest global id, values read in
  * ascending global id and turned around in LDS, 1 = the same tiles read in
  * local order, 2 = local order with `unroll` entries per thread.  The setting applies to every dtype.  Results of the bit-exact
@@ -173,6 +174,18 @@ bs_status bs_mesh_hex_map_host(int64_t K, int N, const int32_t* perm, const uint
 bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_local, int64_t n_global,
                        void* stream, bs_gs** out);
 bs_status bs_gs_destroy(bs_gs* gs);
+
+/* Replace the plan's permuted row order (gather variant 0) with a
+ * lattice-tiled one, for maps whose global ids are lattice points
+ * g = X + mx (Y + my Z) (mx*my*mz == n_global): rows in tile x tile x tile
+ * blocks of the lattice, blocks in lattice order (x fastest), ascending g
+ * within a block, rows without copies last.  A gather in this order keeps
+ * the elements around a block in cache while all their copies are added;
+ * the result is the same (each row is still summed in ascending local
+ * index).  Allocates and synchronises `stream`; BS_ERR_UNSUPPORTED when
+ * the plan has no permuted order (a degree above 255); on failure the
+ * previous order stays in place. */
+bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, void* stream);
 
 /* Sizes of a plan: local length, global length, unmasked local entries,
  * largest node degree.  Any output pointer may be NULL. */

@@ -60,6 +60,7 @@ PROTOTYPES = {
     "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
+    "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _p]),
     "bs_batch_create": (_st, [_p, _i32, _p, _p, _p, _p, _p]),
     "bs_batch_destroy": (_st, [_p]),
     "bs_batch_info": (_st, [_p, _p, _p, _p, _p, _p]),
@@ -301,6 +302,12 @@ def bs_gs_csr(plan, row_starts, col_ids, stream=None):
 def bs_gs_degree(plan, deg, stream=None):
     plan.expect(deg, plan.n_global, "bs_gs_degree")
     _check(lib.bs_gs_degree(plan.handle, _ptr(deg), _stream(stream)), "bs_gs_degree")
+
+
+def bs_gs_order_rows(plan, mx, my, mz, tile, stream=None):
+    """Lattice-tiled row order for gather variant 0 (global ids X + mx (Y + my Z))."""
+    _check(lib.bs_gs_order_rows(plan.handle, int(mx), int(my), int(mz), int(tile), _stream(stream)),
+           "bs_gs_order_rows")
 
 
 def bs_gs_weights(plan, wL, stream=None):

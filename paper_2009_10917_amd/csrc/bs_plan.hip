@@ -189,6 +189,23 @@ __global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t* __restrict__
   if (g >= 0) atomicMin(&key[g], static_cast<uint32_t>(tile_rank[l / kTile]));
 }
 
+// Row keys of a lattice-tiled order: global id g is lattice point
+// (g mod mx, (g / mx) mod my, g / (mx my)); its key is the index of its
+// tile x tile x tile block in lattice order (blocks along x fastest); rows
+// without copies get the largest key so that they come last.
+__global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restrict__ rs, int64_t n_global, int64_t mx,
+                                                         int64_t my, int64_t tile, int64_t ntx, int64_t nty,
+                                                         uint32_t* __restrict__ key) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (g >= n_global) return;
+  if (rs[g + 1] == rs[g]) {
+    key[g] = 0xffffffffu;
+    return;
+  }
+  const int64_t x = g % mx, y = (g / mx) % my, z = g / (mx * my);
+  key[g] = static_cast<uint32_t>(x / tile + ntx * (y / tile + nty * (z / tile)));
+}
+
 // Degrees of the rows in visiting order (byte and int copies).
 __global__ __launch_bounds__(kBlock) void k_perm_degrees(const int32_t* __restrict__ rows, int64_t n_nzrows,
                                                          const int32_t* __restrict__ rs, uint8_t* __restrict__ d8,
@@ -391,7 +408,14 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
 }
 
 // Rows in visiting order (needs the tile order and the CSR).
-void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows) {
+// Lattice description for a tiled gather order (global ids are lattice points).
+struct LatticeOrder {
+  int64_t mx, my, mz, tile;
+};
+
+// Rows with copies in a permuted order and the CSR in that order: by default
+// the visiting order of the scatter tiles, or (lat) lattice tiles.
+void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const LatticeOrder* lat = nullptr) {
   gs->has_perm = false;
   if (gs->max_degree > 255) return;  // degrees are stored in bytes
   const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
@@ -407,13 +431,20 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows) {
   B.need(prs, (nz + 1) * 4, "row starts");
   B.need(pcols, gs->n_unmasked * 4, "columns");
   if (!B.ok()) return;
-  if (nt > 0)
-    hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
-  if (nl > 0)
-    hipLaunchKernelGGL(k_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, rank.as<int32_t>(),
-                       rkey.as<uint32_t>());
+  if (lat) {
+    const int64_t ntx = (lat->mx + lat->tile - 1) / lat->tile, nty = (lat->my + lat->tile - 1) / lat->tile;
+    if (ng > 0)
+      hipLaunchKernelGGL(k_lattice_keys, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, gs->row_starts, ng, lat->mx,
+                         lat->my, lat->tile, ntx, nty, rkey.as<uint32_t>());
+  } else {
+    if (nt > 0)
+      hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
+    if (nl > 0)
+      hipLaunchKernelGGL(k_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, rank.as<int32_t>(),
+                         rkey.as<uint32_t>());
+  }
   B.launched();
   if (ng > 0) {
     uint32_t* k0 = rkey.as<uint32_t>();
@@ -515,6 +546,37 @@ extern "C" bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_l
   }
   *out = gs;
   return BS_OK;
+}
+
+extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, void* stream) {
+  const char* op = "bs_gs_order_rows";
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "%s: plan is NULL", op);
+  if (mx < 1 || my < 1 || mz < 1 || tile < 1 || mx * my * mz != gs->n_global)
+    return fail(BS_ERR_INVALID_ARG, "%s: need mx*my*mz == n_global and tile >= 1", op);
+  const int64_t ntiles = ((mx + tile - 1) / tile) * ((my + tile - 1) / tile) * ((mz + tile - 1) / tile);
+  if (ntiles >= 0xffffffffLL) return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
+  if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 255)", op);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(gs->device);
+  int32_t* old_rows = gs->perm_rows;
+  uint8_t* old_deg = gs->perm_deg;
+  int32_t* old_cols = gs->perm_cols;
+  int32_t* old_bstart = gs->perm_bstart;
+  int32_t* old_bnz0 = gs->perm_bnz0;
+  const int64_t zero_rows = gs->n_global - gs->n_nzrows;
+  Builder B{op, static_cast<hipStream_t>(stream)};
+  const LatticeOrder lat{mx, my, mz, tile};
+  build_gather_order(B, gs, zero_rows, &lat);
+  if (B.ok()) {
+    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_deg), static_cast<void*>(old_cols),
+                    static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
+      (void)hipFree(q);
+  } else {
+    gs->has_perm = true;  // the previous order is still in place
+  }
+  (void)hipSetDevice(prev);
+  return B.s;
 }
 
 extern "C" bs_status bs_gs_destroy(bs_gs* gs) {

@@ -220,3 +220,42 @@ def test_gather_scatter_deterministic(ctx):
         bs.bs_gather(ctx, plan, xL, xG)
         outs.append(bits(to_host(xG)))
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+@pytest.mark.parametrize("remap", [0, 4])
+@pytest.mark.parametrize("K,N,tile", [(6, 5, 1), (6, 5, 4), (7, 3, 7), (5, 7, 64), (9, 2, 5)])
+def test_gather_lattice_tiled_order(ctx, K, N, tile, remap):
+    # the tiled row order changes which rows a workgroup adds, not how a row is summed
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ids = device_map(K, N, 5)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    M = K * N + 1
+    bs.bs_gs_order_rows(plan, M, M, M, tile)
+    with_variant(ctx, 0 + remap)
+    xL = dev_uniform(NL, 11)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
+
+
+def test_gather_lattice_order_masked_and_errors(ctx):
+    K, N = 5, 4
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ids = device_map(K, N, 9)
+    ids = ids.copy()
+    ids[::7] = -1  # masked copies; some rows lose every copy
+    ids[ids == 17] = -1
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ids.astype(np.int32)).cuda(), NG)
+    M = K * N + 1
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_rows(plan, M, M, M + 1, 4)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_rows(plan, M, M, M, 0)
+    bs.bs_gs_order_rows(plan, M, M, M, 3)
+    with_variant(ctx, 0)
+    xL = dev_uniform(NL, 11)
+    xG = torch.full((NG,), 7.0, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
