@@ -294,16 +294,17 @@ bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t* h_n_local,
 bs_status bs_batch_destroy(bs_batch* batch);
 
 /* Totals, chunk counts (chunks of 2048 entries never cross an instance) and
- * the workgroups of one persistent launch (0: the persistent form is not
- * available).  Any output pointer may be NULL. */
+ * the workgroups of one persistent binary64 launch.  Any output pointer may
+ * be NULL. */
 bs_status bs_batch_info(const bs_batch* batch, int64_t* n_local, int64_t* n_global, int64_t* n_chunks_local,
                         int64_t* n_chunks_global, int32_t* persistent_blocks_f64);
 
 /* Host int64[n_inst + 1] prefix offsets of the local and global vectors. */
 bs_status bs_batch_offsets(const bs_batch* batch, int64_t* h_off_local, int64_t* h_off_global);
 
-/* Grid-barrier waits that gave up (always 0: no available form waits on a
- * grid barrier). */
+/* Nonzero if a wait of the persistent form ever outlived its limit (half a
+ * second); the form then stops early and its results are invalid, and
+ * later persistent steps on this batch do nothing.  Synchronises `stream`. */
 bs_status bs_batch_barrier_timeouts(const bs_batch* batch, int32_t* count, void* stream);
 
 /* Concatenated vectors of one batch step (all of the step's dtype): global
@@ -323,7 +324,7 @@ typedef struct {
 enum {
   BS_BATCH_PER_INSTANCE = 0, /* eleven launches per instance               */
   BS_BATCH_PER_PHASE = 1,    /* eleven launches for the whole batch        */
-  BS_BATCH_PERSISTENT = 2    /* one launch; not available (BS_ERR_UNSUPPORTED) */
+  BS_BATCH_PERSISTENT = 2    /* one launch, work claimed in dependency order */
 };
 
 /* One step on every instance: the seven operations of Table 1 once each,
@@ -335,10 +336,10 @@ enum {
  * d_out: device binary64[n_inst * 8]; instance i gets norm, dot, rr, pAp, a,
  * rr2, rr2/rr in slots 0..6 (slot 7 untouched).  Reductions are compensated
  * per chunk and summed per instance in chunk order; the modes run the same
- * code on the same chunks and give identical bits.  A per-phase step
- * neither allocates nor synchronises (graph-capturable).
- * BS_BATCH_PERSISTENT returns BS_ERR_UNSUPPORTED.  Calls on one batch must
- * not overlap (they share its partial sums). */
+ * code on the same chunks and give identical bits.  Per-phase and
+ * persistent steps neither allocate nor synchronise (graph-capturable).
+ * Calls on one batch must not overlap (they share its partial sums and the
+ * persistent form's schedule). */
 bs_status bs_batch_step(bs_ctx* ctx, bs_batch* batch, bs_dtype dtype, int mode, const bs_batch_vectors* v,
                         double alpha, double beta, double* d_out, void* stream);
 

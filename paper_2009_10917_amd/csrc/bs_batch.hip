@@ -21,19 +21,30 @@
 // alpha and beta are shared; a and b = rr2 / rr belong to each instance.
 //
 // Work is cut into chunks of 2048 consecutive elements that never cross an
-// instance.  A workgroup handles one chunk at a time (8 elements per
-// thread); reductions leave one compensated pair per chunk, and an
-// instance's value is the sum of its chunks' pairs in chunk order, formed by
-// one wave.  The steps are grouped into eleven intervals separated by the
-// data dependencies; the forms run the same interval code on the same
-// chunks, so they give identical bits:
-//   per instance  eleven launches per instance, each over its chunks;
-//   per phase     eleven launches in all, each over every chunk.
-// A per-phase step neither allocates nor synchronises, so a caller can
-// capture it in a HIP graph.  The persistent form (one launch, intervals
-// separated by grid barriers) is not offered: a grid barrier whose waiters
-// poll with agent-scope acquire loads did not complete on gfx950, and the
-// form returns BS_ERR_UNSUPPORTED until a barrier-free schedule replaces it.
+// instance, and chunks into items: up to 8 chunks of one instance in one
+// part of a phase (or one instance's final sum of a reduction).  The step's
+// phases are grouped into eleven intervals by data dependence; within an
+// interval no item depends on another.  Reductions leave one compensated
+// pair per chunk in a buffer of their own, and an instance's value is the
+// sum of its chunks' pairs in chunk order, formed by one wave.  Three forms
+// run the same item code on the same chunks, so they give identical bits:
+//   per instance  one launch per interval and instance (11 per instance),
+//                 one chunk per workgroup;
+//   per phase     one launch per interval for the whole batch, one chunk
+//                 per workgroup;
+//   persistent    one launch.  Workgroups claim items with an atomic ticket
+//                 in list order (intervals ascending); before an item of
+//                 interval k of instance i runs, its workgroup waits until
+//                 every interval k-1 item of instance i is done.  Those
+//                 items come earlier in the list, so they were claimed
+//                 earlier by running workgroups and the wait ends however
+//                 many workgroups are resident.  Waits poll with relaxed
+//                 loads; a wait longer than a wall-clock limit sets a sticky
+//                 abort flag that ends every workgroup, so the kernel always
+//                 finishes.  The last workgroup out resets the ticket and
+//                 the counters for the next launch.
+// Per-phase and persistent steps neither allocate nor synchronise, so a
+// caller can capture them in a HIP graph.
 
 #include <algorithm>
 #include <vector>
@@ -51,8 +62,19 @@ namespace {
 constexpr int kPer = 8;                    // elements per thread in a chunk
 constexpr int kChunk = kBlock * kPer;      // elements per chunk
 constexpr int kIntervals = 11;
+constexpr int kItemChunks = 8;             // chunks per item
+constexpr int kClaim = 8;                  // items per ticket of the persistent form
 constexpr int kSlots = 8;                  // output doubles per instance
 enum Slot { S_NORM = 0, S_DOT, S_RR, S_PAP, S_ALPHA, S_RR2, S_BETA };
+
+// Parts of the step; kInterval gives each part's interval, kTable whether it
+// runs over global chunks (0), local chunks (1) or finishes an instance (2).
+enum Part {
+  P_COPY, P_AXPY, P_NORM, P_DOT_XY, F_NORM, P_UPDATE_A, F_DOT, P_SCATTER, F_RR, P_GATHER, P_DOT_PAP, F_PAP,
+  P_UPDATE_B, F_RR2, P_DIRECTION, N_PARTS
+};
+constexpr int kInterval[N_PARTS] = {0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 6, 7, 8, 9, 10};
+constexpr int kTable[N_PARTS] = {0, 0, 1, 0, 2, 0, 2, 1, 2, 0, 0, 2, 0, 2, 0};
 
 template <class T> struct DtypeOf;
 template <> struct DtypeOf<double> { static constexpr bs_dtype v = BS_F64; };
@@ -65,6 +87,34 @@ struct Chunk {
   int32_t inst;
 };
 
+// One unit of work: chunks [c0, c1) of the part's table, all of instance
+// `inst` (or, for a finishing part, that instance's sum).
+struct Item {
+  int32_t part;
+  int32_t inst;
+  int32_t c0, c1;
+};
+
+// One chunk of a part of one instance (chunk -1: the instance's finish).
+struct Unit {
+  int32_t part;
+  int32_t inst;
+  int32_t chunk;
+  int32_t pad;
+};
+
+// Shared state of the persistent form.
+struct Sched {
+  unsigned int* ticket;     // next claim
+  unsigned int* exits;      // workgroups that have left
+  int* abort;               // sticky: a wait outlived the limit
+  unsigned int* done;       // [kIntervals][n_inst] items completed
+  const unsigned int* need; // [kIntervals][n_inst] items in all
+  int64_t n_items;
+  int32_t n_inst;
+  uint64_t wait_ticks;      // wall-clock limit of one wait
+};
+
 template <class T>
 struct Args {
   using E = typename Storage<T>::E;
@@ -73,15 +123,18 @@ struct Args {
   const E* wL;
   const Chunk* cg;  // chunks of the global vectors
   const Chunk* cl;  // chunks of the local vectors
-  int64_t g0, g1, l0, l1;  // chunk ranges to process
-  int32_t i0, i1;          // instance range to finish
+  const Item* items;
+  const Unit* units;
   const int64_t* fg;       // first global chunk of each instance [n_inst + 1]
   const int64_t* fl;       // first local chunk of each instance [n_inst + 1]
   const int32_t* map;      // scatter ids, shifted to the concatenated global vector
   const int32_t* rs;       // CSR of Z^T
   const int32_t* ci;
-  double* part_a;          // compensated pairs, one per chunk
-  double* part_b;
+  double* part_norm;       // compensated pairs per chunk, one buffer per reduction
+  double* part_dot;
+  double* part_rr;
+  double* part_pap;
+  double* part_rr2;
   double* out;             // [n_inst][kSlots]
   C alpha, beta;
 };
@@ -134,7 +187,7 @@ __device__ void ch_norm(const Args<T>& a, const Chunk& ch, int64_t c) {
     const C xk = S::load(a.xL[e]);
     dev::dw_acc(acc, S::load(a.wL[e]) * (xk * xk));
   });
-  put_pair(a.part_a, c, widen(acc));
+  put_pair(a.part_norm, c, widen(acc));
 }
 
 template <class T>
@@ -199,93 +252,197 @@ __device__ __forceinline__ double wave_sum(const double* part, int64_t c0, int64
   return acc.s + acc.c;
 }
 
-// ---------------------------------------------------------------- intervals
+// ---------------------------------------------------------------- items
 
-template <class T, class F>
-__device__ __forceinline__ void over_chunks(const Chunk* table, int64_t c0, int64_t c1, F f) {
-  for (int64_t c = c0 + blockIdx.x; c < c1; c += gridDim.x) f(table[c], c);
-}
-
-template <class F>
-__device__ __forceinline__ void over_instances(int32_t i0, int32_t i1, F f) {
-  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-  for (int64_t i = i0 + static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave; i < i1; i += waves)
-    f(static_cast<int32_t>(i));
-}
-
+// Finishing an instance's sum: wave 0 of the workgroup.
 template <class T>
-__device__ void interval(int k, const Args<T>& a) {
-  using C = typename Storage<T>::C;
-  switch (k) {
-    case 0:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t) { ch_copy(a, ch); });
+__device__ void run_finish(int part, int32_t i, const Args<T>& a) {
+  if (threadIdx.x >= kWave) return;
+  double* o = a.out + static_cast<int64_t>(i) * kSlots;
+  switch (part) {
+    case F_NORM: {
+      const double v = wave_sum(a.part_norm, a.fl[i], a.fl[i + 1]);
+      if (threadIdx.x == 0) o[S_NORM] = v;
       break;
-    case 1:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t) { ch_axpy(a, ch); });
-      over_chunks<T>(a.cl, a.l0, a.l1, [&](const Chunk& ch, int64_t c) { ch_norm(a, ch, c); });
+    }
+    case F_DOT: {
+      const double v = wave_sum(a.part_dot, a.fg[i], a.fg[i + 1]);
+      if (threadIdx.x == 0) o[S_DOT] = v;
       break;
-    case 2:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t c) { ch_dot<T>(a.x, a.y, a.part_b, ch, c); });
-      over_instances(a.i0, a.i1, [&](int32_t i) {
-        const double v = wave_sum(a.part_a, a.fl[i], a.fl[i + 1]);
-        if (threadIdx.x % kWave == 0) a.out[i * kSlots + S_NORM] = v;
-      });
+    }
+    case F_RR: {
+      const double v = wave_sum(a.part_rr, a.fg[i], a.fg[i + 1]);
+      if (threadIdx.x == 0) o[S_RR] = v;
       break;
-    case 3:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t c) { ch_update(a, a.alpha, a.part_a, ch, c); });
-      over_instances(a.i0, a.i1, [&](int32_t i) {
-        const double v = wave_sum(a.part_b, a.fg[i], a.fg[i + 1]);
-        if (threadIdx.x % kWave == 0) a.out[i * kSlots + S_DOT] = v;
-      });
+    }
+    case F_PAP: {
+      const double v = wave_sum(a.part_pap, a.fg[i], a.fg[i + 1]);
+      if (threadIdx.x == 0) {
+        o[S_PAP] = v;
+        o[S_ALPHA] = o[S_RR] / v;
+      }
       break;
-    case 4:
-      over_chunks<T>(a.cl, a.l0, a.l1, [&](const Chunk& ch, int64_t) { ch_scatter(a, a.x, a.xL, ch); });
-      over_chunks<T>(a.cl, a.l0, a.l1, [&](const Chunk& ch, int64_t) { ch_scatter(a, a.p, a.pL, ch); });
-      over_instances(a.i0, a.i1, [&](int32_t i) {
-        const double v = wave_sum(a.part_a, a.fg[i], a.fg[i + 1]);
-        if (threadIdx.x % kWave == 0) a.out[i * kSlots + S_RR] = v;
-      });
+    }
+    default: {  // F_RR2
+      const double v = wave_sum(a.part_rr2, a.fg[i], a.fg[i + 1]);
+      if (threadIdx.x == 0) {
+        o[S_RR2] = v;
+        o[S_BETA] = v / o[S_RR];
+      }
       break;
-    case 5:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t) { ch_gather(a, a.xL, a.y, ch); });
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t) { ch_gather(a, a.pL, a.Ap, ch); });
-      break;
-    case 6:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t c) { ch_dot<T>(a.p, a.Ap, a.part_b, ch, c); });
-      break;
-    case 7:
-      over_instances(a.i0, a.i1, [&](int32_t i) {
-        const double v = wave_sum(a.part_b, a.fg[i], a.fg[i + 1]);
-        if (threadIdx.x % kWave == 0) {
-          a.out[i * kSlots + S_PAP] = v;
-          a.out[i * kSlots + S_ALPHA] = a.out[i * kSlots + S_RR] / v;
-        }
-      });
-      break;
-    case 8:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t c) {
-        const C al = static_cast<C>(a.out[ch.inst * kSlots + S_ALPHA]);
-        ch_update(a, al, a.part_a, ch, c);
-      });
-      break;
-    case 9:
-      over_instances(a.i0, a.i1, [&](int32_t i) {
-        const double v = wave_sum(a.part_a, a.fg[i], a.fg[i + 1]);
-        if (threadIdx.x % kWave == 0) {
-          a.out[i * kSlots + S_RR2] = v;
-          a.out[i * kSlots + S_BETA] = v / a.out[i * kSlots + S_RR];
-        }
-      });
-      break;
-    default:
-      over_chunks<T>(a.cg, a.g0, a.g1, [&](const Chunk& ch, int64_t) { ch_direction(a, ch); });
-      break;
+    }
   }
 }
 
+// One chunk of a part, by the whole workgroup.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_interval(int k, Args<T> a) {
-  interval<T>(k, a);
+__device__ void run_chunk(int part, int32_t i, int32_t c, const Args<T>& a) {
+  using C = typename Storage<T>::C;
+  const Chunk ch = (kTable[part] == 0 ? a.cg : a.cl)[c];
+  switch (part) {
+    case P_COPY: ch_copy(a, ch); break;
+    case P_AXPY: ch_axpy(a, ch); break;
+    case P_NORM: ch_norm(a, ch, c); break;
+    case P_DOT_XY: ch_dot<T>(a.x, a.y, a.part_dot, ch, c); break;
+    case P_UPDATE_A: ch_update(a, a.alpha, a.part_rr, ch, c); break;
+    case P_SCATTER:
+      ch_scatter(a, a.x, a.xL, ch);
+      ch_scatter(a, a.p, a.pL, ch);
+      break;
+    case P_GATHER:
+      ch_gather(a, a.xL, a.y, ch);
+      ch_gather(a, a.pL, a.Ap, ch);
+      break;
+    case P_DOT_PAP: ch_dot<T>(a.p, a.Ap, a.part_pap, ch, c); break;
+    case P_UPDATE_B:
+      ch_update(a, static_cast<C>(a.out[static_cast<int64_t>(i) * kSlots + S_ALPHA]), a.part_rr2, ch, c);
+      break;
+    default: ch_direction(a, ch); break;
+  }
+}
+
+// One item: its chunks in order, or its instance's finish.
+template <class T>
+__device__ void run_item(const Item& it, const Args<T>& a) {
+  if (kTable[it.part] == 2) {
+    run_finish(it.part, it.inst, a);
+    return;
+  }
+  for (int32_t c = it.c0; c < it.c1; ++c) run_chunk(it.part, it.inst, c, a);
+}
+
+// Units [u0, u1): one chunk of an item, or one finish, per workgroup at a
+// time (per-instance and per-phase forms; the launch boundary orders the
+// intervals).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_units(int64_t u0, int64_t u1, Args<T> a) {
+  for (int64_t u = u0 + blockIdx.x; u < u1; u += gridDim.x) {
+    const Unit un = a.units[u];
+    if (un.chunk < 0)
+      run_finish(un.part, un.inst, a);
+    else
+      run_chunk(un.part, un.inst, un.chunk, a);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ unsigned int load_relaxed(const unsigned int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: wait until instance i has finished interval k - 1, counting
+// `local` items of that interval which this workgroup has run but not yet
+// published.  Returns false when the form has been aborted.
+__device__ bool wait_ready(const Sched& sc, int k, int32_t i, unsigned int local) {
+  if (k == 0) return __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  const int64_t slot = static_cast<int64_t>(k - 1) * sc.n_inst + i;
+  const unsigned int need = sc.need[slot] - local;
+  const uint64_t t0 = wall_clock64();
+  bool waited = false;
+  while (load_relaxed(sc.done + slot) < need) {
+    if (__hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (wall_clock64() - t0 > sc.wait_ticks) {
+      __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    waited = true;
+    __builtin_amdgcn_s_sleep(4);
+  }
+  // what the finished items of other workgroups wrote is visible from here on
+  if (waited || need > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// Each claim of kClaim consecutive items runs in list order; its completions
+// are published together after one release fence (an item may depend on an
+// earlier item of the same claim, whose writes this workgroup already sees).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_persistent(Args<T> a, Sched sc) {
+  __shared__ int64_t s_claim;
+  __shared__ int s_go;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const bool stop = __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      s_claim = stop ? sc.n_items
+                     : static_cast<int64_t>(__hip_atomic_fetch_add(sc.ticket, 1u, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT)) * kClaim;
+    }
+    __syncthreads();
+    const int64_t first = s_claim;
+    if (first >= sc.n_items) break;
+    const int64_t last = first + kClaim < sc.n_items ? first + kClaim : sc.n_items;
+    bool stop = false;
+    for (int64_t t = first; t < last; ++t) {
+      const Item it = a.items[t];
+      const int k = kInterval[it.part];
+      if (threadIdx.x == 0) {
+        unsigned int local = 0;  // earlier items of this claim that (k - 1, inst) is waiting for
+        for (int64_t u = first; u < t; ++u) {
+          const Item e = a.items[u];
+          local += (kInterval[e.part] == k - 1 && e.inst == it.inst) ? 1u : 0u;
+        }
+        s_go = wait_ready(sc, k, it.inst, local) ? 1 : 0;
+      }
+      __syncthreads();
+      if (!s_go) {
+        stop = true;
+        break;
+      }
+      run_item(it, a);
+      __syncthreads();  // every thread's writes of the item are complete
+    }
+    if (stop) break;
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      int64_t t = first;
+      while (t < last) {  // one increment per run of items with the same (interval, instance)
+        const Item it = a.items[t];
+        const int k = kInterval[it.part];
+        unsigned int n = 0;
+        while (t < last && kInterval[a.items[t].part] == k && a.items[t].inst == it.inst) {
+          ++n;
+          ++t;
+        }
+        __hip_atomic_fetch_add(sc.done + static_cast<int64_t>(k) * sc.n_inst + it.inst, n, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+  }
+  // the last workgroup out resets the schedule for the next launch
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    s_go = __hip_atomic_fetch_add(sc.exits, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_go) {
+    for (int64_t j = threadIdx.x; j < static_cast<int64_t>(kIntervals) * sc.n_inst; j += kBlock) sc.done[j] = 0;
+    if (threadIdx.x == 0) {
+      *sc.ticket = 0;
+      *sc.exits = 0;
+    }
+  }
 }
 
 }  // namespace
@@ -297,14 +454,23 @@ struct bs_batch {
   int device;
   int32_t n_inst;
   int64_t n_local, n_global;
-  std::vector<int64_t> off_local, off_global;    // [n_inst + 1]
+  std::vector<int64_t> off_local, off_global;      // [n_inst + 1]
   std::vector<int64_t> first_local, first_global;  // first chunk of each instance [n_inst + 1]
+  std::vector<int64_t> first_item;                 // [kIntervals * n_inst + 1]: items of (interval, instance)
   bs::Chunk* chunks_local;
   bs::Chunk* chunks_global;
+  bs::Item* items;
+  int64_t n_items;
+  bs::Unit* units;
+  std::vector<int64_t> first_unit;                 // [n_items + 1]
   int64_t* d_first_local;
   int64_t* d_first_global;
   bs_gs* plan;
-  double* partials;  // two buffers of 2 * max(chunks) doubles
+  double* partials;  // one buffer per reduction: 2 pairs-worth per chunk of its table
+  unsigned int* sched;  // ticket, exits, abort, then done[kIntervals * n_inst]
+  unsigned int* need;   // [kIntervals * n_inst]
+  int resident[3];      // workgroups of one persistent launch per dtype
+  uint64_t wait_ticks;
 };
 
 using namespace bs;
@@ -315,14 +481,18 @@ void free_batch(bs_batch* b) {
   if (!b) return;
   (void)hipFree(b->chunks_local);
   (void)hipFree(b->chunks_global);
+  (void)hipFree(b->items);
+  (void)hipFree(b->units);
   (void)hipFree(b->d_first_local);
   (void)hipFree(b->d_first_global);
   (void)hipFree(b->partials);
+  (void)hipFree(b->sched);
+  (void)hipFree(b->need);
   if (b->plan) (void)bs_gs_destroy(b->plan);
   delete b;
 }
 
-// chunks of the concatenation with per-instance lengths len[i]
+// chunks of the concatenation with per-instance lengths from the offsets
 void make_chunks(const std::vector<int64_t>& off, std::vector<Chunk>& chunks, std::vector<int64_t>& first) {
   const size_t n = off.size() - 1;
   first.assign(n + 1, 0);
@@ -335,6 +505,34 @@ void make_chunks(const std::vector<int64_t>& off, std::vector<Chunk>& chunks, st
     }
   }
   first[n] = static_cast<int64_t>(chunks.size());
+}
+
+// The item list, sorted by (interval, instance, part), and the number of
+// items of every (interval, instance).
+void make_items(const bs_batch* b, std::vector<Item>& items, std::vector<int64_t>& first,
+                std::vector<unsigned int>& need) {
+  const int32_t n = b->n_inst;
+  items.clear();
+  first.assign(static_cast<size_t>(kIntervals) * n + 1, 0);
+  need.assign(static_cast<size_t>(kIntervals) * n, 0);
+  for (int k = 0; k < kIntervals; ++k) {
+    for (int32_t i = 0; i < n; ++i) {
+      first[static_cast<size_t>(k) * n + i] = static_cast<int64_t>(items.size());
+      for (int p = 0; p < N_PARTS; ++p) {
+        if (kInterval[p] != k) continue;
+        if (kTable[p] == 2) {
+          items.push_back(Item{p, i, 0, 0});
+          continue;
+        }
+        const std::vector<int64_t>& f = kTable[p] == 0 ? b->first_global : b->first_local;
+        for (int64_t c = f[i]; c < f[i + 1]; c += kItemChunks)
+          items.push_back(Item{p, i, static_cast<int32_t>(c), static_cast<int32_t>(std::min<int64_t>(c + kItemChunks, f[i + 1]))});
+      }
+      need[static_cast<size_t>(k) * n + i] =
+          static_cast<unsigned int>(items.size() - first[static_cast<size_t>(k) * n + i]);
+    }
+  }
+  first.back() = static_cast<int64_t>(items.size());
 }
 
 __global__ void k_shift_map(const int32_t* in, int32_t* out, const Chunk* chunks, int64_t n_chunks,
@@ -356,8 +554,19 @@ __global__ void k_shift_map(const int32_t* in, int32_t* out, const Chunk* chunks
 }
 
 template <class T>
-bs_status run_step(bs_ctx* ctx, bs_batch* b, int mode, const bs_batch_vectors* v, double alpha, double beta,
-                   double* d_out, hipStream_t st) {
+int resident_blocks(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<T>, kBlock, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return per_cu * cus;
+}
+
+template <class T>
+bs_status run_step(bs_batch* b, int mode, const bs_batch_vectors* v, double alpha, double beta, double* d_out,
+                   hipStream_t st) {
   using E = typename Storage<T>::E;
   using C = typename Storage<T>::C;
   Args<T> a{};
@@ -371,48 +580,55 @@ bs_status run_step(bs_ctx* ctx, bs_batch* b, int mode, const bs_batch_vectors* v
   a.wL = static_cast<const E*>(v->wL);
   a.cg = b->chunks_global;
   a.cl = b->chunks_local;
+  a.items = b->items;
+  a.units = b->units;
   a.fg = b->d_first_global;
   a.fl = b->d_first_local;
   a.map = b->plan->map;
   a.rs = b->plan->row_starts;
   a.ci = b->plan->col_ids;
-  const int64_t nch = std::max(b->first_global.back(), b->first_local.back());
-  a.part_a = b->partials;
-  a.part_b = b->partials + 2 * nch;
+  const int64_t ncl = b->first_local.back(), ncg = b->first_global.back();
+  a.part_norm = b->partials;
+  a.part_dot = a.part_norm + 2 * ncl;
+  a.part_rr = a.part_dot + 2 * ncg;
+  a.part_pap = a.part_rr + 2 * ncg;
+  a.part_rr2 = a.part_pap + 2 * ncg;
   a.out = d_out;
   a.alpha = static_cast<C>(alpha);
   a.beta = static_cast<C>(beta);
-  (void)ctx;
-  auto grid_of = [](int64_t g, int64_t l, int64_t inst) {
-    int64_t n = std::max(g, l);
-    n = std::max(n, (inst + kBlock / kWave - 1) / (kBlock / kWave));
-    return static_cast<unsigned int>(std::max<int64_t>(1, std::min<int64_t>(n, 1 << 20)));
+  const int32_t n = b->n_inst;
+  // units of items [i0, i1)
+  auto launch = [&](int64_t i0, int64_t i1) {
+    const int64_t u0 = b->first_unit[i0], u1 = b->first_unit[i1];
+    if (u1 <= u0) return;
+    const unsigned int grid = static_cast<unsigned int>(std::min<int64_t>(u1 - u0, 1 << 20));
+    hipLaunchKernelGGL(k_units<T>, dim3(grid), dim3(kBlock), 0, st, u0, u1, a);
   };
   if (mode == BS_BATCH_PER_INSTANCE) {
-    for (int32_t i = 0; i < b->n_inst; ++i) {
-      a.g0 = b->first_global[i];
-      a.g1 = b->first_global[i + 1];
-      a.l0 = b->first_local[i];
-      a.l1 = b->first_local[i + 1];
-      a.i0 = i;
-      a.i1 = i + 1;
-      const unsigned int grid = grid_of(a.g1 - a.g0, a.l1 - a.l0, 1);
-      for (int k = 0; k < kIntervals; ++k) hipLaunchKernelGGL(k_interval<T>, dim3(grid), dim3(kBlock), 0, st, k, a);
-    }
+    for (int32_t i = 0; i < n; ++i)
+      for (int k = 0; k < kIntervals; ++k)
+        launch(b->first_item[static_cast<size_t>(k) * n + i], b->first_item[static_cast<size_t>(k) * n + i + 1]);
     return check_launch("bs_batch_step");
   }
-  a.g0 = 0;
-  a.g1 = b->first_global.back();
-  a.l0 = 0;
-  a.l1 = b->first_local.back();
-  a.i0 = 0;
-  a.i1 = b->n_inst;
   if (mode == BS_BATCH_PER_PHASE) {
-    const unsigned int grid = grid_of(a.g1, a.l1, b->n_inst);
-    for (int k = 0; k < kIntervals; ++k) hipLaunchKernelGGL(k_interval<T>, dim3(grid), dim3(kBlock), 0, st, k, a);
+    for (int k = 0; k < kIntervals; ++k)
+      launch(b->first_item[static_cast<size_t>(k) * n], b->first_item[static_cast<size_t>(k + 1) * n]);
     return check_launch("bs_batch_step");
   }
-  return fail(BS_ERR_UNSUPPORTED, "bs_batch_step: the persistent form is not available");
+  Sched sc{};
+  sc.ticket = b->sched;
+  sc.exits = b->sched + 1;
+  sc.abort = reinterpret_cast<int*>(b->sched + 2);
+  sc.done = b->sched + 4;
+  sc.need = b->need;
+  sc.n_items = b->n_items;
+  sc.n_inst = n;
+  sc.wait_ticks = b->wait_ticks;
+  const int dt = static_cast<int>(DtypeOf<T>::v);
+  const int64_t claims = (b->n_items + kClaim - 1) / kClaim;
+  const unsigned int grid = static_cast<unsigned int>(std::max<int64_t>(1, std::min<int64_t>(b->resident[dt], claims)));
+  hipLaunchKernelGGL(k_persistent<T>, dim3(grid), dim3(kBlock), 0, st, a, sc);
+  return check_launch("bs_batch_step");
 }
 
 }  // namespace
@@ -480,7 +696,27 @@ extern "C" bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t*
   make_chunks(b->off_local, cl, b->first_local);
   make_chunks(b->off_global, cgl, b->first_global);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t nch = std::max<int64_t>(cl.size(), cgl.size());
+  std::vector<Item> items;
+  std::vector<unsigned int> need;
+  make_items(b, items, b->first_item, need);
+  b->n_items = static_cast<int64_t>(items.size());
+  if (b->n_items >= (int64_t(kClaim) << 31)) {
+    delete b;
+    return fail(BS_ERR_INVALID_ARG, "%s: too many work items", op);
+  }
+  std::vector<Unit> units;
+  b->first_unit.assign(items.size() + 1, 0);
+  for (size_t t = 0; t < items.size(); ++t) {
+    b->first_unit[t] = static_cast<int64_t>(units.size());
+    const Item& it = items[t];
+    if (kTable[it.part] == 2)
+      units.push_back(Unit{it.part, it.inst, -1, 0});
+    else
+      for (int32_t c = it.c0; c < it.c1; ++c) units.push_back(Unit{it.part, it.inst, c, 0});
+  }
+  b->first_unit.back() = static_cast<int64_t>(units.size());
+  const size_t n_sched = 4 + static_cast<size_t>(kIntervals) * n_inst;
+  const size_t n_part = 2 * cl.size() + 8 * cgl.size();
   int32_t* shifted = nullptr;
   int64_t* d_off_global = nullptr;
   int* bad = nullptr;
@@ -489,7 +725,11 @@ extern "C" bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t*
             alloc(reinterpret_cast<void**>(&b->chunks_global), cgl.size() * sizeof(Chunk)) &&
             alloc(reinterpret_cast<void**>(&b->d_first_local), (n_inst + 1) * sizeof(int64_t)) &&
             alloc(reinterpret_cast<void**>(&b->d_first_global), (n_inst + 1) * sizeof(int64_t)) &&
-            alloc(reinterpret_cast<void**>(&b->partials), 4 * nch * sizeof(double)) &&
+            alloc(reinterpret_cast<void**>(&b->partials), n_part * sizeof(double)) &&
+            alloc(reinterpret_cast<void**>(&b->items), items.size() * sizeof(Item)) &&
+            alloc(reinterpret_cast<void**>(&b->units), units.size() * sizeof(Unit)) &&
+            alloc(reinterpret_cast<void**>(&b->sched), n_sched * sizeof(unsigned int)) &&
+            alloc(reinterpret_cast<void**>(&b->need), need.size() * sizeof(unsigned int)) &&
             alloc(reinterpret_cast<void**>(&shifted), b->n_local * sizeof(int32_t)) &&
             alloc(reinterpret_cast<void**>(&d_off_global), (n_inst + 1) * sizeof(int64_t)) &&
             alloc(reinterpret_cast<void**>(&bad), sizeof(int));
@@ -505,6 +745,10 @@ extern "C" bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t*
   if (!s) s = check_hip(hipMemcpyAsync(b->d_first_local, b->first_local.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), op);
   if (!s) s = check_hip(hipMemcpyAsync(b->d_first_global, b->first_global.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), op);
   if (!s) s = check_hip(hipMemcpyAsync(d_off_global, b->off_global.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st), op);
+  if (!s) s = check_hip(hipMemcpyAsync(b->items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, st), op);
+  if (!s) s = check_hip(hipMemcpyAsync(b->units, units.data(), units.size() * sizeof(Unit), hipMemcpyHostToDevice, st), op);
+  if (!s) s = check_hip(hipMemcpyAsync(b->need, need.data(), need.size() * sizeof(unsigned int), hipMemcpyHostToDevice, st), op);
+  if (!s) s = check_hip(hipMemsetAsync(b->sched, 0, n_sched * sizeof(unsigned int), st), op);
   if (!s) s = check_hip(hipMemsetAsync(bad, 0, sizeof(int), st), op);
   if (!s) {
     const unsigned int grid = static_cast<unsigned int>(std::min<int64_t>(static_cast<int64_t>(cl.size()), 65536));
@@ -524,6 +768,15 @@ extern "C" bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t*
     free_batch(b);
     return s;
   }
+  b->resident[BS_F64] = resident_blocks<double>(b->device);
+  b->resident[BS_F32] = resident_blocks<float>(b->device);
+  b->resident[BS_BF16] = resident_blocks<dev::bf16>(b->device);
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess || khz <= 0) {
+    (void)hipGetLastError();
+    khz = 100000;  // 100 MHz
+  }
+  b->wait_ticks = static_cast<uint64_t>(khz) * 500;  // half a second
   *out = b;
   return BS_OK;
 }
@@ -540,7 +793,7 @@ extern "C" bs_status bs_batch_info(const bs_batch* b, int64_t* n_local, int64_t*
   if (n_global) *n_global = b->n_global;
   if (n_chunks_local) *n_chunks_local = b->first_local.back();
   if (n_chunks_global) *n_chunks_global = b->first_global.back();
-  if (persistent_blocks_f64) *persistent_blocks_f64 = 0;
+  if (persistent_blocks_f64) *persistent_blocks_f64 = b->resident[BS_F64];
   return BS_OK;
 }
 
@@ -553,9 +806,11 @@ extern "C" bs_status bs_batch_offsets(const bs_batch* b, int64_t* h_off_local, i
 
 extern "C" bs_status bs_batch_barrier_timeouts(const bs_batch* b, int32_t* count, void* stream) {
   if (!b || !count) return fail(BS_ERR_INVALID_ARG, "bs_batch_barrier_timeouts: NULL argument");
-  (void)stream;
-  *count = 0;  // no form waits on a grid barrier
-  return BS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bs_status s = check_hip(hipMemcpyAsync(count, b->sched + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                          "bs_batch_barrier_timeouts");
+  if (!s) s = check_hip(hipStreamSynchronize(st), "bs_batch_barrier_timeouts");
+  return s;
 }
 
 extern "C" bs_status bs_batch_step(bs_ctx* ctx, bs_batch* b, bs_dtype dtype, int mode, const bs_batch_vectors* v,
@@ -575,9 +830,9 @@ extern "C" bs_status bs_batch_step(bs_ctx* ctx, bs_batch* b, bs_dtype dtype, int
   if (!aligned_to(d_out, 8)) return fail(BS_ERR_INVALID_ARG, "%s: misaligned output", op);
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {
-    case BS_F64: return run_step<double>(ctx, b, mode, v, alpha, beta, d_out, st);
-    case BS_F32: return run_step<float>(ctx, b, mode, v, alpha, beta, d_out, st);
-    case BS_BF16: return run_step<dev::bf16>(ctx, b, mode, v, alpha, beta, d_out, st);
+    case BS_F64: return run_step<double>(b, mode, v, alpha, beta, d_out, st);
+    case BS_F32: return run_step<float>(b, mode, v, alpha, beta, d_out, st);
+    case BS_BF16: return run_step<dev::bf16>(b, mode, v, alpha, beta, d_out, st);
   }
   return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype", op);
 }

@@ -1,9 +1,9 @@
 """GPU parity of the batched step (many box-mesh instances in one batch).
 
-The forms (per-instance launches, per-phase launches) run the same code on
-the same chunks and must agree bit for bit.  The persistent form (one launch
-with grid barriers) is switched off: its barrier did not complete on the
-device, and its tests are skipped until a barrier-free schedule replaces it.  Against the oracle's step, instance by instance: vectors that do
+The three forms (per-instance launches, per-phase launches, one persistent
+launch that claims work items in dependency order) run the same code on the
+same chunks and must agree bit for bit; the persistent form's waits must
+never have run into their time limit.  Against the oracle's step, instance by instance: vectors that do
 not depend on a reduction (y, xL, pL, Ap, and x after step 5) are bit-exact
 in binary64; reductions are within 1e-14 relative of the exact sums; x, r
 and p after the CG iteration carry the rounding of a = rr/pAp and
@@ -73,44 +73,34 @@ def bits(t):
     return t.view(torch.int64 if t.dtype == torch.float64 else torch.int32).cpu()
 
 
-PERSISTENT_OFF = ("persistent form switched off: its grid barrier (agent-scope acquire polling) did not "
-                  "complete on the device; kept skipped until a barrier-free schedule replaces it")
-
-
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_forms_agree_bit_for_bit(ctx, small, dtype):
     b = small[0]
     v0 = inputs(b, dtype)
-    res = [run(ctx, b, v0, m) for m in (0, 1)]
+    res = [run(ctx, b, v0, m) for m in (0, 1, 2)]
     for v, out in res[1:]:
         assert torch.equal(out.view(torch.int64), res[0][1].view(torch.int64))
         for k in v:
             assert torch.equal(bits(v[k]), bits(res[0][0][k])), k
-
-
-@pytest.mark.skip(reason=PERSISTENT_OFF)
-def test_persistent_form_agrees(ctx, small):
-    b = small[0]
-    v0 = inputs(b)
-    ref, out_ref = run(ctx, b, v0, bs.BS_BATCH_PER_PHASE)
-    v, out = run(ctx, b, v0, bs.BS_BATCH_PERSISTENT)
-    assert torch.equal(out.view(torch.int64), out_ref.view(torch.int64))
     assert bs.bs_batch_barrier_timeouts(b) == 0
 
 
-def test_persistent_form_reports_unsupported(ctx, small):
+def test_persistent_form_repeats(ctx, small):
+    # the schedule resets itself at the end of each launch
     b = small[0]
-    v = inputs(b)
-    out = torch.zeros(8 * b.n_inst, dtype=torch.float64, device="cuda")
-    with pytest.raises(bs.BSError) as e:
-        bs.bs_batch_step(ctx, b, v, ALPHA, BETA, out, bs.BS_BATCH_PERSISTENT)
-    assert e.value.status == 2
+    v0 = inputs(b)
+    ref, out_ref = run(ctx, b, v0, bs.BS_BATCH_PER_PHASE)
+    for _ in range(3):
+        v, out = run(ctx, b, v0, bs.BS_BATCH_PERSISTENT)
+        assert torch.equal(out.view(torch.int64), out_ref.view(torch.int64))
+        assert torch.equal(bits(v["p"]), bits(ref["p"]))
+    assert bs.bs_batch_barrier_timeouts(b) == 0
 
 
 def test_binary64_matches_oracle(ctx, small):
     b, maps, ng = small
     v0 = inputs(b)
-    v, out = run(ctx, b, v0, bs.BS_BATCH_PER_INSTANCE)
+    v, out = run(ctx, b, v0, bs.BS_BATCH_PERSISTENT)
     h0 = {k: to_host(t) for k, t in v0.items()}
     hv = {k: to_host(t) for k, t in v.items()}
     ho = to_host(out).reshape(-1, 8)
@@ -154,8 +144,7 @@ def test_binary32_within_bounds(ctx, small):
             assert abs(ho[i, j] - sc[name]) <= bound * 2.0 ** -24 * abs(sc[name]), (i, name)
 
 
-@pytest.mark.parametrize("mode", [bs.BS_BATCH_PER_PHASE,
-                                  pytest.param(bs.BS_BATCH_PERSISTENT, marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
+@pytest.mark.parametrize("mode", [bs.BS_BATCH_PER_PHASE, bs.BS_BATCH_PERSISTENT])
 def test_graph_replays_match_eager(ctx, small, mode):
     b = small[0]
     v0 = inputs(b)
@@ -181,6 +170,7 @@ def test_graph_replays_match_eager(ctx, small, mode):
         for k in v:
             assert torch.equal(bits(v[k]), bits(eager[k])), (rep, k)
         _ = torch.ones(1000, device="cuda").sum()  # eager work between replays
+    assert bs.bs_batch_barrier_timeouts(b) == 0
 
 
 def test_full_descriptor_set_builds_and_runs(ctx):
@@ -189,7 +179,10 @@ def test_full_descriptor_set_builds_and_runs(ctx):
     b, maps, ng = build(ctx, E, N)
     assert 1.2e8 < b.n_local < 1.7e8
     v0 = inputs(b)
-    v, out = run(ctx, b, v0, bs.BS_BATCH_PER_PHASE)
+    v, out = run(ctx, b, v0, bs.BS_BATCH_PERSISTENT)
+    v1, out1 = run(ctx, b, v0, bs.BS_BATCH_PER_PHASE)
+    assert torch.equal(out.view(torch.int64), out1.view(torch.int64))
+    assert bs.bs_batch_barrier_timeouts(b) == 0
     ho = to_host(out).reshape(-1, 8)
     for i in (0, 511, 1023, int(np.argmax(E * (N + 1) ** 3))):
         gs = slice(b.off_global[i], b.off_global[i + 1])
