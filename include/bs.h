@@ -104,8 +104,33 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * through the order of their compensated additions.  Defaults: unroll 1
  * and one-pass grids for element-wise operations and gather/scatter;
  * norm and dot unroll 8 with 4096 workgroups; cg_update unroll 4 with
- * 65536 workgroups; gather and scatter variant 1. */
+ * 65536 workgroups; gather and scatter variant 1 (a loaded tune table
+ * replaces them, see below). */
 bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap, int variant);
+
+/* Tune entries by length.  Each (op, dtype) holds up to 8 entries; entry k
+ * applies to lengths n >= n_min[k] up to the next entry (gather and scatter
+ * look up the plan's local length).  bs_ctx_set_tune replaces them with one
+ * entry for every dtype and length; bs_ctx_set_tune_entry inserts or
+ * replaces the entry of one (op, dtype, n_min); bs_ctx_tune_for reports
+ * the entry used for length n; bs_ctx_get_tune reports the n_min = 0 one.
+ *
+ * bs_ctx_load_tune reads a text table, one entry per line:
+ *     op dtype n_min unroll grid_cap variant      (# starts a comment)
+ * with op in copy, axpy, norm, dot, cg_update, gather, scatter and dtype in
+ * f64, f32, bf16.  Every (op, dtype) the table names gets exactly the
+ * table's entries (which must include n_min 0); the others keep theirs.
+ * Nothing is applied if any line is malformed (BS_ERR_INVALID_ARG, with the
+ * line in bs_last_error).  *n_entries (may be NULL) gets the count.
+ * bs_ctx_create loads the table that the environment variable BS_TUNE_FILE
+ * names ("none": built-in defaults), else tune_gfx950.txt beside the
+ * library if it exists (the autotuner's output), and fails if that table
+ * is malformed. */
+bs_status bs_ctx_set_tune_entry(bs_ctx* ctx, int op, bs_dtype dtype, int64_t n_min, int unroll, int grid_cap,
+                                int variant);
+bs_status bs_ctx_tune_for(const bs_ctx* ctx, int op, bs_dtype dtype, int64_t n, int* unroll, int* grid_cap,
+                          int* variant);
+bs_status bs_ctx_load_tune(bs_ctx* ctx, const char* path, int* n_entries);
 bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap,
                           int* variant);
 

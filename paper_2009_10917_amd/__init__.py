@@ -61,6 +61,9 @@ PROTOTYPES = {
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
     "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _p]),
+    "bs_ctx_set_tune_entry": (_st, [_p, _i32, _i32, _i64, _i32, _i32, _i32]),
+    "bs_ctx_tune_for": (_st, [_p, _i32, _i32, _i64, _p, _p, _p]),
+    "bs_ctx_load_tune": (_st, [_p, ctypes.c_char_p, _p]),
     "bs_batch_create": (_st, [_p, _i32, _p, _p, _p, _p, _p]),
     "bs_batch_destroy": (_st, [_p]),
     "bs_batch_info": (_st, [_p, _p, _p, _p, _p, _p]),
@@ -443,3 +446,27 @@ def bs_batch_step(ctx, batch, vectors, alpha, beta, out, mode=BS_BATCH_PER_PHASE
     v = BatchVectors(*[_ptr(vectors[k]) for k in BATCH_GLOBAL + BATCH_LOCAL])
     _check(lib.bs_batch_step(ctx.handle, batch.handle, dt, int(mode), ctypes.byref(v), float(alpha), float(beta),
                              _ptr(out), _stream(stream)), "bs_batch_step")
+
+
+# ---------------------------------------------------------------- tune tables
+
+def _op_id(op):
+    return OP_IDS[op] if isinstance(op, str) else int(op)
+
+
+def bs_ctx_set_tune_entry(ctx, op, n_min, unroll, grid_cap, variant=0, dtype=BS_F64):
+    _check(lib.bs_ctx_set_tune_entry(ctx.handle, _op_id(op), int(dtype), int(n_min), int(unroll), int(grid_cap),
+                                     int(variant)), "bs_ctx_set_tune_entry")
+
+
+def bs_ctx_tune_for(ctx, op, n, dtype=BS_F64):
+    v = [ctypes.c_int() for _ in range(3)]
+    _check(lib.bs_ctx_tune_for(ctx.handle, _op_id(op), int(dtype), int(n), *[ctypes.byref(a) for a in v]),
+           "bs_ctx_tune_for")
+    return tuple(a.value for a in v)
+
+
+def bs_ctx_load_tune(ctx, path):
+    n = ctypes.c_int()
+    _check(lib.bs_ctx_load_tune(ctx.handle, str(path).encode(), ctypes.byref(n)), "bs_ctx_load_tune")
+    return n.value

@@ -1,0 +1,194 @@
+"""Autotuner for the launch shapes of the streaming operations.
+
+    python -m paper_2009_10917_amd.autotune --out tune_gfx950.txt [--quick]
+
+Measures, on the current GPU, every candidate launch shape of each
+operation, dtype and length bucket, and writes the fastest as a tune table
+(the text format bs_ctx_load_tune reads).  Install the table as
+``paper_2009_10917_amd/tune_gfx950.txt`` (beside libbs.so), where
+bs_ctx_create picks it up; BS_TUNE_FILE overrides it.
+
+Candidates:
+  copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass}
+  norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536}
+  cg_update           (the reductions' partial buffer holds 65536 pairs)
+  gather, scatter   kernel variant {0, 1, 2}, each with and without the XCD
+                    renumbering, on permuted and oriented N = 7 meshes, with
+                    plans as bs_gs_create builds them (a caller that applies
+                    bs_gs_order_rows chooses gather variant 0 itself)
+
+Each candidate is timed with HIP events around back-to-back calls on
+resident inputs (median of three trials after a warm-up).  A candidate
+replaces the built-in default only when it is faster by more than 2%, so
+that noise does not move the table.  The timings of every candidate are
+written beside the table as JSON lines.
+"""
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+STREAM_OPS = ("copy", "axpy", "norm", "dot", "cg_update")
+REDUCTIONS = ("norm", "dot", "cg_update")
+DTYPES = (("f64", 0), ("f32", 1), ("bf16", 2))
+# bucket lower bounds and the length timed in each bucket
+BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 24, 1 << 26), (1 << 27, 1 << 28))
+MESH_K = ((0, 4), (1 << 20, 16), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
+DEFAULTS = {"copy": (1, 1 << 30, 0), "axpy": (1, 1 << 30, 0), "norm": (8, 4096, 0), "dot": (8, 4096, 0),
+            "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (1, 1 << 30, 1)}
+MARGIN = 0.98
+
+
+def _time(torch, fn, reps, trials=3):
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(trials):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / reps)
+    return statistics.median(out)
+
+
+def _pick(times, default):
+    """Fastest candidate, unless the default is within the margin."""
+    best = min(times, key=times.get)
+    if default in times and times[best] >= MARGIN * times[default]:
+        return default
+    return best
+
+
+def tune_streaming(torch, bs, bsgen, ctx, quick, log):
+    entries = []
+    tdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
+    for dname, did in DTYPES:
+        for n_min, n in BUCKETS:
+            if quick and n > (1 << 24):
+                continue
+            vec = {}
+            for k, sid in (("x", 1), ("y", 2), ("p", 3), ("r", 4), ("Ap", 5), ("w", 6)):
+                t = torch.empty(n, dtype=tdt[did], device="cuda")
+                bsgen.device_uniform(t, 10917, sid, lo=0.0 if k == "w" else -1.0)
+                vec[k] = t
+            out = torch.zeros(1, dtype=torch.float64, device="cuda")
+            calls = {
+                "copy": lambda: bs.bs_copy(ctx, vec["x"], vec["y"]),
+                "axpy": lambda: bs.bs_axpy(ctx, 0.37, vec["x"], 0.61, vec["y"]),
+                "norm": lambda: bs.bs_norm(ctx, vec["x"], vec["w"], out),
+                "dot": lambda: bs.bs_dot(ctx, vec["x"], vec["y"], out),
+                "cg_update": lambda: bs.bs_cg_update(ctx, 1e-3, vec["x"], vec["p"], vec["r"], vec["Ap"], vec["w"], out),
+            }
+            reps = 50 if n <= (1 << 20) else 10
+            for op in STREAM_OPS:
+                caps = (256, 1024, 4096, 16384, 65536) if op in REDUCTIONS else (1024, 4096, 16384, 65536, 1 << 30)
+                times = {}
+                for u in (1, 2, 4, 8):
+                    for g in caps:
+                        bs.bs_ctx_set_tune(ctx, op, u, g, 0)
+                        times[(u, g, 0)] = _time(torch, calls[op], reps)
+                        log.write(json.dumps({"op": op, "dtype": dname, "n": n, "unroll": u, "grid_cap": g,
+                                              "ms": round(times[(u, g, 0)], 5)}) + "\n")
+                choice = _pick(times, DEFAULTS[op])
+                entries.append((op, dname, n_min, *choice))
+                bs.bs_ctx_set_tune(ctx, op, *DEFAULTS[op])
+                print(f"# {op:9s} {dname:4s} n={n:>10d}: {choice} {times[choice]:.4f} ms "
+                      f"(default {times.get(DEFAULTS[op], float('nan')):.4f})", flush=True)
+            del vec, out
+            torch.cuda.empty_cache()
+    return entries
+
+
+def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
+    entries = {("gather", d): [] for d, _ in DTYPES}
+    entries.update({("scatter", d): [] for d, _ in DTYPES})
+    N, seed = 7, 10917
+    for n_min, K in MESH_K:
+        if quick and K > 64:
+            continue
+        E, M = K ** 3, K * N + 1
+        NL, NG = E * (N + 1) ** 3, M ** 3
+        perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
+        orient = torch.from_numpy(bsgen.orientations(seed, E).astype(np.uint8)).cuda()
+        d_map = torch.empty(NL, dtype=torch.int32, device="cuda")
+        bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+        plan = bs.bs_gs_create(ctx, d_map, NG)
+        del d_map, perm, orient
+        for dname, did in DTYPES:
+            tdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[did]
+            xL = torch.empty(NL, dtype=tdt, device="cuda")
+            xG = torch.empty(NG, dtype=tdt, device="cuda")
+            bsgen.device_uniform(xL, seed, 11)
+            bsgen.device_uniform(xG, seed, 12)
+            reps = 50 if NL <= (1 << 22) else 5
+            for op, call in (("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
+                             ("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL))):
+                times = {}
+                for v in (0, 1, 2, 4, 5, 6):
+                    bs.bs_ctx_set_tune(ctx, op, 1, 1 << 30, v)
+                    times[(1, 1 << 30, v)] = _time(torch, call, reps)
+                    log.write(json.dumps({"op": op, "dtype": dname, "n_local": NL, "variant": v,
+                                          "ms": round(times[(1, 1 << 30, v)], 5)}) + "\n")
+                choice = _pick(times, DEFAULTS[op])
+                entries[(op, dname)].append((op, dname, n_min, *choice))
+                bs.bs_ctx_set_tune(ctx, op, *DEFAULTS[op])
+                print(f"# {op:9s} {dname:4s} K={K:4d}: {choice} {times[choice]:.4f} ms "
+                      f"(default {times.get(DEFAULTS[op], float('nan')):.4f})", flush=True)
+            del xL, xG
+        plan.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return [e for v in entries.values() for e in v]
+
+
+def write_table(path, entries, device, seconds, quick):
+    with open(path, "w") as f:
+        f.write("# Launch-shape table for the streaming operations (bs_ctx_load_tune format)\n")
+        f.write(f"# measured by paper_2009_10917_amd/autotune.py{' --quick' if quick else ''} on {device} "
+                f"in {seconds:.0f} s\n")
+        f.write("# op dtype n_min unroll grid_cap variant\n")
+        for op, dname, n_min, u, g, v in entries:
+            f.write(f"{op} {dname} {n_min} {u} {g} {v}\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", default="tune_gfx950.txt")
+    ap.add_argument("--quick", action="store_true", help="skip the largest sizes")
+    args = ap.parse_args(argv)
+    os.environ["BS_TUNE_FILE"] = "none"  # measure against the built-in defaults
+    import numpy as np
+    import torch
+
+    import bsgen
+    import paper_2009_10917_amd as bs
+
+    if not torch.cuda.is_available():
+        print("autotune needs a GPU", file=sys.stderr)
+        return 1
+    ctx = bs.bs_ctx_create(0)
+    t0 = time.time()
+    with open(args.out + ".jsonl", "w") as log:
+        entries = tune_streaming(torch, bs, bsgen, ctx, args.quick, log)
+        entries += tune_gather_scatter(torch, np, bs, bsgen, ctx, args.quick, log)
+    props = torch.cuda.get_device_properties(0)
+    device = f"{getattr(props, 'gcnArchName', '?').split(':')[0]} ({props.multi_processor_count} CUs)"
+    write_table(args.out, entries, device, time.time() - t0, args.quick)
+    n = bs.bs_ctx_load_tune(ctx, args.out)  # the library must accept what it will load
+    print(f"# wrote {n} entries to {args.out}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -64,7 +64,7 @@ def build(verbose=False):
         objs = dict(zip(srcs, ex.map(_compile, srcs)))
     for lib, lib_srcs in LIBS.items():
         tmp = lib + ".tmp"
-        _run([HIPCC, *COMMON, "-shared", "-o", tmp, *[objs[s] for s in lib_srcs]])
+        _run([HIPCC, *COMMON, "-shared", "-o", tmp, *[objs[s] for s in lib_srcs], "-ldl"])
         os.replace(tmp, lib)
         if verbose:
             print("built", os.path.relpath(lib, ROOT))

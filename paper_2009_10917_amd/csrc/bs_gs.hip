@@ -29,6 +29,8 @@
 // XCD so that neighbouring blocks, which share cache lines, run on the same
 // XCD's L2.
 
+#include <type_traits>
+
 #include "bs_device.h"
 #include "bs_internal.h"
 
@@ -335,10 +337,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
 
 inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
 
+template <class T> constexpr int dtype_index() { return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2; }
+
 template <class T>
 bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hipStream_t st) {
   using E = typename Storage<T>::E;
-  const Tune& tn = ctx->tune[OP_GATHER][0];
+  const Tune& tn = tune_for(ctx, OP_GATHER, dtype_index<T>(), gs->n_local);
   const bool remap = (tn.variant & kNoXcdRemap) == 0;
   int kind = tn.variant & kVariantMask;
   if (kind == 0 && !gs->has_perm) kind = 1;
@@ -374,7 +378,7 @@ void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipS
 template <class T>
 bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hipStream_t st) {
   using E = typename Storage<T>::E;
-  const Tune& tn = ctx->tune[OP_SCATTER][0];
+  const Tune& tn = tune_for(ctx, OP_SCATTER, dtype_index<T>(), gs->n_local);
   const bool remap = (tn.variant & kNoXcdRemap) == 0;
   const int kind = tn.variant & kVariantMask;
   const dim3 tiles(static_cast<unsigned int>(gs->n_tiles));

@@ -1,8 +1,13 @@
 // Contexts, status strings, error recording and argument checks.
 
+#include <dlfcn.h>
+
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "bs_internal.h"
 
@@ -69,6 +74,63 @@ extern "C" const char* bs_last_error(void) { return g_last_error; }
 
 extern "C" const char* bs_version(void) { return "bs-mi355x 0.1 (gfx950)"; }
 
+namespace {
+
+const char* const kOpNames[OP_COUNT] = {"copy", "axpy", "norm", "dot", "cg_update", "gather", "scatter"};
+const char* const kDtypeNames[3] = {"f64", "f32", "bf16"};
+
+void set_one(TuneList& L, Tune t) {
+  L.count = 1;
+  L.n_min[0] = 0;
+  L.t[0] = t;
+}
+
+// Defaults measured on MI355X at n = 7.2e8 binary64 values: element-wise
+// operations run one 16-byte packet per thread in a one-pass grid; the
+// reductions grid-stride with several packets in flight per thread.
+void set_defaults(bs_ctx* c) {
+  for (int op = 0; op < OP_COUNT; ++op)
+    for (int d = 0; d < 3; ++d) set_one(c->tune[op][d], Tune{1, 1 << 30, 0});
+  for (int d = 0; d < 3; ++d) {
+    set_one(c->tune[OP_NORM][d], Tune{8, 4096, 0});
+    set_one(c->tune[OP_DOT][d], Tune{8, 4096, 0});
+    set_one(c->tune[OP_CG_UPDATE][d], Tune{4, kMaxReduceBlocks, 0});
+    // gather: rows in global order; scatter: tiles read in local order
+    set_one(c->tune[OP_GATHER][d], Tune{1, 1 << 30, 1});
+    set_one(c->tune[OP_SCATTER][d], Tune{1, 1 << 30, 1});
+  }
+}
+
+bs_status check_tune(const char* op, int unroll, int grid_cap, int variant) {
+  if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
+    return fail(BS_ERR_INVALID_ARG, "%s: unroll must be 1, 2, 4 or 8", op);
+  if (grid_cap < 1) return fail(BS_ERR_INVALID_ARG, "%s: grid_cap must be positive", op);
+  if (variant < 0 || variant > 7 || (variant & kVariantMask) == 3)
+    return fail(BS_ERR_INVALID_ARG, "%s: variant must be 0, 1 or 2, optionally plus 4", op);
+  return BS_OK;
+}
+
+// Insert or replace the entry for n_min in a list kept sorted by n_min.
+bool put_entry(TuneList& L, int64_t n_min, Tune t) {
+  for (int j = 0; j < L.count; ++j)
+    if (L.n_min[j] == n_min) {
+      L.t[j] = t;
+      return true;
+    }
+  if (L.count == kTuneEntries) return false;
+  int j = L.count++;
+  while (j > 0 && L.n_min[j - 1] > n_min) {
+    L.n_min[j] = L.n_min[j - 1];
+    L.t[j] = L.t[j - 1];
+    --j;
+  }
+  L.n_min[j] = n_min;
+  L.t[j] = t;
+  return true;
+}
+
+}  // namespace
+
 extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
   if (!out) return fail(BS_ERR_INVALID_ARG, "bs_ctx_create: out is NULL");
   *out = nullptr;
@@ -97,18 +159,33 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
     (void)hipSetDevice(prev);
     return s;
   }
-  // Defaults measured on MI355X at n = 7.2e8 binary64 values: element-wise
-  // operations run one 16-byte packet per thread in a one-pass grid; the
-  // reductions grid-stride with several packets in flight per thread.
-  for (int op = 0; op < OP_COUNT; ++op)
-    for (int d = 0; d < 3; ++d) c->tune[op][d] = Tune{1, 1 << 30, 0};
-  for (int d = 0; d < 3; ++d) {
-    c->tune[OP_NORM][d] = Tune{8, 4096, 0};
-    c->tune[OP_DOT][d] = Tune{8, 4096, 0};
-    c->tune[OP_CG_UPDATE][d] = Tune{4, kMaxReduceBlocks, 0};
-    // gather: rows in global order; scatter: tiles read in local order
-    c->tune[OP_GATHER][d] = Tune{1, 1 << 30, 1};
-    c->tune[OP_SCATTER][d] = Tune{1, 1 << 30, 1};
+  set_defaults(c);
+  // A tune table next to the library (written by the autotuner), or the one
+  // BS_TUNE_FILE names ("none": keep the defaults).
+  std::string path;
+  if (const char* env = std::getenv("BS_TUNE_FILE")) {
+    path = env;
+  } else {
+    Dl_info info{};
+    if (dladdr(reinterpret_cast<void*>(&bs_ctx_create), &info) && info.dli_fname) {
+      path = info.dli_fname;
+      const size_t slash = path.find_last_of('/');
+      path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tune_gfx950.txt";
+      if (FILE* f = std::fopen(path.c_str(), "r")) {
+        std::fclose(f);
+      } else {
+        path.clear();
+      }
+    }
+  }
+  if (!path.empty() && path != "none") {
+    int entries = 0;
+    if ((s = bs_ctx_load_tune(c, path.c_str(), &entries))) {
+      (void)hipFree(ws);
+      delete c;
+      (void)hipSetDevice(prev);
+      return s;
+    }
   }
   (void)hipSetDevice(prev);
   *out = c;
@@ -130,13 +207,96 @@ extern "C" bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int un
   if (!ctx) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: ctx is NULL");
   if (op < 0 || op >= OP_COUNT) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unknown op %d", op);
   if (dtype_size(dtype) == 0) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unknown dtype %d", (int)dtype);
-  if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
-    return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: unroll must be 1, 2, 4 or 8");
-  if (grid_cap < 1) return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: grid_cap must be positive");
-  if (variant < 0 || variant > 7 || (variant & kVariantMask) == 3)
-    return fail(BS_ERR_INVALID_ARG, "bs_ctx_set_tune: variant must be 0, 1 or 2, optionally plus 4");
-  // every dtype currently shares one entry per op
-  for (int d = 0; d < 3; ++d) ctx->tune[op][d] = Tune{unroll, grid_cap, variant};
+  if (bs_status s = check_tune("bs_ctx_set_tune", unroll, grid_cap, variant)) return s;
+  // one entry for every dtype and length
+  for (int d = 0; d < 3; ++d) set_one(ctx->tune[op][d], Tune{unroll, grid_cap, variant});
+  return BS_OK;
+}
+
+extern "C" bs_status bs_ctx_set_tune_entry(bs_ctx* ctx, int op, bs_dtype dtype, int64_t n_min, int unroll,
+                                           int grid_cap, int variant) {
+  const char* name = "bs_ctx_set_tune_entry";
+  if (!ctx) return fail(BS_ERR_INVALID_ARG, "%s: ctx is NULL", name);
+  if (op < 0 || op >= OP_COUNT) return fail(BS_ERR_INVALID_ARG, "%s: unknown op %d", name, op);
+  if (dtype_size(dtype) == 0) return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype %d", name, (int)dtype);
+  if (n_min < 0) return fail(BS_ERR_INVALID_ARG, "%s: n_min must be >= 0", name);
+  if (bs_status s = check_tune(name, unroll, grid_cap, variant)) return s;
+  if (!put_entry(ctx->tune[op][static_cast<int>(dtype)], n_min, Tune{unroll, grid_cap, variant}))
+    return fail(BS_ERR_INVALID_ARG, "%s: at most %d entries per operation and dtype", name, kTuneEntries);
+  return BS_OK;
+}
+
+extern "C" bs_status bs_ctx_tune_for(const bs_ctx* ctx, int op, bs_dtype dtype, int64_t n, int* unroll,
+                                     int* grid_cap, int* variant) {
+  if (!ctx || op < 0 || op >= OP_COUNT || dtype_size(dtype) == 0 || n < 0)
+    return fail(BS_ERR_INVALID_ARG, "bs_ctx_tune_for: bad argument");
+  const Tune& t = tune_for(ctx, op, static_cast<int>(dtype), n);
+  if (unroll) *unroll = t.unroll;
+  if (grid_cap) *grid_cap = t.grid_cap;
+  if (variant) *variant = t.variant;
+  return BS_OK;
+}
+
+extern "C" bs_status bs_ctx_load_tune(bs_ctx* ctx, const char* path, int* n_entries) {
+  const char* name = "bs_ctx_load_tune";
+  if (!ctx || !path) return fail(BS_ERR_INVALID_ARG, "%s: NULL argument", name);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(BS_ERR_INVALID_ARG, "%s: cannot open %s", name, path);
+  TuneList fresh[OP_COUNT][3];
+  bool seen[OP_COUNT][3] = {};
+  char line[512];
+  int lineno = 0, entries = 0;
+  bs_status s = BS_OK;
+  while (!s && std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    char* hash = std::strchr(line, '#');
+    if (hash) *hash = '\0';
+    char op_name[32], dt_name[16];
+    long long n_min = 0;
+    int unroll = 0, grid_cap = 0, variant = 0, used = 0;
+    const int got = std::sscanf(line, "%31s %15s %lld %d %d %d %n", op_name, dt_name, &n_min, &unroll, &grid_cap,
+                                &variant, &used);
+    if (got <= 0) continue;  // blank or comment
+    if (got != 6 || line[used] != '\0') {
+      s = fail(BS_ERR_INVALID_ARG, "%s: %s line %d: expected 'op dtype n_min unroll grid_cap variant'", name, path,
+               lineno);
+      break;
+    }
+    const int op = static_cast<int>(std::find_if(kOpNames, kOpNames + OP_COUNT,
+                                                 [&](const char* q) { return std::strcmp(q, op_name) == 0; }) -
+                                    kOpNames);
+    const int d = static_cast<int>(std::find_if(kDtypeNames, kDtypeNames + 3,
+                                                [&](const char* q) { return std::strcmp(q, dt_name) == 0; }) -
+                                   kDtypeNames);
+    if (op == OP_COUNT || d == 3) {
+      s = fail(BS_ERR_INVALID_ARG, "%s: %s line %d: unknown operation or dtype", name, path, lineno);
+      break;
+    }
+    if (n_min < 0 || (s = check_tune(name, unroll, grid_cap, variant))) {
+      if (!s) s = fail(BS_ERR_INVALID_ARG, "%s: %s line %d: negative n_min", name, path, lineno);
+      break;
+    }
+    if (!seen[op][d]) {
+      seen[op][d] = true;
+      fresh[op][d].count = 0;
+    }
+    if (!put_entry(fresh[op][d], n_min, Tune{unroll, grid_cap, variant})) {
+      s = fail(BS_ERR_INVALID_ARG, "%s: %s line %d: too many entries for %s %s", name, path, lineno, op_name, dt_name);
+      break;
+    }
+    ++entries;
+  }
+  std::fclose(f);
+  if (s) return s;
+  for (int op = 0; op < OP_COUNT; ++op)
+    for (int d = 0; d < 3; ++d)
+      if (seen[op][d] && fresh[op][d].n_min[0] != 0)
+        return fail(BS_ERR_INVALID_ARG, "%s: %s: %s %s has no entry for n_min 0", name, path, kOpNames[op],
+                    kDtypeNames[d]);
+  for (int op = 0; op < OP_COUNT; ++op)
+    for (int d = 0; d < 3; ++d)
+      if (seen[op][d]) ctx->tune[op][d] = fresh[op][d];
+  if (n_entries) *n_entries = entries;
   return BS_OK;
 }
 
@@ -144,7 +304,7 @@ extern "C" bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, 
                                      int* variant) {
   if (!ctx || op < 0 || op >= OP_COUNT || dtype_size(dtype) == 0)
     return fail(BS_ERR_INVALID_ARG, "bs_ctx_get_tune: bad argument");
-  const Tune& t = ctx->tune[op][static_cast<int>(dtype)];
+  const Tune& t = ctx->tune[op][static_cast<int>(dtype)].t[0];
   if (unroll) *unroll = t.unroll;
   if (grid_cap) *grid_cap = t.grid_cap;
   if (variant) *variant = t.variant;

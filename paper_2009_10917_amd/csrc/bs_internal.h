@@ -49,6 +49,16 @@ struct Tune {
 
 enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCATTER, OP_COUNT };
 
+// Tune entries of one operation and dtype, by length: entry k applies to
+// lengths n >= n_min[k] up to the next entry's n_min (n_min[0] == 0,
+// ascending).  Gather and scatter use the plan's local length.
+constexpr int kTuneEntries = 8;
+struct TuneList {
+  int count;
+  int64_t n_min[kTuneEntries];
+  Tune t[kTuneEntries];
+};
+
 // Largest number of workgroups a reduction may use: the context's partial
 // buffer holds one compensated pair per workgroup.
 constexpr int kMaxReduceBlocks = 65536;
@@ -60,8 +70,19 @@ constexpr int kFinishBlock = 1024;  // threads of the second reduction stage
 struct bs_ctx {
   int device;
   double* partials;  // 2 * kMaxReduceBlocks doubles: (sum, compensation) per workgroup
-  bs::Tune tune[bs::OP_COUNT][3];
+  bs::TuneList tune[bs::OP_COUNT][3];
 };
+
+namespace bs {
+// The entry that applies to length n.
+inline const Tune& tune_for(const bs_ctx* c, int op, int dt, int64_t n) {
+  const TuneList& L = c->tune[op][dt];
+  int k = 0;
+  for (int j = 1; j < L.count; ++j)
+    if (L.n_min[j] <= n) k = j;
+  return L.t[k];
+}
+}  // namespace bs
 
 struct bs_gs {
   int device;

@@ -17,6 +17,8 @@
 // first launch would need an agent-scope fence per workgroup, which on this
 // 8-XCD part costs more than the second launch.
 
+#include <type_traits>
+
 #include "bs_stream_ops.h"
 
 namespace bs {
@@ -140,10 +142,12 @@ inline int norm_unroll(int u) { return (u >= 8) ? 8 : (u >= 4) ? 4 : (u >= 2) ? 
     }                                                                                                      \
   } while (0)
 
+template <class T> constexpr int dtype_index() { return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2; }
+
 template <class T>
 bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t st) {
   const Span sp = make_span<T>(n, {x, y});
-  const Tune& tn = ctx->tune[OP_COPY][0];
+  const Tune& tn = tune_for(ctx, OP_COPY, dtype_index<T>(), n);
   const int u = norm_unroll(tn.unroll);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
   BS_DISPATCH(k_copy, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
@@ -154,7 +158,7 @@ template <class T>
 bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double beta, void* y, hipStream_t st) {
   using C = typename Storage<T>::C;
   const Span sp = make_span<T>(n, {x, y});
-  const Tune& tn = ctx->tune[OP_AXPY][0];
+  const Tune& tn = tune_for(ctx, OP_AXPY, dtype_index<T>(), n);
   const int u = norm_unroll(tn.unroll);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
   BS_DISPATCH(k_axpy, T, sp, u, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
@@ -165,7 +169,7 @@ bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double b
 template <class T>
 bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double* out, hipStream_t st) {
   const Span sp = make_span<T>(n, {x, w});
-  const Tune& tn = ctx->tune[OP_NORM][0];
+  const Tune& tn = tune_for(ctx, OP_NORM, dtype_index<T>(), n);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
@@ -181,7 +185,7 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
 template <class T>
 bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* out, hipStream_t st) {
   const Span sp = make_span<T>(n, {x, y});
-  const Tune& tn = ctx->tune[OP_DOT][0];
+  const Tune& tn = tune_for(ctx, OP_DOT, dtype_index<T>(), n);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
@@ -194,7 +198,7 @@ bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const voi
                         const void* w, double* out, hipStream_t st) {
   using C = typename Storage<T>::C;
   const Span sp = make_span<T>(n, {x, p, r, Ap, w});
-  const Tune& tn = ctx->tune[OP_CG_UPDATE][0];
+  const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
