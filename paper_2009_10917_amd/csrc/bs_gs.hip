@@ -42,20 +42,42 @@ using dev::Storage;
 
 // ---------------------------------------------------------------- BS6 gather, rows in visiting order
 
+// ((+0 + v[a]) + v[a+1]) + ... + v[e-1], with the LDS reads issued four at a time.
+template <class C>
+__device__ __forceinline__ C row_sum(const C* v, int32_t a, int32_t e) {
+  C s = C(0);
+  int32_t j = a;
+  for (; j + 4 <= e; j += 4) {
+    const C t0 = v[j], t1 = v[j + 1], t2 = v[j + 2], t3 = v[j + 3];
+    s += t0;
+    s += t1;
+    s += t2;
+    s += t3;
+  }
+  for (; j < e; ++j) s += v[j];
+  return s;
+}
+
+// A workgroup owns the rows of one block and the CSR window of their
+// nonzeros (at most kStage).  The window's local values are loaded in
+// ascending local index (the plan stores each window's column ids sorted),
+// so that lanes of one load share cache lines, and each value is put in LDS
+// at its CSR offset; every row then adds its copies from LDS in CSR order,
+// i.e. in ascending local index, as the definition of x_G = Z^T x_L does.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restrict__ pcols,
+__global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restrict__ scols,
+                                                        const uint16_t* __restrict__ sdst,
                                                         const int32_t* __restrict__ prows,
                                                         const uint8_t* __restrict__ pdeg,
                                                         const int32_t* __restrict__ pbstart,
                                                         const int32_t* __restrict__ pbnz0,
                                                         const typename Storage<T>::E* __restrict__ xL,
-                                                        typename Storage<T>::E* __restrict__ xG, int64_t chunk,
-                                                        int64_t nnz, int64_t n_pblocks, int64_t n_nzrows,
-                                                        int64_t n_rows, bool remap) {
+                                                        typename Storage<T>::E* __restrict__ xG, int64_t n_pblocks,
+                                                        int64_t n_nzrows, int64_t n_rows, bool remap) {
   using S = Storage<T>;
   using C = typename S::C;
   constexpr int L = kStage / kBlock;
-  __shared__ C lds[kStage];            // local values of the CSR window
+  __shared__ C lds[kStage];            // the window's local values, CSR order
   __shared__ int32_t sst[kStage + 1];  // row starts relative to the window
   __shared__ int32_t wsum[kBlock / 64];
   const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -64,23 +86,35 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restric
     if (q < n_rows) dev::st_nt(xG + prows[q], S::store(C(0)));
     return;
   }
-  const int64_t w0 = b * chunk;  // CSR window [w0, w0 + kStage)
-  // 1. window values: column ids, then the local values they name
-  C v[L];
+  const int64_t w0 = pbnz0[b];
+  const int32_t n = static_cast<int32_t>(pbnz0[b + 1] - w0);  // <= kStage
+  if (n == 0) return;  // a trailing block whose range holds no row start
+  // 1. the window's values in address order, with their CSR offsets: all
+  //    index loads first, then all value loads (lanes past the window repeat
+  //    its last entry, so that no load waits behind a branch)
+  int32_t col[L], slot[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    const int64_t j = w0 + threadIdx.x + k * kBlock;
-    if (j < nnz) v[k] = S::load(xL[dev::ld_nt(pcols + j)]);
+    const int32_t t = min(static_cast<int32_t>(threadIdx.x) + k * kBlock, n - 1);
+    col[k] = dev::ld_nt(scols + w0 + t);
+    slot[k] = dev::ld_nt(sdst + w0 + t);
   }
+  C v[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) v[k] = S::load(xL[col[k]]);
   // 2. meanwhile the block's rows: degrees of rows t*L .. t*L+L-1, scanned
   const int32_t r0 = pbstart[b], r1 = pbstart[b + 1];
-  const int32_t nrows = r1 - r0;  // <= kStage: every row has a copy
-  int32_t d[L];
+  const int32_t nrows = r1 - r0;  // in [1, n]: every row has a copy
+  int32_t d[L], gid[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) d[i] = pdeg[r0 + min(static_cast<int32_t>(threadIdx.x) * L + i, nrows - 1)];
+  // and the global ids of the rows this thread adds in step 3 (q = t + k kBlock)
+#pragma unroll
+  for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(static_cast<int32_t>(threadIdx.x) + k * kBlock, nrows - 1)];
   int32_t tsum = 0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const int32_t q = threadIdx.x * L + i;
-    d[i] = (q < nrows) ? static_cast<int32_t>(pdeg[r0 + q]) : 0;
+    if (static_cast<int32_t>(threadIdx.x) * L + i >= nrows) d[i] = 0;
     tsum += d[i];
   }
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
@@ -92,39 +126,26 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restric
   }
   if (lane == 63) wsum[w] = incl;
 #pragma unroll
-  for (int k = 0; k < L; ++k) {
-    const int64_t j = w0 + threadIdx.x + k * kBlock;
-    if (j < nnz) lds[threadIdx.x + k * kBlock] = v[k];
-  }
+  for (int k = 0; k < L; ++k)
+    if (static_cast<int32_t>(threadIdx.x) + k * kBlock < n) lds[slot[k]] = v[k];
   __syncthreads();
-  int32_t before = 0, total = 0;
+  int32_t before = 0;
 #pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) {
-    before += (i < w) ? wsum[i] : 0;
-    total += wsum[i];
-  }
-  const int32_t s0 = static_cast<int32_t>(pbnz0[b] - w0);  // first row's start in the window
-  int32_t pos = s0 + before + incl - tsum;
+  for (int i = 0; i < kBlock / 64; ++i) before += (i < w) ? wsum[i] : 0;
+  int32_t pos = before + incl - tsum;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int32_t q = threadIdx.x * L + i;
     if (q < nrows) sst[q] = pos;
     pos += d[i];
   }
-  if (threadIdx.x == 0) sst[nrows] = s0 + total;
+  if (threadIdx.x == 0) sst[nrows] = n;
   __syncthreads();
-  // 3. each thread adds whole rows in CSR order (from LDS when the rows lie
-  //    in the window, as the plan guarantees; from memory otherwise)
-  const bool staged = s0 >= 0 && s0 + total <= kStage;
-  for (int32_t q = threadIdx.x; q < nrows; q += kBlock) {
-    const int32_t a = sst[q], e = sst[q + 1];
-    C s = C(0);
-    if (staged) {
-      for (int32_t j = a; j < e; ++j) s += lds[j];
-    } else {
-      for (int32_t j = a; j < e; ++j) s += S::load(xL[pcols[w0 + j]]);
-    }
-    dev::st_nt(xG + prows[r0 + q], S::store(s));
+  // 3. each thread adds whole rows in CSR order
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int32_t q = threadIdx.x + k * kBlock;
+    if (q < nrows) dev::st_nt(xG + gid[k], S::store(row_sum<C>(lds, sst[q], sst[q + 1])));
   }
 }
 
@@ -143,22 +164,30 @@ __global__ __launch_bounds__(kBlock) void k_gather_nnz(const int32_t* __restrict
   __shared__ int32_t srs[kStage + 1];  // row starts of the block's rows
   const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   const int64_t w0 = b * chunk;  // CSR window [w0, w0 + kStage)
-  // 1. window values: column ids, then the local values they name
+  // 1. window values: all column ids, then the local values they name
+  //    (lanes past the end repeat the last entry, so that no load waits
+  //    behind a branch).  The plan has at least one block, so a plan
+  //    without nonzeros has a block with an empty window.
   C v[L];
+  if (w0 < nnz) {
+    int32_t col[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) {
-    const int64_t j = w0 + threadIdx.x + k * kBlock;
-    if (j < nnz) v[k] = S::load(xL[dev::ld_nt(ci + j)]);
+    for (int k = 0; k < L; ++k) col[k] = dev::ld_nt(ci + min(w0 + threadIdx.x + k * kBlock, nnz - 1));
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = S::load(xL[col[k]]);
   }
   // 2. meanwhile, the block's rows and their starts
   const int32_t r0 = bstart[b], r1 = bstart[b + 1];
   const int32_t nrows = r1 - r0;
   const bool rows_staged = nrows <= kStage;
   if (rows_staged) {
+    int32_t st[L + 1];
+#pragma unroll
+    for (int k = 0; k <= L; ++k) st[k] = rs[r0 + min(static_cast<int32_t>(threadIdx.x) + k * kBlock, nrows)];
 #pragma unroll
     for (int k = 0; k <= L; ++k) {
       const int32_t q = threadIdx.x + k * kBlock;
-      if (q <= nrows) srs[q] = rs[r0 + q];
+      if (q <= nrows) srs[q] = st[k];
     }
   }
 #pragma unroll
@@ -177,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_nnz(const int32_t* __restrict
     const int32_t e = rows_staged ? srs[q + 1] : rs[r0 + q + 1];
     C s = C(0);
     if (staged) {
-      for (int32_t j = a; j < e; ++j) s += lds[j - w0];
+      s = row_sum<C>(lds, static_cast<int32_t>(a - w0), static_cast<int32_t>(e - w0));
     } else {
       for (int32_t j = a; j < e; ++j) s += S::load(xL[ci[j]]);
     }
@@ -203,26 +232,25 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ r
   const int32_t base = rs[row0];
   const int32_t nnz = rs[row1] - base;
   if (nnz <= CAP) {
-    C v[L];
+    if (nnz > 0) {  // all column ids, then all values (lanes past the end repeat the last entry)
+      int32_t col[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-      const int32_t i = threadIdx.x + k * kBlock;
-      if (i < nnz) v[k] = S::load(xL[ci[base + i]]);
-    }
+      for (int k = 0; k < L; ++k) col[k] = ci[base + min(static_cast<int32_t>(threadIdx.x) + k * kBlock, nnz - 1)];
+      C v[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-      const int32_t i = threadIdx.x + k * kBlock;
-      if (i < nnz) lds[i] = v[k];
+      for (int k = 0; k < L; ++k) v[k] = S::load(xL[col[k]]);
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        const int32_t i = threadIdx.x + k * kBlock;
+        if (i < nnz) lds[i] = v[k];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int32_t row = row0 + q * kBlock + threadIdx.x;
       if (row < row1) {
-        const int32_t a = rs[row] - base, e = rs[row + 1] - base;
-        C s = C(0);
-        for (int32_t j = a; j < e; ++j) s += lds[j];
-        xG[row] = S::store(s);
+        xG[row] = S::store(row_sum<C>(lds, rs[row] - base, rs[row + 1] - base));
       }
     }
   } else {
@@ -350,9 +378,9 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
     const int64_t zero_blocks = (gs->n_global - gs->n_nzrows + kBlock - 1) / kBlock;
     const int64_t grid = gs->n_pblocks + zero_blocks;
     if (grid > 0)
-      hipLaunchKernelGGL((k_gather_perm<T>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st, gs->perm_cols,
-                         gs->perm_rows, gs->perm_deg, gs->perm_bstart, gs->perm_bnz0, static_cast<const E*>(xL),
-                         static_cast<E*>(xG), gs->chunk, gs->n_unmasked, gs->n_pblocks, gs->n_nzrows, gs->n_global,
+      hipLaunchKernelGGL((k_gather_perm<T>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
+                         gs->perm_scols, gs->perm_dst, gs->perm_rows, gs->perm_deg, gs->perm_bstart, gs->perm_bnz0,
+                         static_cast<const E*>(xL), static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global,
                          remap);
   } else if (kind == 1) {
     hipLaunchKernelGGL((k_gather_nnz<T>), dim3(static_cast<unsigned int>(gs->n_blocks)), dim3(kBlock), 0, st,

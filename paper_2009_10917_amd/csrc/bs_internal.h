@@ -111,18 +111,25 @@ struct bs_gs {
   int32_t* tile_count;   // [n_tiles]
   int64_t n_tiles;
 
-  // Gather, rows in visiting order: rows grouped by the first tile (in
-  // tile_order) that holds one of their copies; perm_rows lists rows with
-  // copies first (perm_deg copies each, columns in perm_cols, ascending local
-  // index per row), then rows without copies.  Nonzero-balanced blocks as
-  // above (perm_bstart, with perm_bnz0[b] the CSR offset of the block's first
-  // row).  Built only when every degree fits in a byte (has_perm).
+  // Gather, rows in a permuted order: by default grouped by the first tile
+  // (in tile_order) that holds one of their copies, or in lattice blocks
+  // (bs_gs_order_rows); perm_rows lists rows with copies first (perm_deg
+  // copies each), then rows without copies.  Nonzero-balanced blocks as
+  // above: block b adds rows [perm_bstart[b], perm_bstart[b+1]), whose
+  // nonzeros are the CSR positions [perm_bnz0[b], perm_bnz0[b+1]) (at most
+  // kStage of them, since chunk + max_degree <= kStage).  Within that
+  // window the column ids are stored sorted (perm_scols, so that a block
+  // reads its local values in address order) with, for each, its position
+  // in the window's CSR order (perm_dst; rows list their copies in
+  // ascending local index).  Built only when every degree fits in a byte
+  // (has_perm).
   bool has_perm;
   int32_t* perm_rows;    // [n_global]
   uint8_t* perm_deg;     // [n_nzrows]
-  int32_t* perm_cols;    // [n_unmasked]
+  int32_t* perm_scols;   // [n_unmasked]
+  uint16_t* perm_dst;    // [n_unmasked]
   int32_t* perm_bstart;  // [n_pblocks + 1]
-  int32_t* perm_bnz0;    // [n_pblocks]
+  int32_t* perm_bnz0;    // [n_pblocks + 1]
   int64_t n_nzrows;
   int64_t n_pblocks;
 };

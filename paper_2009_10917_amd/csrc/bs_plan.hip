@@ -102,7 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_degree_stats(const int32_t* __restri
 }
 
 // bstart[b] = first index k in [0, n_rows] with starts[k] >= b*chunk
-// (b < n_blocks); bstart[n_blocks] = n_rows; optionally bnz0[b] = starts[bstart[b]].
+// (b < n_blocks); bstart[n_blocks] = n_rows; optionally bnz0[b] = starts[bstart[b]]
+// for b <= n_blocks.
 __global__ __launch_bounds__(kBlock) void k_block_starts(const int32_t* __restrict__ starts, int64_t n_rows,
                                                          int64_t chunk, int64_t n_blocks, int32_t* __restrict__ bstart,
                                                          int32_t* __restrict__ bnz0) {
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_block_starts(const int32_t* __restri
   if (b > n_blocks) return;
   if (b == n_blocks) {
     bstart[b] = static_cast<int32_t>(n_rows);
+    if (bnz0) bnz0[b] = starts[n_rows];
     return;
   }
   const int64_t target = b * chunk;
@@ -191,11 +193,13 @@ __global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t* __restrict__
 
 // Row keys of a lattice-tiled order: global id g is lattice point
 // (g mod mx, (g / mx) mod my, g / (mx my)); its key is the index of its
-// tile x tile x tile block in lattice order (blocks along x fastest); rows
-// without copies get the largest key so that they come last.
+// tile x tile x tile block in lattice order (blocks along x fastest) and,
+// within the block, of its sub x sub x sub box (ns boxes per side, in the
+// same order); rows without copies get the largest key so that they come
+// last.
 __global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restrict__ rs, int64_t n_global, int64_t mx,
                                                          int64_t my, int64_t tile, int64_t ntx, int64_t nty,
-                                                         uint32_t* __restrict__ key) {
+                                                         int64_t sub, int64_t ns, uint32_t* __restrict__ key) {
   const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (g >= n_global) return;
   if (rs[g + 1] == rs[g]) {
@@ -203,7 +207,44 @@ __global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restri
     return;
   }
   const int64_t x = g % mx, y = (g / mx) % my, z = g / (mx * my);
-  key[g] = static_cast<uint32_t>(x / tile + ntx * (y / tile + nty * (z / tile)));
+  const int64_t t = x / tile + ntx * (y / tile + nty * (z / tile));
+  const int64_t b = (x % tile) / sub + ns * ((y % tile) / sub + ns * ((z % tile) / sub));
+  key[g] = static_cast<uint32_t>(t * ns * ns * ns + b);
+}
+
+// Per gather block: the column ids of its window [bnz0[b], bnz0[b+1])
+// (at most kStage) sorted ascending, each with its offset in the window
+// (a bitonic sort of (column, offset) keys in LDS).
+__global__ __launch_bounds__(kBlock) void k_window_sort(const int32_t* __restrict__ cols,
+                                                        const int32_t* __restrict__ bnz0, int32_t* __restrict__ scols,
+                                                        uint16_t* __restrict__ dst) {
+  static_assert((kStage & (kStage - 1)) == 0 && kStage <= 65536, "window offsets are 16-bit, sort size a power of 2");
+  __shared__ uint64_t key[kStage];
+  const int64_t a = bnz0[blockIdx.x];
+  const int32_t n = static_cast<int32_t>(bnz0[blockIdx.x + 1] - a);
+  for (int t = threadIdx.x; t < kStage; t += kBlock)
+    key[t] = (t < n) ? (static_cast<uint64_t>(static_cast<uint32_t>(cols[a + t])) << 16) | static_cast<uint64_t>(t)
+                     : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= kStage; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < kStage; t += kBlock) {
+        const int p = t ^ j;
+        if (p > t) {
+          const uint64_t u = key[t], v = key[p];
+          if ((u > v) == ((t & k) == 0)) {
+            key[t] = v;
+            key[p] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < n; t += kBlock) {
+    scols[a + t] = static_cast<int32_t>(key[t] >> 16);
+    dst[a + t] = static_cast<uint16_t>(key[t] & 0xffffu);
+  }
 }
 
 // Degrees of the rows in visiting order (byte and int copies).
@@ -410,7 +451,7 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
 // Rows in visiting order (needs the tile order and the CSR).
 // Lattice description for a tiled gather order (global ids are lattice points).
 struct LatticeOrder {
-  int64_t mx, my, mz, tile;
+  int64_t mx, my, mz, tile, sub;  // sub: side of the boxes inside a tile (tile: none)
 };
 
 // Rows with copies in a permuted order and the CSR in that order: by default
@@ -420,7 +461,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   if (gs->max_degree > 255) return;  // degrees are stored in bytes
   const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
   const int64_t nz = ng - n_zero_rows;  // rows with copies
-  DevBuf rank, rkey, rkey_out, rows0, rows, d8, d32, prs, pcols, bstart, bnz0;
+  DevBuf rank, rkey, rkey_out, rows0, rows, d8, d32, prs, pcols, scols, dst, bstart, bnz0;
   B.need(rank, nt * 4, "tile ranks");
   B.need(rkey, ng * 4, "row keys");
   B.need(rkey_out, ng * 4, "row keys");
@@ -434,9 +475,10 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
   if (lat) {
     const int64_t ntx = (lat->mx + lat->tile - 1) / lat->tile, nty = (lat->my + lat->tile - 1) / lat->tile;
+    const int64_t ns = (lat->tile + lat->sub - 1) / lat->sub;
     if (ng > 0)
       hipLaunchKernelGGL(k_lattice_keys, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, gs->row_starts, ng, lat->mx,
-                         lat->my, lat->tile, ntx, nty, rkey.as<uint32_t>());
+                         lat->my, lat->tile, ntx, nty, lat->sub, ns, rkey.as<uint32_t>());
   } else {
     if (nt > 0)
       hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
@@ -467,16 +509,22 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.launched();
   const int64_t nb = (gs->n_unmasked + gs->chunk - 1) / gs->chunk;
   B.need(bstart, (nb + 1) * 4, "block starts");
-  B.need(bnz0, (nb > 0 ? nb : 1) * 4, "block offsets");
+  B.need(bnz0, (nb + 1) * 4, "block offsets");
+  B.need(scols, gs->n_unmasked * 4, "sorted columns");
+  B.need(dst, gs->n_unmasked * 2, "window offsets");
   if (!B.ok()) return;
   hipLaunchKernelGGL(k_block_starts, dim3(blocks_for(nb + 1)), dim3(kBlock), 0, B.st, prs.as<int32_t>(), nz, gs->chunk,
                      nb, bstart.as<int32_t>(), bnz0.as<int32_t>());
+  if (nb > 0)
+    hipLaunchKernelGGL(k_window_sort, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, pcols.as<int32_t>(),
+                       bnz0.as<int32_t>(), scols.as<int32_t>(), dst.as<uint16_t>());
   B.launched();
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
   gs->perm_rows = rows.release<int32_t>();
   gs->perm_deg = d8.release<uint8_t>();
-  gs->perm_cols = pcols.release<int32_t>();
+  gs->perm_scols = scols.release<int32_t>();
+  gs->perm_dst = dst.release<uint16_t>();
   gs->perm_bstart = bstart.release<int32_t>();
   gs->perm_bnz0 = bnz0.release<int32_t>();
   gs->n_nzrows = nz;
@@ -492,7 +540,8 @@ void free_plan(bs_gs* gs) {
                   static_cast<void*>(gs->block_starts), static_cast<void*>(gs->tile_order),
                   static_cast<void*>(gs->tile_gid), static_cast<void*>(gs->tile_loc),
                   static_cast<void*>(gs->tile_count), static_cast<void*>(gs->perm_rows),
-                  static_cast<void*>(gs->perm_deg), static_cast<void*>(gs->perm_cols),
+                  static_cast<void*>(gs->perm_deg), static_cast<void*>(gs->perm_scols),
+                  static_cast<void*>(gs->perm_dst),
                   static_cast<void*>(gs->perm_bstart), static_cast<void*>(gs->perm_bnz0)})
     if (p) (void)hipFree(p);
   delete gs;
@@ -548,29 +597,35 @@ extern "C" bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_l
   return BS_OK;
 }
 
-extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, void* stream) {
+extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t sub,
+                                      void* stream) {
   const char* op = "bs_gs_order_rows";
   if (!gs) return fail(BS_ERR_INVALID_ARG, "%s: plan is NULL", op);
   if (mx < 1 || my < 1 || mz < 1 || tile < 1 || mx * my * mz != gs->n_global)
     return fail(BS_ERR_INVALID_ARG, "%s: need mx*my*mz == n_global and tile >= 1", op);
+  if (sub < 0) return fail(BS_ERR_INVALID_ARG, "%s: sub must be >= 0", op);
+  if (sub == 0 || sub > tile) sub = tile;
+  const int64_t ns = (tile + sub - 1) / sub;
   const int64_t ntiles = ((mx + tile - 1) / tile) * ((my + tile - 1) / tile) * ((mz + tile - 1) / tile);
-  if (ntiles >= 0xffffffffLL) return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
+  if (ns > 2048 || ntiles >= 0xffffffffLL / (ns * ns * ns))
+    return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
   if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 255)", op);
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(gs->device);
   int32_t* old_rows = gs->perm_rows;
   uint8_t* old_deg = gs->perm_deg;
-  int32_t* old_cols = gs->perm_cols;
+  int32_t* old_scols = gs->perm_scols;
+  uint16_t* old_dst = gs->perm_dst;
   int32_t* old_bstart = gs->perm_bstart;
   int32_t* old_bnz0 = gs->perm_bnz0;
   const int64_t zero_rows = gs->n_global - gs->n_nzrows;
   Builder B{op, static_cast<hipStream_t>(stream)};
-  const LatticeOrder lat{mx, my, mz, tile};
+  const LatticeOrder lat{mx, my, mz, tile, sub};
   build_gather_order(B, gs, zero_rows, &lat);
   if (B.ok()) {
-    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_deg), static_cast<void*>(old_cols),
-                    static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
+    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_deg), static_cast<void*>(old_scols),
+                    static_cast<void*>(old_dst), static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
       (void)hipFree(q);
   } else {
     gs->has_perm = true;  // the previous order is still in place

@@ -208,6 +208,31 @@ def test_many_empty_rows_and_long_rows(ctx):
         assert np.array_equal(bits(to_host(xG)), bits(ref)), variant
 
 
+@pytest.mark.parametrize("tile,sub", [(0, 0), (1000, 0), (1000, 37)])
+def test_gather_windows_near_the_stage_size(ctx, tile, sub):
+    # degrees 1..255 (the largest the permuted order takes), local copies in
+    # random order: windows of up to chunk + 254 = 2047 values, each loaded in
+    # address order and put back in CSR order; rows still add copies in
+    # ascending local index.  tile > 0 re-orders rows on a 1-D lattice.
+    rng = np.random.default_rng(17)
+    NG = 5000
+    deg = rng.integers(1, 256, NG)
+    deg[[0, 1, 2, NG // 2, NG - 1]] = 255
+    deg[rng.choice(NG, 300, replace=False)] = 0  # rows without copies
+    ref_map = rng.permutation(np.repeat(np.arange(NG), deg))
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
+    assert plan.max_degree == 255
+    if tile:
+        bs.bs_gs_order_rows(plan, NG, 1, 1, tile, sub)
+    rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+    xLh = bsgen.uniform(2, 11, ref_map.size)
+    ref = ops.gather(rs_ref, ci_ref, xLh)
+    with_variant(ctx, 0)
+    xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, torch.from_numpy(xLh).cuda(), xG)
+    assert np.array_equal(bits(to_host(xG)), bits(ref))
+
+
 def test_gather_scatter_deterministic(ctx):
     K, N = 10, 7
     E, NL, NG = mesh.sizes(K, N)
@@ -223,14 +248,16 @@ def test_gather_scatter_deterministic(ctx):
 
 
 @pytest.mark.parametrize("remap", [0, 4])
-@pytest.mark.parametrize("K,N,tile", [(6, 5, 1), (6, 5, 4), (7, 3, 7), (5, 7, 64), (9, 2, 5)])
-def test_gather_lattice_tiled_order(ctx, K, N, tile, remap):
+@pytest.mark.parametrize("K,N,tile,sub", [(6, 5, 1, 0), (6, 5, 4, 0), (7, 3, 7, 0), (5, 7, 64, 0), (9, 2, 5, 0),
+                                          (6, 5, 10, 5), (7, 3, 12, 6), (5, 7, 28, 14), (9, 2, 7, 3), (6, 7, 98, 14),
+                                          (4, 7, 5, 9)])
+def test_gather_lattice_tiled_order(ctx, K, N, tile, sub, remap):
     # the tiled row order changes which rows a workgroup adds, not how a row is summed
     E, NL, NG = mesh.sizes(K, N)
     d_map, ids = device_map(K, N, 5)
     plan = bs.bs_gs_create(ctx, d_map, NG)
     M = K * N + 1
-    bs.bs_gs_order_rows(plan, M, M, M, tile)
+    bs.bs_gs_order_rows(plan, M, M, M, tile, sub)
     with_variant(ctx, 0 + remap)
     xL = dev_uniform(NL, 11)
     xG = torch.empty(NG, dtype=torch.float64, device="cuda")
@@ -252,7 +279,11 @@ def test_gather_lattice_order_masked_and_errors(ctx):
         bs.bs_gs_order_rows(plan, M, M, M + 1, 4)
     with pytest.raises(bs.BSError):
         bs.bs_gs_order_rows(plan, M, M, M, 0)
-    bs.bs_gs_order_rows(plan, M, M, M, 3)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_rows(plan, M, M, M, 4, -1)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_rows(plan, M, M, M, 1 << 30, 1)  # more boxes than 32-bit keys hold
+    bs.bs_gs_order_rows(plan, M, M, M, 3, 2)
     with_variant(ctx, 0)
     xL = dev_uniform(NL, 11)
     xG = torch.full((NG,), 7.0, dtype=torch.float64, device="cuda")
