@@ -141,13 +141,18 @@ struct Args {
 
 // ---------------------------------------------------------------- chunk bodies
 
-template <class T, class F>
-__device__ __forceinline__ void each(const Chunk& ch, F f) {
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int e = threadIdx.x + kBlock * k;
-    if (e < ch.len) f(ch.start + e);
-  }
+// A chunk's elements are e = threadIdx.x + kBlock k (k < kPer).  Each body
+// issues every load of the chunk before it computes or stores anything (a
+// store between two loads would order them: the vectors may alias as far as
+// the compiler knows), with lanes past the chunk's end loading its last
+// element; results are then formed and stored for the elements inside the
+// chunk, in k order, so that sums add in the same order as an element-wise
+// loop would.
+__device__ __forceinline__ int64_t elem(const Chunk& ch, int k) {
+  return ch.start + min(static_cast<int32_t>(threadIdx.x) + kBlock * k, ch.len - 1);
+}
+__device__ __forceinline__ bool inside(const Chunk& ch, int k) {
+  return static_cast<int32_t>(threadIdx.x) + kBlock * k < ch.len;
 }
 
 // One pair per chunk.  The trailing barrier lets a workgroup call this again
@@ -169,24 +174,44 @@ __device__ __forceinline__ DW<double> widen(DW<C> a) {
 
 template <class T>
 __device__ void ch_copy(const Args<T>& a, const Chunk& ch) {
-  each<T>(ch, [&](int64_t e) { a.y[e] = a.x[e]; });
+  typename Storage<T>::E v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = a.x[elem(ch, k)];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) a.y[elem(ch, k)] = v[k];
 }
 
 template <class T>
 __device__ void ch_axpy(const Args<T>& a, const Chunk& ch) {
   using S = Storage<T>;
-  each<T>(ch, [&](int64_t e) { a.y[e] = S::store(a.alpha * S::load(a.x[e]) + a.beta * S::load(a.y[e])); });
+  typename S::E u[kPer], v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    u[k] = a.x[elem(ch, k)];
+    v[k] = a.y[elem(ch, k)];
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) a.y[elem(ch, k)] = S::store(a.alpha * S::load(u[k]) + a.beta * S::load(v[k]));
 }
 
 template <class T>
 __device__ void ch_norm(const Args<T>& a, const Chunk& ch, int64_t c) {
   using S = Storage<T>;
   using C = typename S::C;
+  typename S::E u[kPer], w[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    u[k] = a.xL[elem(ch, k)];
+    w[k] = a.wL[elem(ch, k)];
+  }
   DW<C> acc{C(0), C(0)};
-  each<T>(ch, [&](int64_t e) {
-    const C xk = S::load(a.xL[e]);
-    dev::dw_acc(acc, S::load(a.wL[e]) * (xk * xk));
-  });
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const C xk = S::load(u[k]);
+    if (inside(ch, k)) dev::dw_acc(acc, S::load(w[k]) * (xk * xk));
+  }
   put_pair(a.part_norm, c, widen(acc));
 }
 
@@ -195,8 +220,16 @@ __device__ void ch_dot(const typename Storage<T>::E* u, const typename Storage<T
                        const Chunk& ch, int64_t c) {
   using S = Storage<T>;
   using C = typename S::C;
+  typename S::E p[kPer], q[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    p[k] = u[elem(ch, k)];
+    q[k] = v[elem(ch, k)];
+  }
   DW<C> acc{C(0), C(0)};
-  each<T>(ch, [&](int64_t e) { dev::dw_acc_prod(acc, S::load(u[e]), S::load(v[e])); });
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) dev::dw_acc_prod(acc, S::load(p[k]), S::load(q[k]));
   put_pair(part, c, widen(acc));
 }
 
@@ -204,34 +237,90 @@ template <class T>
 __device__ void ch_update(const Args<T>& a, typename Storage<T>::C alpha, double* part, const Chunk& ch, int64_t c) {
   using S = Storage<T>;
   using C = typename S::C;
+  typename S::E xv[kPer], pv[kPer], rv[kPer], av[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t e = elem(ch, k);
+    xv[k] = a.x[e];
+    pv[k] = a.p[e];
+    rv[k] = a.r[e];
+    av[k] = a.Ap[e];
+  }
   DW<C> acc{C(0), C(0)};
-  each<T>(ch, [&](int64_t e) {
-    a.x[e] = S::store(S::load(a.x[e]) + alpha * S::load(a.p[e]));
-    const typename S::E rn = S::store(S::load(a.r[e]) - alpha * S::load(a.Ap[e]));
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!inside(ch, k)) continue;
+    const int64_t e = elem(ch, k);
+    a.x[e] = S::store(S::load(xv[k]) + alpha * S::load(pv[k]));
+    const typename S::E rn = S::store(S::load(rv[k]) - alpha * S::load(av[k]));
     a.r[e] = rn;
     const C rk = S::load(rn);
     dev::dw_acc_prod(acc, rk, rk);
-  });
+  }
   put_pair(part, c, widen(acc));
 }
 
 template <class T>
 __device__ void ch_scatter(const Args<T>& a, const typename Storage<T>::E* g, typename Storage<T>::E* l,
                            const Chunk& ch) {
-  each<T>(ch, [&](int64_t e) { l[e] = g[a.map[e]]; });
+  int32_t id[kPer];
+  typename Storage<T>::E v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) id[k] = a.map[elem(ch, k)];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) v[k] = g[id[k]];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) l[elem(ch, k)] = v[k];
 }
 
-// each row from +0.0, its local copies added in ascending local index
+// Each row from +0.0, its local copies added in ascending local index.  The
+// chunk's rows own the CSR positions [rs[first row], rs[last row + 1]);
+// these are walked in windows of kChunk: column ids loaded contiguously,
+// then every value of the window at once, staged in LDS, and each row adds
+// the copies it has in the window (a row's partial sum carries over to the
+// next window, so the additions keep their order).
 template <class T>
 __device__ void ch_gather(const Args<T>& a, const typename Storage<T>::E* l, typename Storage<T>::E* g,
                           const Chunk& ch) {
   using S = Storage<T>;
   using C = typename S::C;
-  each<T>(ch, [&](int64_t e) {
-    C s = C(0);
-    for (int32_t j = a.rs[e]; j < a.rs[e + 1]; ++j) s = s + S::load(l[a.ci[j]]);
-    g[e] = S::store(s);
-  });
+  __shared__ C stage[kChunk];
+  int32_t j0[kPer], j1[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t e = elem(ch, k);
+    j0[k] = a.rs[e];
+    j1[k] = a.rs[e + 1];
+  }
+  const int32_t n0 = a.rs[ch.start], n1 = a.rs[ch.start + ch.len];
+  C s[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) s[k] = C(0);
+  for (int32_t w0 = n0; w0 < n1; w0 += kChunk) {
+    const int32_t wn = min(kChunk, n1 - w0);
+    int32_t col[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) col[k] = a.ci[w0 + min(static_cast<int32_t>(threadIdx.x) + kBlock * k, wn - 1)];
+    typename S::E v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = l[col[k]];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t q = threadIdx.x + kBlock * k;
+      if (q < wn) stage[q] = S::load(v[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t lo = max(j0[k], w0), hi = min(j1[k], w0 + wn);
+      for (int32_t j = lo; j < hi; ++j) s[k] = s[k] + stage[j - w0];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) g[elem(ch, k)] = S::store(s[k]);
 }
 
 template <class T>
@@ -239,7 +328,15 @@ __device__ void ch_direction(const Args<T>& a, const Chunk& ch) {
   using S = Storage<T>;
   using C = typename S::C;
   const C b = static_cast<C>(a.out[ch.inst * kSlots + S_BETA]);
-  each<T>(ch, [&](int64_t e) { a.p[e] = S::store(C(1) * S::load(a.r[e]) + b * S::load(a.p[e])); });
+  typename S::E rv[kPer], pv[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    rv[k] = a.r[elem(ch, k)];
+    pv[k] = a.p[elem(ch, k)];
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (inside(ch, k)) a.p[elem(ch, k)] = S::store(C(1) * S::load(rv[k]) + b * S::load(pv[k]));
 }
 
 // Sum of one instance's chunk pairs in chunk order, by one wave; every lane
