@@ -15,7 +15,10 @@ Candidates:
   gather, scatter   kernel variant {0, 1, 2}, each with and without the XCD
                     renumbering, on permuted and oriented N = 7 meshes, with
                     plans as bs_gs_create builds them (a caller that applies
-                    bs_gs_order_rows chooses gather variant 0 itself)
+                    bs_gs_order_rows chooses gather variant 0 itself); for the
+                    scatter's tile variants (0, 1) also 1, 2 or 4 tiles per
+                    workgroup (the unroll field), for its map-order variant (2)
+                    1 or 4 entries per thread
 
 Each candidate is timed with HIP events around back-to-back calls on
 resident inputs (median of three trials after a warm-up).  A candidate
@@ -42,7 +45,7 @@ DTYPES = (("f64", 0), ("f32", 1), ("bf16", 2))
 BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 24, 1 << 26), (1 << 27, 1 << 28))
 MESH_K = ((0, 4), (1 << 20, 16), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
 DEFAULTS = {"copy": (1, 1 << 30, 0), "axpy": (1, 1 << 30, 0), "norm": (8, 4096, 0), "dot": (8, 4096, 0),
-            "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (1, 1 << 30, 1)}
+            "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (2, 1 << 30, 1)}
 MARGIN = 0.98
 
 
@@ -136,10 +139,12 @@ def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
                              ("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL))):
                 times = {}
                 for v in (0, 1, 2, 4, 5, 6):
-                    bs.bs_ctx_set_tune(ctx, op, 1, 1 << 30, v)
-                    times[(1, 1 << 30, v)] = _time(torch, call, reps)
-                    log.write(json.dumps({"op": op, "dtype": dname, "n_local": NL, "variant": v,
-                                          "ms": round(times[(1, 1 << 30, v)], 5)}) + "\n")
+                    unrolls = (1,) if op == "gather" else ((1, 2, 4) if v % 4 < 2 else (1, 4))
+                    for u in unrolls:
+                        bs.bs_ctx_set_tune(ctx, op, u, 1 << 30, v)
+                        times[(u, 1 << 30, v)] = _time(torch, call, reps)
+                        log.write(json.dumps({"op": op, "dtype": dname, "n_local": NL, "unroll": u, "variant": v,
+                                              "ms": round(times[(u, 1 << 30, v)], 5)}) + "\n")
                 choice = _pick(times, DEFAULTS[op])
                 entries[(op, dname)].append((op, dname, n_min, *choice))
                 bs.bs_ctx_set_tune(ctx, op, *DEFAULTS[op])

@@ -269,75 +269,103 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ r
 
 // ---------------------------------------------------------------- BS7 scatter, sorted tiles
 
-template <class E>
+// A workgroup takes TPW consecutive tiles of the visiting order.  Within a
+// tile the (global id, local offset) pairs are read in ascending global id,
+// the values fetched in that order and put in place through LDS, and the
+// tile's entries are written contiguously.
+template <class E, int TPW>
 __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __restrict__ order,
                                                            const int32_t* __restrict__ tgid,
                                                            const uint16_t* __restrict__ tloc,
                                                            const int32_t* __restrict__ tcnt, const E* __restrict__ xG,
-                                                           E* __restrict__ xL, int64_t n_local, bool remap) {
+                                                           E* __restrict__ xL, int64_t n_local, int64_t n_tiles,
+                                                           bool remap) {
   constexpr int P = kTile / kBlock;
-  __shared__ E val[kTile];
-  __shared__ uint8_t has[kTile];
-  const int64_t tile = order[remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x];
-  const int64_t base = tile * kTile;
-  const int cnt = tcnt[tile];
-  const int64_t rem = n_local - base;
-  const int ntile = rem < kTile ? static_cast<int>(rem) : kTile;
-  const bool full = cnt == ntile;  // no masked entry: every slot gets a value
-  if (!full) {
+  __shared__ E val[TPW][kTile];
+  __shared__ uint8_t has[TPW][kTile];
+  const int64_t t0 = static_cast<int64_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * TPW;
+  int64_t tile[TPW];
+  int cnt[TPW];
 #pragma unroll
-    for (int k = 0; k < P; ++k) has[threadIdx.x + k * kBlock] = 0;
-    __syncthreads();
-  }
-  int32_t g[P];
-  uint16_t o[P];
-  E v[P];
+  for (int i = 0; i < TPW; ++i) tile[i] = order[min(t0 + i, n_tiles - 1)];
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const int q = threadIdx.x + k * kBlock;
-    g[k] = (q < cnt) ? dev::ld_nt(tgid + base + q) : -1;
-    o[k] = (q < cnt) ? dev::ld_nt(tloc + base + q) : 0;
-  }
+  for (int i = 0; i < TPW; ++i) cnt[i] = (t0 + i < n_tiles) ? tcnt[tile[i]] : 0;
 #pragma unroll
-  for (int k = 0; k < P; ++k)
-    if (g[k] >= 0) v[k] = xG[g[k]];
+  for (int i = 0; i < TPW; ++i)
 #pragma unroll
-  for (int k = 0; k < P; ++k)
-    if (g[k] >= 0) {
-      val[o[k]] = v[k];
-      if (!full) has[o[k]] = 1;
+    for (int k = 0; k < P; ++k) has[i][threadIdx.x + k * kBlock] = 0;
+  int32_t g[TPW][P];
+  uint16_t o[TPW][P];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int q = min(static_cast<int>(threadIdx.x) + k * kBlock, kTile - 1);
+      g[i][k] = dev::ld_nt(tgid + tile[i] * kTile + q);
+      o[i][k] = dev::ld_nt(tloc + tile[i] * kTile + q);
     }
+  E v[TPW][P];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int q = threadIdx.x + k * kBlock;
+      v[i][k] = xG[q < cnt[i] ? g[i][k] : 0];
+    }
+  __syncthreads();  // has[] cleared
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (static_cast<int>(threadIdx.x) + k * kBlock < cnt[i]) {
+        val[i][o[i][k]] = v[i][k];
+        has[i][o[i][k]] = 1;
+      }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const int q = threadIdx.x + k * kBlock;
-    if (q < ntile && (full || has[q])) dev::st_nt(xL + base + q, val[q]);
+  for (int i = 0; i < TPW; ++i) {
+    const int64_t base = tile[i] * kTile;
+    const int64_t rem = n_local - base;
+    const int ntile = (t0 + i < n_tiles) ? (rem < kTile ? static_cast<int>(rem) : kTile) : 0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int q = threadIdx.x + k * kBlock;
+      if (q < ntile && has[i][q]) dev::st_nt(xL + base + q, val[i][q]);
+    }
   }
 }
 
 // ---------------------------------------------------------------- BS7 scatter, tiles in local order
 
-template <class E>
+// A workgroup takes TPW consecutive tiles of the visiting order and copies
+// xG[map[l]] to xL[l] over each: ids first, then values, then stores.
+template <class E, int TPW>
 __global__ __launch_bounds__(kBlock) void k_scatter_tiles(const int32_t* __restrict__ map,
                                                           const int32_t* __restrict__ order,
                                                           const E* __restrict__ xG, E* __restrict__ xL,
-                                                          int64_t n_local, bool remap) {
+                                                          int64_t n_local, int64_t n_tiles, bool remap) {
   constexpr int P = kTile / kBlock;
-  const uint32_t t = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int64_t l0 = static_cast<int64_t>(order[t]) * kTile + threadIdx.x;
-  int32_t id[P];
-  E v[P];
+  const int64_t t0 = static_cast<int64_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * TPW;
+  int64_t l0[TPW];
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const int64_t l = l0 + k * kBlock;
-    id[k] = (l < n_local) ? dev::ld_nt(map + l) : -1;
-  }
+  for (int i = 0; i < TPW; ++i) l0[i] = static_cast<int64_t>(order[min(t0 + i, n_tiles - 1)]) * kTile + threadIdx.x;
+  int32_t id[TPW][P];
 #pragma unroll
-  for (int k = 0; k < P; ++k)
-    if (id[k] >= 0) v[k] = xG[id[k]];
+  for (int i = 0; i < TPW; ++i)
 #pragma unroll
-  for (int k = 0; k < P; ++k)
-    if (id[k] >= 0) dev::st_nt(xL + l0 + k * kBlock, v[k]);
+    for (int k = 0; k < P; ++k) id[i][k] = dev::ld_nt(map + min(l0[i] + k * kBlock, n_local - 1));
+  E v[TPW][P];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[i][k] = xG[max(id[i][k], 0)];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int64_t l = l0[i] + k * kBlock;
+      if (t0 + i < n_tiles && l < n_local && id[i][k] >= 0) dev::st_nt(xL + l, v[i][k]);
+    }
 }
 
 // ---------------------------------------------------------------- BS7 scatter, local order
@@ -403,19 +431,43 @@ void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipS
                      static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local);
 }
 
+template <class E, int TPW>
+void launch_scatter_sorted(const bs_gs* gs, bool remap, const void* xG, void* xL, hipStream_t st) {
+  const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
+  hipLaunchKernelGGL((k_scatter_sorted<E, TPW>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order, gs->tile_gid,
+                     gs->tile_loc, gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
+                     gs->n_tiles, remap);
+}
+
+template <class E, int TPW>
+void launch_scatter_tiles(const bs_gs* gs, bool remap, const void* xG, void* xL, hipStream_t st) {
+  const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
+  hipLaunchKernelGGL((k_scatter_tiles<E, TPW>), dim3(grid), dim3(kBlock), 0, st, gs->map, gs->tile_order,
+                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local, gs->n_tiles, remap);
+}
+
 template <class T>
 bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hipStream_t st) {
   using E = typename Storage<T>::E;
   const Tune& tn = tune_for(ctx, OP_SCATTER, dtype_index<T>(), gs->n_local);
   const bool remap = (tn.variant & kNoXcdRemap) == 0;
   const int kind = tn.variant & kVariantMask;
-  const dim3 tiles(static_cast<unsigned int>(gs->n_tiles));
-  if (kind == 0) {
-    hipLaunchKernelGGL((k_scatter_sorted<E>), tiles, dim3(kBlock), 0, st, gs->tile_order, gs->tile_gid, gs->tile_loc,
-                       gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local, remap);
-  } else if (kind == 1) {
-    hipLaunchKernelGGL((k_scatter_tiles<E>), tiles, dim3(kBlock), 0, st, gs->map, gs->tile_order,
-                       static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local, remap);
+  if (kind <= 1) {
+    // tiles per workgroup: the tune entry's unroll, rounded down to 1, 2 or 4
+    const int tpw = tn.unroll >= 4 ? 4 : tn.unroll >= 2 ? 2 : 1;
+    // (with no global entries every local entry is masked: nothing to write,
+    // and the kernels' padding lanes read xG[0])
+    if (gs->n_tiles > 0 && gs->n_global > 0) {
+      if (kind == 0) {
+        if (tpw == 4) launch_scatter_sorted<E, 4>(gs, remap, xG, xL, st);
+        else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, remap, xG, xL, st);
+        else launch_scatter_sorted<E, 1>(gs, remap, xG, xL, st);
+      } else {
+        if (tpw == 4) launch_scatter_tiles<E, 4>(gs, remap, xG, xL, st);
+        else if (tpw == 2) launch_scatter_tiles<E, 2>(gs, remap, xG, xL, st);
+        else launch_scatter_tiles<E, 1>(gs, remap, xG, xL, st);
+      }
+    }
   } else if (tn.unroll >= 8) {
     launch_scatter_map<E, 8>(gs, tn.grid_cap, xG, xL, st);
   } else if (tn.unroll >= 4) {

@@ -95,9 +95,10 @@ void set_defaults(bs_ctx* c) {
     set_one(c->tune[OP_NORM][d], Tune{8, 4096, 0});
     set_one(c->tune[OP_DOT][d], Tune{8, 4096, 0});
     set_one(c->tune[OP_CG_UPDATE][d], Tune{4, kMaxReduceBlocks, 0});
-    // gather: rows in global order; scatter: tiles read in local order
+    // gather: rows in global order; scatter: tiles read in local order, two
+    // tiles per workgroup
     set_one(c->tune[OP_GATHER][d], Tune{1, 1 << 30, 1});
-    set_one(c->tune[OP_SCATTER][d], Tune{1, 1 << 30, 1});
+    set_one(c->tune[OP_SCATTER][d], Tune{2, 1 << 30, 1});
   }
 }
 

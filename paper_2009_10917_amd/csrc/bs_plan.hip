@@ -472,7 +472,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.need(prs, (nz + 1) * 4, "row starts");
   B.need(pcols, gs->n_unmasked * 4, "columns");
   if (!B.ok()) return;
-  hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
+  if (ng > 0) hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
   if (lat) {
     const int64_t ntx = (lat->mx + lat->tile - 1) / lat->tile, nty = (lat->my + lat->tile - 1) / lat->tile;
     const int64_t ns = (lat->tile + lat->sub - 1) / lat->sub;
@@ -482,7 +482,8 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   } else {
     if (nt > 0)
       hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
+    if (ng > 0)
+      hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
     if (nl > 0)
       hipLaunchKernelGGL(k_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, rank.as<int32_t>(),
                          rkey.as<uint32_t>());

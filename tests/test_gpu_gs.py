@@ -188,6 +188,37 @@ def test_scatter_map_order_unrolls(ctx, unroll):
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
 
+@pytest.mark.parametrize("variant", [0, 1, 4, 5])
+@pytest.mark.parametrize("tpw", [1, 2, 4, 8])
+def test_scatter_tiles_per_workgroup(ctx, variant, tpw):
+    # tile variants take 1, 2 or 4 tiles of the visiting order per workgroup
+    # (the tune entry's unroll; 8 rounds down to 4); 7^3 elements of degree 3
+    # give 7^3/8 = 42.9 tiles, so the last workgroup holds a partial tile and
+    # missing ones
+    K, N = 7, 3
+    E, NL, NG = mesh.sizes(K, N)
+    _, ref_map = device_map(K, N, 13)
+    ref_map = ref_map.copy()
+    ref_map[5::9] = -1
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
+    bs.bs_ctx_set_tune(ctx, "scatter", tpw, 1 << 30, variant)
+    xL = dev_uniform(NL, 11)
+    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
+    assert np.array_equal(bits(to_host(xL)), bits(ref))
+
+
+def test_scatter_with_no_global_entries(ctx):
+    # every local entry masked: nothing is written, whatever the variant
+    ref_map = np.full(1000, -1, dtype=np.int32)
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map).cuda(), 0)
+    for variant in (0, 1, 2):
+        bs.bs_ctx_set_tune(ctx, "scatter", 4, 1 << 30, variant)
+        xL = torch.full((1000,), 3.0, dtype=torch.float64, device="cuda")
+        bs.bs_scatter(ctx, plan, torch.empty(0, dtype=torch.float64, device="cuda"), xL)
+        assert np.array_equal(to_host(xL), np.full(1000, 3.0))
+
+
 def test_many_empty_rows_and_long_rows(ctx):
     # globals with no copies between used ones, plus a few very long rows:
     # exercises blocks with many rows and windows that rows overrun
