@@ -59,16 +59,17 @@ __device__ __forceinline__ C row_sum(const C* v, int32_t a, int32_t e) {
 }
 
 // A workgroup owns the rows of one block and the CSR window of their
-// nonzeros (at most kStage).  The window's local values are loaded in
-// ascending local index (the plan stores each window's column ids sorted),
-// so that lanes of one load share cache lines, and each value is put in LDS
-// at its CSR offset; every row then adds its copies from LDS in CSR order,
-// i.e. in ascending local index, as the definition of x_G = Z^T x_L does.
+// nonzeros (at most kStage).  The plan stores the window in ascending local
+// index, one word per entry (segment rank, column mod 512, CSR offset,
+// row-start bit), so that lanes of one load share cache lines; each value is
+// put in LDS at its CSR offset, the rows' starts are recovered from the
+// row-start bits, and every row adds its copies from LDS in CSR order, i.e.
+// in ascending local index, as the definition of x_G = Z^T x_L does.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restrict__ scols,
-                                                        const uint16_t* __restrict__ sdst,
+__global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restrict__ words,
+                                                        const int32_t* __restrict__ segs,
+                                                        const int32_t* __restrict__ segoff,
                                                         const int32_t* __restrict__ prows,
-                                                        const uint8_t* __restrict__ pdeg,
                                                         const int32_t* __restrict__ pbstart,
                                                         const int32_t* __restrict__ pbnz0,
                                                         const typename Storage<T>::E* __restrict__ xL,
@@ -76,48 +77,52 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restric
                                                         int64_t n_nzrows, int64_t n_rows, bool remap) {
   using S = Storage<T>;
   using C = typename S::C;
+  using E = typename S::E;
   constexpr int L = kStage / kBlock;
-  __shared__ C lds[kStage];            // the window's local values, CSR order
-  __shared__ int32_t sst[kStage + 1];  // row starts relative to the window
+  static_assert(L == 8, "a thread scans the row-start bytes of 8 offsets as one word");
+  __shared__ C lds[kStage];                   // the window's local values, CSR order
+  __shared__ int32_t sst[kStage + 1];         // the window's segment ids, then its row starts
+  __shared__ uint64_t first64[kStage / 8];    // row-start byte per CSR offset
   __shared__ int32_t wsum[kBlock / 64];
+  uint8_t* first = reinterpret_cast<uint8_t*>(first64);
+  const int t = threadIdx.x;
   const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (b >= n_pblocks) {  // rows without copies: +0.0
-    const int64_t q = n_nzrows + (b - n_pblocks) * kBlock + threadIdx.x;
+    const int64_t q = n_nzrows + (b - n_pblocks) * kBlock + t;
     if (q < n_rows) dev::st_nt(xG + prows[q], S::store(C(0)));
     return;
   }
   const int64_t w0 = pbnz0[b];
   const int32_t n = static_cast<int32_t>(pbnz0[b + 1] - w0);  // <= kStage
   if (n == 0) return;  // a trailing block whose range holds no row start
-  // 1. the window's values in address order, with their CSR offsets: all
-  //    index loads first, then all value loads (lanes past the window repeat
-  //    its last entry, so that no load waits behind a branch)
-  int32_t col[L], slot[L];
+  const int32_t s0 = segoff[b], ns = segoff[b + 1] - s0;      // <= n
+  const int32_t r0 = pbstart[b], nrows = pbstart[b + 1] - r0;  // in [1, n]
+  // 1. the window's words, its segment ids, and the global ids of the rows
+  //    this thread adds in step 5 (q = t + k kBlock); lanes past the end
+  //    repeat the last entry, so that no load waits behind a branch
+  uint32_t wd[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) {
-    const int32_t t = min(static_cast<int32_t>(threadIdx.x) + k * kBlock, n - 1);
-    col[k] = dev::ld_nt(scols + w0 + t);
-    slot[k] = dev::ld_nt(sdst + w0 + t);
-  }
-  C v[L];
+  for (int k = 0; k < L; ++k) wd[k] = dev::ld_nt(words + w0 + min(t + k * kBlock, n - 1));
+  int32_t gid[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) v[k] = S::load(xL[col[k]]);
-  // 2. meanwhile the block's rows: degrees of rows t*L .. t*L+L-1, scanned
-  const int32_t r0 = pbstart[b], r1 = pbstart[b + 1];
-  const int32_t nrows = r1 - r0;  // in [1, n]: every row has a copy
-  int32_t d[L], gid[L];
+  for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(t + k * kBlock, nrows - 1)];
+  for (int i = t; i < ns; i += kBlock) sst[i] = segs[s0 + i];
 #pragma unroll
-  for (int i = 0; i < L; ++i) d[i] = pdeg[r0 + min(static_cast<int32_t>(threadIdx.x) * L + i, nrows - 1)];
-  // and the global ids of the rows this thread adds in step 3 (q = t + k kBlock)
+  for (int k = 0; k < L; ++k)
+    if (t + k * kBlock < n) first[(wd[k] >> 1) & 2047u] = static_cast<uint8_t>(wd[k] & 1u);
+  __syncthreads();
+  // 2. the values, in address order
+  E v[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(static_cast<int32_t>(threadIdx.x) + k * kBlock, nrows - 1)];
+  for (int k = 0; k < L; ++k)
+    v[k] = xL[static_cast<int64_t>(sst[wd[k] >> 21]) * 512 + ((wd[k] >> 12) & 511u)];
+  // 3. meanwhile the row starts: thread t reads the row-start bytes of
+  //    offsets t*L .. t*L+L-1 (every offset below n was written once)
+  const uint64_t fl = first64[t];
   int32_t tsum = 0;
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    if (static_cast<int32_t>(threadIdx.x) * L + i >= nrows) d[i] = 0;
-    tsum += d[i];
-  }
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (int i = 0; i < L; ++i) tsum += (t * L + i < n) ? static_cast<int32_t>((fl >> (8 * i)) & 1u) : 0;
+  const int lane = t % 64, w = t / 64;
   int32_t incl = tsum;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -125,26 +130,24 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const int32_t* __restric
     if (lane >= off) incl += y;
   }
   if (lane == 63) wsum[w] = incl;
-#pragma unroll
-  for (int k = 0; k < L; ++k)
-    if (static_cast<int32_t>(threadIdx.x) + k * kBlock < n) lds[slot[k]] = v[k];
-  __syncthreads();
+  __syncthreads();  // also: every segment id has been read
   int32_t before = 0;
 #pragma unroll
   for (int i = 0; i < kBlock / 64; ++i) before += (i < w) ? wsum[i] : 0;
-  int32_t pos = before + incl - tsum;
+  int32_t row = before + incl - tsum;
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const int32_t q = threadIdx.x * L + i;
-    if (q < nrows) sst[q] = pos;
-    pos += d[i];
-  }
-  if (threadIdx.x == 0) sst[nrows] = n;
+  for (int i = 0; i < L; ++i)
+    if (t * L + i < n && ((fl >> (8 * i)) & 1u)) sst[row++] = t * L + i;
+  if (t == 0) sst[nrows] = n;
+  // 4. the values into LDS at their CSR offsets
+#pragma unroll
+  for (int k = 0; k < L; ++k)
+    if (t + k * kBlock < n) lds[(wd[k] >> 1) & 2047u] = S::load(v[k]);
   __syncthreads();
-  // 3. each thread adds whole rows in CSR order
+  // 5. each thread adds whole rows in CSR order
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    const int32_t q = threadIdx.x + k * kBlock;
+    const int32_t q = t + k * kBlock;
     if (q < nrows) dev::st_nt(xG + gid[k], S::store(row_sum<C>(lds, sst[q], sst[q + 1])));
   }
 }
@@ -407,7 +410,7 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
     const int64_t grid = gs->n_pblocks + zero_blocks;
     if (grid > 0)
       hipLaunchKernelGGL((k_gather_perm<T>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
-                         gs->perm_scols, gs->perm_dst, gs->perm_rows, gs->perm_deg, gs->perm_bstart, gs->perm_bnz0,
+                         gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_bstart, gs->perm_bnz0,
                          static_cast<const E*>(xL), static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global,
                          remap);
   } else if (kind == 1) {

@@ -113,21 +113,23 @@ struct bs_gs {
 
   // Gather, rows in a permuted order: by default grouped by the first tile
   // (in tile_order) that holds one of their copies, or in lattice blocks
-  // (bs_gs_order_rows); perm_rows lists rows with copies first (perm_deg
-  // copies each), then rows without copies.  Nonzero-balanced blocks as
-  // above: block b adds rows [perm_bstart[b], perm_bstart[b+1]), whose
-  // nonzeros are the CSR positions [perm_bnz0[b], perm_bnz0[b+1]) (at most
-  // kStage of them, since chunk + max_degree <= kStage).  Within that
-  // window the column ids are stored sorted (perm_scols, so that a block
-  // reads its local values in address order) with, for each, its position
-  // in the window's CSR order (perm_dst; rows list their copies in
-  // ascending local index).  Built only when every degree fits in a byte
-  // (has_perm).
+  // (bs_gs_order_rows); perm_rows lists rows with copies first, then rows
+  // without copies.  Nonzero-balanced blocks as above: block b adds rows
+  // [perm_bstart[b], perm_bstart[b+1]), whose nonzeros are the CSR positions
+  // [perm_bnz0[b], perm_bnz0[b+1]) (at most kStage of them, since chunk +
+  // max_degree <= kStage).  Each window is stored in ascending column id
+  // (so that a block reads its local values in address order), one word per
+  // entry: the rank of the column's 512-entry segment among the window's
+  // segments (bits 21..31; the segment ids are perm_segs[perm_segoff[b] +
+  // rank]), the column mod 512 (bits 12..20), the entry's CSR offset in the
+  // window (bits 1..11; rows list their copies in ascending local index) and
+  // whether that offset starts a row (bit 0).  Built only when every degree
+  // fits in a byte (has_perm).
   bool has_perm;
   int32_t* perm_rows;    // [n_global]
-  uint8_t* perm_deg;     // [n_nzrows]
-  int32_t* perm_scols;   // [n_unmasked]
-  uint16_t* perm_dst;    // [n_unmasked]
+  uint32_t* perm_words;  // [n_unmasked]
+  int32_t* perm_segs;    // [perm_segoff[n_pblocks]]
+  int32_t* perm_segoff;  // [n_pblocks + 1]
   int32_t* perm_bstart;  // [n_pblocks + 1]
   int32_t* perm_bnz0;    // [n_pblocks + 1]
   int64_t n_nzrows;

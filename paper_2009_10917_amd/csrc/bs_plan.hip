@@ -212,20 +212,36 @@ __global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restri
   key[g] = static_cast<uint32_t>(t * ns * ns * ns + b);
 }
 
-// Per gather block: the column ids of its window [bnz0[b], bnz0[b+1])
-// (at most kStage) sorted ascending, each with its offset in the window
-// (a bitonic sort of (column, offset) keys in LDS).
-__global__ __launch_bounds__(kBlock) void k_window_sort(const int32_t* __restrict__ cols,
+// Per gather block: the entries of its window [bnz0[b], bnz0[b+1]) (at most
+// kStage) in ascending column id, each packed into one word (the layout the
+// gather kernel reads):
+//   bits 21..31  rank of the column's 512-entry segment among the window's
+//                distinct segments (ascending),
+//   bits 12..20  column mod 512,
+//   bits  1..11  the entry's offset in the window (its CSR position),
+//   bit   0      set when that CSR position starts a row.
+// Also the sorted column ids (scols, for the segment list) and the number of
+// distinct segments (nseg).  A bitonic sort of (column, offset) keys in LDS.
+__global__ __launch_bounds__(kBlock) void k_window_pack(const int32_t* __restrict__ cols,
+                                                        const int32_t* __restrict__ prs,
+                                                        const int32_t* __restrict__ bstart,
                                                         const int32_t* __restrict__ bnz0, int32_t* __restrict__ scols,
-                                                        uint16_t* __restrict__ dst) {
-  static_assert((kStage & (kStage - 1)) == 0 && kStage <= 65536, "window offsets are 16-bit, sort size a power of 2");
+                                                        uint32_t* __restrict__ words, int32_t* __restrict__ nseg) {
+  static_assert(kStage == 2048 && kStage == 8 * kBlock, "window offsets and segment ranks take 11 bits");
+  constexpr int L = kStage / kBlock;
   __shared__ uint64_t key[kStage];
+  __shared__ uint8_t first[kStage];
+  __shared__ int32_t wsum[kBlock / 64];
   const int64_t a = bnz0[blockIdx.x];
   const int32_t n = static_cast<int32_t>(bnz0[blockIdx.x + 1] - a);
-  for (int t = threadIdx.x; t < kStage; t += kBlock)
+  for (int t = threadIdx.x; t < kStage; t += kBlock) {
     key[t] = (t < n) ? (static_cast<uint64_t>(static_cast<uint32_t>(cols[a + t])) << 16) | static_cast<uint64_t>(t)
                      : ~0ull;
+    first[t] = 0;
+  }
   __syncthreads();
+  for (int32_t r = bstart[blockIdx.x] + threadIdx.x; r < bstart[blockIdx.x + 1]; r += kBlock)
+    first[prs[r] - a] = 1;
   for (int k = 2; k <= kStage; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int t = threadIdx.x; t < kStage; t += kBlock) {
@@ -241,16 +257,63 @@ __global__ __launch_bounds__(kBlock) void k_window_sort(const int32_t* __restric
       __syncthreads();
     }
   }
-  for (int t = threadIdx.x; t < n; t += kBlock) {
-    scols[a + t] = static_cast<int32_t>(key[t] >> 16);
-    dst[a + t] = static_cast<uint16_t>(key[t] & 0xffffu);
+  // segment ranks: thread t owns sorted entries t*L .. t*L+L-1
+  const int i0 = threadIdx.x * L;
+  int32_t prev = (i0 > 0 && i0 - 1 < n) ? static_cast<int32_t>(key[i0 - 1] >> 16) : -1;
+  int32_t c[L];
+  bool fresh[L];
+  int32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    c[i] = (i0 + i < n) ? static_cast<int32_t>(key[i0 + i] >> 16) : -1;
+    fresh[i] = (i0 + i < n) && (prev < 0 || (c[i] >> 9) != (prev >> 9));
+    prev = c[i];
+    cnt += fresh[i];
+  }
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  int32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    before += (i < w) ? wsum[i] : 0;
+    total += wsum[i];
+  }
+  int32_t seen = before + incl - cnt;  // distinct segments before entry i0
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    if (i0 + i >= n) break;
+    seen += fresh[i];
+    const uint32_t off = static_cast<uint32_t>(key[i0 + i] & 0xffffu);
+    words[a + i0 + i] = (static_cast<uint32_t>(seen - 1) << 21) | ((static_cast<uint32_t>(c[i]) & 511u) << 12) |
+                        (off << 1) | static_cast<uint32_t>(first[off]);
+    scols[a + i0 + i] = c[i];
+  }
+  if (threadIdx.x == 0) nseg[blockIdx.x] = total;
+}
+
+// The segment list of each window: segs[segoff[b] + rank] = segment id.
+__global__ __launch_bounds__(kBlock) void k_window_segs(const int32_t* __restrict__ scols,
+                                                        const uint32_t* __restrict__ words,
+                                                        const int32_t* __restrict__ bnz0,
+                                                        const int32_t* __restrict__ segoff, int32_t* __restrict__ segs) {
+  const int64_t a = bnz0[blockIdx.x];
+  const int32_t n = static_cast<int32_t>(bnz0[blockIdx.x + 1] - a);
+  for (int32_t i = threadIdx.x; i < n; i += kBlock) {
+    const int32_t c = scols[a + i];
+    if (i == 0 || (scols[a + i - 1] >> 9) != (c >> 9)) segs[segoff[blockIdx.x] + (words[a + i] >> 21)] = c >> 9;
   }
 }
 
-// Degrees of the rows in visiting order (byte and int copies).
+// Degrees of the rows in visiting order.
 __global__ __launch_bounds__(kBlock) void k_perm_degrees(const int32_t* __restrict__ rows, int64_t n_nzrows,
-                                                         const int32_t* __restrict__ rs, uint8_t* __restrict__ d8,
-                                                         int32_t* __restrict__ d32) {
+                                                         const int32_t* __restrict__ rs, int32_t* __restrict__ d32) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (k > n_nzrows) return;
   if (k == n_nzrows) {
@@ -258,9 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_perm_degrees(const int32_t* __restri
     return;
   }
   const int32_t g = rows[k];
-  const int32_t d = rs[g + 1] - rs[g];
-  d8[k] = static_cast<uint8_t>(d);
-  d32[k] = d;
+  d32[k] = rs[g + 1] - rs[g];
 }
 
 // Columns of the rows in visiting order.
@@ -461,13 +522,12 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   if (gs->max_degree > 255) return;  // degrees are stored in bytes
   const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
   const int64_t nz = ng - n_zero_rows;  // rows with copies
-  DevBuf rank, rkey, rkey_out, rows0, rows, d8, d32, prs, pcols, scols, dst, bstart, bnz0;
+  DevBuf rank, rkey, rkey_out, rows0, rows, d32, prs, pcols, scols, words, nseg, segoff, segs, bstart, bnz0;
   B.need(rank, nt * 4, "tile ranks");
   B.need(rkey, ng * 4, "row keys");
   B.need(rkey_out, ng * 4, "row keys");
   B.need(rows0, ng * 4, "rows");
   B.need(rows, ng * 4, "row order");
-  B.need(d8, nz, "degrees");
   B.need(d32, (nz + 1) * 4, "degrees");
   B.need(prs, (nz + 1) * 4, "row starts");
   B.need(pcols, gs->n_unmasked * 4, "columns");
@@ -499,7 +559,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
     });
   }
   hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(nz + 1)), dim3(kBlock), 0, B.st, rows.as<int32_t>(), nz,
-                     gs->row_starts, d8.as<uint8_t>(), d32.as<int32_t>());
+                     gs->row_starts, d32.as<int32_t>());
   B.launched();
   int32_t* dp = d32.as<int32_t>();
   int32_t* pp = prs.as<int32_t>();
@@ -512,20 +572,34 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.need(bstart, (nb + 1) * 4, "block starts");
   B.need(bnz0, (nb + 1) * 4, "block offsets");
   B.need(scols, gs->n_unmasked * 4, "sorted columns");
-  B.need(dst, gs->n_unmasked * 2, "window offsets");
+  B.need(words, gs->n_unmasked * 4, "window words");
+  B.need(nseg, (nb + 1) * 4, "segment counts");
+  B.need(segoff, (nb + 1) * 4, "segment offsets");
   if (!B.ok()) return;
   hipLaunchKernelGGL(k_block_starts, dim3(blocks_for(nb + 1)), dim3(kBlock), 0, B.st, prs.as<int32_t>(), nz, gs->chunk,
                      nb, bstart.as<int32_t>(), bnz0.as<int32_t>());
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nb + 1)), dim3(kBlock), 0, B.st, nseg.as<int32_t>(), nb + 1, 0);
   if (nb > 0)
-    hipLaunchKernelGGL(k_window_sort, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, pcols.as<int32_t>(),
-                       bnz0.as<int32_t>(), scols.as<int32_t>(), dst.as<uint16_t>());
+    hipLaunchKernelGGL(k_window_pack, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, pcols.as<int32_t>(),
+                       prs.as<int32_t>(), bstart.as<int32_t>(), bnz0.as<int32_t>(), scols.as<int32_t>(),
+                       words.as<uint32_t>(), nseg.as<int32_t>());
+  B.launched();
+  int32_t* ns = nseg.as<int32_t>();
+  int32_t* so = segoff.as<int32_t>();
+  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, ns, so, static_cast<int>(nb + 1), B.st); });
+  const int64_t total_segs = B.ok() ? static_cast<int64_t>(B.read(so + nb)) : 0;
+  B.need(segs, (total_segs > 0 ? total_segs : 1) * 4, "window segments");
+  if (!B.ok()) return;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_window_segs, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, scols.as<int32_t>(),
+                       words.as<uint32_t>(), bnz0.as<int32_t>(), so, segs.as<int32_t>());
   B.launched();
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
   gs->perm_rows = rows.release<int32_t>();
-  gs->perm_deg = d8.release<uint8_t>();
-  gs->perm_scols = scols.release<int32_t>();
-  gs->perm_dst = dst.release<uint16_t>();
+  gs->perm_words = words.release<uint32_t>();
+  gs->perm_segs = segs.release<int32_t>();
+  gs->perm_segoff = segoff.release<int32_t>();
   gs->perm_bstart = bstart.release<int32_t>();
   gs->perm_bnz0 = bnz0.release<int32_t>();
   gs->n_nzrows = nz;
@@ -541,8 +615,8 @@ void free_plan(bs_gs* gs) {
                   static_cast<void*>(gs->block_starts), static_cast<void*>(gs->tile_order),
                   static_cast<void*>(gs->tile_gid), static_cast<void*>(gs->tile_loc),
                   static_cast<void*>(gs->tile_count), static_cast<void*>(gs->perm_rows),
-                  static_cast<void*>(gs->perm_deg), static_cast<void*>(gs->perm_scols),
-                  static_cast<void*>(gs->perm_dst),
+                  static_cast<void*>(gs->perm_words), static_cast<void*>(gs->perm_segs),
+                  static_cast<void*>(gs->perm_segoff),
                   static_cast<void*>(gs->perm_bstart), static_cast<void*>(gs->perm_bnz0)})
     if (p) (void)hipFree(p);
   delete gs;
@@ -615,9 +689,9 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(gs->device);
   int32_t* old_rows = gs->perm_rows;
-  uint8_t* old_deg = gs->perm_deg;
-  int32_t* old_scols = gs->perm_scols;
-  uint16_t* old_dst = gs->perm_dst;
+  uint32_t* old_words = gs->perm_words;
+  int32_t* old_segs = gs->perm_segs;
+  int32_t* old_segoff = gs->perm_segoff;
   int32_t* old_bstart = gs->perm_bstart;
   int32_t* old_bnz0 = gs->perm_bnz0;
   const int64_t zero_rows = gs->n_global - gs->n_nzrows;
@@ -625,8 +699,8 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   const LatticeOrder lat{mx, my, mz, tile, sub};
   build_gather_order(B, gs, zero_rows, &lat);
   if (B.ok()) {
-    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_deg), static_cast<void*>(old_scols),
-                    static_cast<void*>(old_dst), static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
+    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_words), static_cast<void*>(old_segs),
+                    static_cast<void*>(old_segoff), static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
       (void)hipFree(q);
   } else {
     gs->has_perm = true;  // the previous order is still in place
