@@ -70,6 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
                                                         const int32_t* __restrict__ segs,
                                                         const int32_t* __restrict__ segoff,
                                                         const int32_t* __restrict__ prows,
+                                                        const int32_t* __restrict__ runoff,
+                                                        const int32_t* __restrict__ runs,
                                                         const int32_t* __restrict__ pbstart,
                                                         const int32_t* __restrict__ pbnz0,
                                                         const typename Storage<T>::E* __restrict__ xL,
@@ -78,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
   using S = Storage<T>;
   using C = typename S::C;
   using E = typename S::E;
+  static_assert(2 * kRunCap * sizeof(int32_t) <= kStage * sizeof(C), "the run table fits in the value stage");
   constexpr int L = kStage / kBlock;
   static_assert(L == 8, "a thread scans the row-start bytes of 8 offsets as one word");
   __shared__ C lds[kStage];                   // the window's local values, CSR order
@@ -97,15 +100,28 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
   if (n == 0) return;  // a trailing block whose range holds no row start
   const int32_t s0 = segoff[b], ns = segoff[b + 1] - s0;      // <= n
   const int32_t r0 = pbstart[b], nrows = pbstart[b + 1] - r0;  // in [1, n]
-  // 1. the window's words, its segment ids, and the global ids of the rows
-  //    this thread adds in step 5 (q = t + k kBlock); lanes past the end
-  //    repeat the last entry, so that no load waits behind a branch
+  const int32_t u0 = runoff[b], nr = runoff[b + 1] - u0;        // in [1, nrows]
+  const bool by_runs = nr <= kRunCap;
+  // the run table (first row, first id) sits in the value stage until step 4
+  int32_t* rpos = reinterpret_cast<int32_t*>(lds);
+  int32_t* rgid = rpos + kRunCap;
+  // 1. the window's words, its segment ids, and the rows' global ids (as
+  //    runs, or, for a block with many runs, those of the rows this thread
+  //    adds in step 5: q = t + k kBlock); lanes past the end repeat the last
+  //    entry, so that no load waits behind a branch
   uint32_t wd[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) wd[k] = dev::ld_nt(words + w0 + min(t + k * kBlock, n - 1));
   int32_t gid[L];
+  if (by_runs) {
+    for (int i = t; i < nr; i += kBlock) {
+      rpos[i] = runs[2 * (u0 + i)];
+      rgid[i] = runs[2 * (u0 + i) + 1];
+    }
+  } else {
 #pragma unroll
-  for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(t + k * kBlock, nrows - 1)];
+    for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(t + k * kBlock, nrows - 1)];
+  }
   for (int i = t; i < ns; i += kBlock) sst[i] = segs[s0 + i];
 #pragma unroll
   for (int k = 0; k < L; ++k)
@@ -116,8 +132,27 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
 #pragma unroll
   for (int k = 0; k < L; ++k)
     v[k] = xL[static_cast<int64_t>(sst[wd[k] >> 21]) * 512 + ((wd[k] >> 12) & 511u)];
-  // 3. meanwhile the row starts: thread t reads the row-start bytes of
-  //    offsets t*L .. t*L+L-1 (every offset below n was written once)
+  // 3. meanwhile the rows' global ids from the runs (the last run that
+  //    starts at or before the row) and the row starts: thread t reads the
+  //    row-start bytes of offsets t*L .. t*L+L-1 (every offset below n was
+  //    written once)
+  if (by_runs) {  // the eight searches advance together, one LDS read each per step
+    int32_t q[L], lo[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      q[k] = min(t + k * kBlock, nrows - 1);
+      lo[k] = 0;
+    }
+    for (int step = 1 << (31 - __clz(nr)); step > 0; step >>= 1) {
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        const int probe = min(lo[k] + step, nr - 1);
+        if (rpos[probe] <= q[k]) lo[k] = max(lo[k], probe);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) gid[k] = rgid[lo[k]] + (q[k] - rpos[lo[k]]);
+  }
   const uint64_t fl = first64[t];
   int32_t tsum = 0;
 #pragma unroll
@@ -410,7 +445,8 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
     const int64_t grid = gs->n_pblocks + zero_blocks;
     if (grid > 0)
       hipLaunchKernelGGL((k_gather_perm<T>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
-                         gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_bstart, gs->perm_bnz0,
+                         gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff, gs->perm_runs,
+                         gs->perm_bstart, gs->perm_bnz0,
                          static_cast<const E*>(xL), static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global,
                          remap);
   } else if (kind == 1) {

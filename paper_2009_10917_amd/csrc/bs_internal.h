@@ -123,13 +123,18 @@ struct bs_gs {
   // segments (bits 21..31; the segment ids are perm_segs[perm_segoff[b] +
   // rank]), the column mod 512 (bits 12..20), the entry's CSR offset in the
   // window (bits 1..11; rows list their copies in ascending local index) and
-  // whether that offset starts a row (bit 0).  Built only when every degree
-  // fits in a byte (has_perm).
+  // whether that offset starts a row (bit 0).  The rows of block b, as runs
+  // of consecutive global ids: perm_runs[2 i] is the run's first row
+  // (offset in the block) and perm_runs[2 i + 1] its first global id, for i
+  // in [perm_runoff[b], perm_runoff[b+1]).  Built only when every degree fits
+  // in a byte (has_perm).
   bool has_perm;
   int32_t* perm_rows;    // [n_global]
   uint32_t* perm_words;  // [n_unmasked]
   int32_t* perm_segs;    // [perm_segoff[n_pblocks]]
   int32_t* perm_segoff;  // [n_pblocks + 1]
+  int32_t* perm_runoff;  // [n_pblocks + 1]
+  int32_t* perm_runs;    // [2 perm_runoff[n_pblocks]]
   int32_t* perm_bstart;  // [n_pblocks + 1]
   int32_t* perm_bnz0;    // [n_pblocks + 1]
   int64_t n_nzrows;
@@ -138,6 +143,7 @@ struct bs_gs {
 
 namespace bs {
 constexpr int kStage = 2048;  // values staged in LDS per gather workgroup
+constexpr int kRunCap = 256;  // row-id runs a gather workgroup takes from LDS (more: it reads the row ids)
 constexpr int kTile = 512;    // local entries per scatter workgroup
 static_assert(kTile == 2 * kBlock, "scatter tiles hold two entries per thread");
 static_assert(kStage == 8 * kBlock, "gather stages eight values per thread");

@@ -311,6 +311,60 @@ __global__ __launch_bounds__(kBlock) void k_window_segs(const int32_t* __restric
   }
 }
 
+// Runs of consecutive global ids among the rows of each gather block: a row
+// starts a run when it is the block's first or its id is not one more than
+// the previous row's.  Counting pass (nruns[b]), then, with the offsets
+// runoff, the filling pass: runs[2 i] = the run's first row (offset in the
+// block), runs[2 i + 1] = its first global id, for i = runoff[b] + rank.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_row_runs(const int32_t* __restrict__ rows,
+                                                     const int32_t* __restrict__ bstart, int32_t* __restrict__ nruns,
+                                                     const int32_t* __restrict__ runoff, int32_t* __restrict__ runs) {
+  constexpr int L = kStage / kBlock;
+  __shared__ int32_t wsum[kBlock / 64];
+  const int32_t r0 = bstart[blockIdx.x], nrows = bstart[blockIdx.x + 1] - r0;  // <= kStage
+  const int i0 = threadIdx.x * L;
+  int32_t prev = (i0 > 0 && i0 - 1 < nrows) ? rows[r0 + i0 - 1] : 0;
+  int32_t g[L];
+  bool st[L];
+  int32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int q = i0 + i;
+    g[i] = (q < nrows) ? rows[r0 + q] : 0;
+    st[i] = (q < nrows) && (q == 0 || g[i] != prev + 1);
+    prev = g[i];
+    cnt += st[i];
+  }
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  int32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    before += (i < w) ? wsum[i] : 0;
+    total += wsum[i];
+  }
+  if (!FILL) {
+    if (threadIdx.x == 0) nruns[blockIdx.x] = total;
+    return;
+  }
+  int64_t idx = runoff[blockIdx.x] + before + incl - cnt;
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+    if (st[i]) {
+      runs[2 * idx] = i0 + i;
+      runs[2 * idx + 1] = g[i];
+      ++idx;
+    }
+}
+
 // Degrees of the rows in visiting order.
 __global__ __launch_bounds__(kBlock) void k_perm_degrees(const int32_t* __restrict__ rows, int64_t n_nzrows,
                                                          const int32_t* __restrict__ rs, int32_t* __restrict__ d32) {
@@ -523,6 +577,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
   const int64_t nz = ng - n_zero_rows;  // rows with copies
   DevBuf rank, rkey, rkey_out, rows0, rows, d32, prs, pcols, scols, words, nseg, segoff, segs, bstart, bnz0;
+  DevBuf nruns, runoff, runs;
   B.need(rank, nt * 4, "tile ranks");
   B.need(rkey, ng * 4, "row keys");
   B.need(rkey_out, ng * 4, "row keys");
@@ -594,9 +649,31 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
     hipLaunchKernelGGL(k_window_segs, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, scols.as<int32_t>(),
                        words.as<uint32_t>(), bnz0.as<int32_t>(), so, segs.as<int32_t>());
   B.launched();
+  // runs of consecutive row ids per block
+  B.need(nruns, (nb + 1) * 4, "run counts");
+  B.need(runoff, (nb + 1) * 4, "run offsets");
+  if (!B.ok()) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nb + 1)), dim3(kBlock), 0, B.st, nruns.as<int32_t>(), nb + 1, 0);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_row_runs<false>, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st,
+                       rows.as<int32_t>(), bstart.as<int32_t>(), nruns.as<int32_t>(), static_cast<const int32_t*>(nullptr),
+                       static_cast<int32_t*>(nullptr));
+  B.launched();
+  int32_t* nr = nruns.as<int32_t>();
+  int32_t* ro = runoff.as<int32_t>();
+  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, nr, ro, static_cast<int>(nb + 1), B.st); });
+  const int64_t total_runs = B.ok() ? static_cast<int64_t>(B.read(ro + nb)) : 0;
+  B.need(runs, (total_runs > 0 ? total_runs : 1) * 8, "row runs");
+  if (!B.ok()) return;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_row_runs<true>, dim3(static_cast<unsigned int>(nb)), dim3(kBlock), 0, B.st, rows.as<int32_t>(),
+                       bstart.as<int32_t>(), static_cast<int32_t*>(nullptr), ro, runs.as<int32_t>());
+  B.launched();
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
   gs->perm_rows = rows.release<int32_t>();
+  gs->perm_runoff = runoff.release<int32_t>();
+  gs->perm_runs = runs.release<int32_t>();
   gs->perm_words = words.release<uint32_t>();
   gs->perm_segs = segs.release<int32_t>();
   gs->perm_segoff = segoff.release<int32_t>();
@@ -616,7 +693,8 @@ void free_plan(bs_gs* gs) {
                   static_cast<void*>(gs->tile_gid), static_cast<void*>(gs->tile_loc),
                   static_cast<void*>(gs->tile_count), static_cast<void*>(gs->perm_rows),
                   static_cast<void*>(gs->perm_words), static_cast<void*>(gs->perm_segs),
-                  static_cast<void*>(gs->perm_segoff),
+                  static_cast<void*>(gs->perm_segoff), static_cast<void*>(gs->perm_runoff),
+                  static_cast<void*>(gs->perm_runs),
                   static_cast<void*>(gs->perm_bstart), static_cast<void*>(gs->perm_bnz0)})
     if (p) (void)hipFree(p);
   delete gs;
@@ -692,6 +770,8 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   uint32_t* old_words = gs->perm_words;
   int32_t* old_segs = gs->perm_segs;
   int32_t* old_segoff = gs->perm_segoff;
+  int32_t* old_runoff = gs->perm_runoff;
+  int32_t* old_runs = gs->perm_runs;
   int32_t* old_bstart = gs->perm_bstart;
   int32_t* old_bnz0 = gs->perm_bnz0;
   const int64_t zero_rows = gs->n_global - gs->n_nzrows;
@@ -700,7 +780,8 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   build_gather_order(B, gs, zero_rows, &lat);
   if (B.ok()) {
     for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_words), static_cast<void*>(old_segs),
-                    static_cast<void*>(old_segoff), static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
+                    static_cast<void*>(old_segoff), static_cast<void*>(old_runoff), static_cast<void*>(old_runs),
+                    static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
       (void)hipFree(q);
   } else {
     gs->has_perm = true;  // the previous order is still in place
