@@ -308,13 +308,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ r
 // ---------------------------------------------------------------- BS7 scatter, sorted tiles
 
 // A workgroup takes TPW consecutive tiles of the visiting order.  Within a
-// tile the (global id, local offset) pairs are read in ascending global id,
-// the values fetched in that order and put in place through LDS, and the
-// tile's entries are written contiguously.
-template <class E, int TPW>
+// tile the (global id, local offset) pairs are read in ascending global id
+// (PACKED: one word per pair, id - tile minimum above the 9-bit offset), the
+// values fetched in that order and put in place through LDS, and the tile's
+// entries are written contiguously.
+template <class E, int TPW, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __restrict__ order,
                                                            const int32_t* __restrict__ tgid,
                                                            const uint16_t* __restrict__ tloc,
+                                                           const uint32_t* __restrict__ tword,
+                                                           const int32_t* __restrict__ tmin,
                                                            const int32_t* __restrict__ tcnt, const E* __restrict__ xG,
                                                            E* __restrict__ xL, int64_t n_local, int64_t n_tiles,
                                                            bool remap) {
@@ -324,10 +327,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
   const int64_t t0 = static_cast<int64_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * TPW;
   int64_t tile[TPW];
   int cnt[TPW];
+  int32_t g0[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) tile[i] = order[min(t0 + i, n_tiles - 1)];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) cnt[i] = (t0 + i < n_tiles) ? tcnt[tile[i]] : 0;
+  for (int i = 0; i < TPW; ++i) {
+    cnt[i] = (t0 + i < n_tiles) ? tcnt[tile[i]] : 0;
+    if (PACKED) g0[i] = tmin[tile[i]];
+  }
 #pragma unroll
   for (int i = 0; i < TPW; ++i)
 #pragma unroll
@@ -339,8 +346,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int q = min(static_cast<int>(threadIdx.x) + k * kBlock, kTile - 1);
-      g[i][k] = dev::ld_nt(tgid + tile[i] * kTile + q);
-      o[i][k] = dev::ld_nt(tloc + tile[i] * kTile + q);
+      if (PACKED) {
+        const uint32_t w = dev::ld_nt(tword + tile[i] * kTile + q);
+        g[i][k] = g0[i] + static_cast<int32_t>(w >> 9);
+        o[i][k] = static_cast<uint16_t>(w & 511u);
+      } else {
+        g[i][k] = dev::ld_nt(tgid + tile[i] * kTile + q);
+        o[i][k] = dev::ld_nt(tloc + tile[i] * kTile + q);
+      }
     }
   E v[TPW][P];
 #pragma unroll
@@ -473,9 +486,16 @@ void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipS
 template <class E, int TPW>
 void launch_scatter_sorted(const bs_gs* gs, bool remap, const void* xG, void* xL, hipStream_t st) {
   const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
-  hipLaunchKernelGGL((k_scatter_sorted<E, TPW>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order, gs->tile_gid,
-                     gs->tile_loc, gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
-                     gs->n_tiles, remap);
+  if (gs->tile_packed)
+    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, true>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
+                       static_cast<const int32_t*>(nullptr), static_cast<const uint16_t*>(nullptr), gs->tile_word,
+                       gs->tile_min, gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
+                       gs->n_tiles, remap);
+  else
+    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, false>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
+                       gs->tile_gid, gs->tile_loc, static_cast<const uint32_t*>(nullptr),
+                       static_cast<const int32_t*>(nullptr), gs->tile_count, static_cast<const E*>(xG),
+                       static_cast<E*>(xL), gs->n_local, gs->n_tiles, remap);
 }
 
 template <class E, int TPW>

@@ -105,9 +105,16 @@ struct bs_gs {
   // of the smallest global id each references (tile_order); within tile t,
   // entry k of tile_gid/tile_loc is the k-th smallest (global id, local
   // offset) pair, masked entries excluded (tile_count[t] valid pairs).
+  // When every tile's ids span less than 2^23 (tile_packed), the pairs are
+  // kept as one word each instead: tile_word = (id - tile_min[t]) << 9 |
+  // offset, tile_min[t] the tile's smallest id; tile_gid/tile_loc are then
+  // not kept.
   int32_t* tile_order;   // [n_tiles]
   int32_t* tile_gid;     // [n_tiles * kTile]
   uint16_t* tile_loc;    // [n_tiles * kTile]
+  bool tile_packed;
+  uint32_t* tile_word;   // [n_tiles * kTile]
+  int32_t* tile_min;     // [n_tiles]
   int32_t* tile_count;   // [n_tiles]
   int64_t n_tiles;
 

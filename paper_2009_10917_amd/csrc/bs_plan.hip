@@ -126,10 +126,16 @@ __global__ __launch_bounds__(kBlock) void k_block_starts(const int32_t* __restri
 
 // Per tile: smallest unmasked id (key for the visiting order) and the tile's
 // entries sorted by (id, local offset), masked and padding entries last.
+//
+// Also the packed form: tword[e] = (id - tmin[tile]) << 9 | offset for the
+// tile's valid pairs (tmin: its smallest id), with *wide set when a tile's
+// ids span 2^23 or more (the packed form then does not apply).
 __global__ __launch_bounds__(kBlock) void k_tile_sort(const int32_t* __restrict__ map, int64_t n_local,
                                                       uint32_t* __restrict__ tkey, int32_t* __restrict__ tidx,
                                                       int32_t* __restrict__ tgid, uint16_t* __restrict__ tloc,
-                                                      int32_t* __restrict__ tcnt) {
+                                                      int32_t* __restrict__ tcnt, uint32_t* __restrict__ tword,
+                                                      int32_t* __restrict__ tmin, int* __restrict__ wide) {
+  static_assert(kTile == 512, "packed tile words hold a 9-bit offset");
   __shared__ uint64_t key[kTile];
   __shared__ int s_cnt;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile;
@@ -159,12 +165,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_sort(const int32_t* __restrict_
     }
   }
   int mine = 0;
+  const uint32_t g0 = static_cast<uint32_t>(key[0] >> 16);  // smallest valid id (if any)
   for (int k = threadIdx.x; k < kTile; k += kBlock) {
     const uint64_t v = key[k];
     const uint32_t g = static_cast<uint32_t>(v >> 16);
     const bool valid = g != 0xFFFFFFFFu;
     tgid[base + k] = valid ? static_cast<int32_t>(g) : -1;
     tloc[base + k] = static_cast<uint16_t>(v & 0xFFFFu);
+    tword[base + k] = valid ? ((g - g0) << 9) | static_cast<uint32_t>(v & 0x1FFu) : 0u;
+    if (valid && g - g0 >= (1u << 23)) atomicOr(wide, 1);
     mine += valid;
   }
   atomicAdd(&s_cnt, mine);
@@ -173,6 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_sort(const int32_t* __restrict_
     tcnt[blockIdx.x] = s_cnt;
     tkey[blockIdx.x] = static_cast<uint32_t>(key[0] >> 16);  // 0xFFFFFFFF when the tile has no valid entry
     tidx[blockIdx.x] = static_cast<int32_t>(blockIdx.x);
+    tmin[blockIdx.x] = static_cast<int32_t>(g0);
   }
 }
 
@@ -533,19 +543,23 @@ void build_gather_blocks(Builder& B, bs_gs* gs) {
 void build_scatter_tiles(Builder& B, bs_gs* gs) {
   const int64_t nt = (gs->n_local + kTile - 1) / kTile;
   gs->n_tiles = nt;
-  DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx;
+  DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx, tword, tmin, wide;
   B.need(tgid, nt * kTile * 4, "tile ids");
   B.need(tloc, nt * kTile * 2, "tile offsets");
+  B.need(tword, nt * kTile * 4, "tile words");
+  B.need(tmin, nt * 4, "tile minima");
+  B.need(wide, 64, "flag");
   B.need(tcnt, nt * 4, "tile counts");
   B.need(order, nt * 4, "tile order");
   B.need(tkey, nt * 4, "tile keys");
   B.need(tkey_out, nt * 4, "tile keys");
   B.need(tidx, nt * 4, "tile indices");
   if (!B.ok()) return;
+  B.hip(hipMemsetAsync(wide.p, 0, 64, B.st));
   if (nt > 0) {
     hipLaunchKernelGGL(k_tile_sort, dim3(static_cast<unsigned int>(nt)), dim3(kBlock), 0, B.st, gs->map, gs->n_local,
                        tkey.as<uint32_t>(), tidx.as<int32_t>(), tgid.as<int32_t>(), tloc.as<uint16_t>(),
-                       tcnt.as<int32_t>());
+                       tcnt.as<int32_t>(), tword.as<uint32_t>(), tmin.as<int32_t>(), wide.as<int>());
     B.launched();
     uint32_t* k0 = tkey.as<uint32_t>();
     uint32_t* k1 = tkey_out.as<uint32_t>();
@@ -557,8 +571,14 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
   }
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
-  gs->tile_gid = tgid.release<int32_t>();
-  gs->tile_loc = tloc.release<uint16_t>();
+  gs->tile_packed = B.read(wide.as<int>()) == 0;
+  if (gs->tile_packed) {  // one word per pair
+    gs->tile_word = tword.release<uint32_t>();
+    gs->tile_min = tmin.release<int32_t>();
+  } else {
+    gs->tile_gid = tgid.release<int32_t>();
+    gs->tile_loc = tloc.release<uint16_t>();
+  }
   gs->tile_count = tcnt.release<int32_t>();
   gs->tile_order = order.release<int32_t>();
 }
@@ -691,6 +711,7 @@ void free_plan(bs_gs* gs) {
   for (void* p : {static_cast<void*>(gs->map), static_cast<void*>(gs->row_starts), static_cast<void*>(gs->col_ids),
                   static_cast<void*>(gs->block_starts), static_cast<void*>(gs->tile_order),
                   static_cast<void*>(gs->tile_gid), static_cast<void*>(gs->tile_loc),
+                  static_cast<void*>(gs->tile_word), static_cast<void*>(gs->tile_min),
                   static_cast<void*>(gs->tile_count), static_cast<void*>(gs->perm_rows),
                   static_cast<void*>(gs->perm_words), static_cast<void*>(gs->perm_segs),
                   static_cast<void*>(gs->perm_segoff), static_cast<void*>(gs->perm_runoff),

@@ -208,6 +208,22 @@ def test_scatter_tiles_per_workgroup(ctx, variant, tpw):
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
 
+@pytest.mark.parametrize("tpw", [1, 2, 4])
+def test_scatter_sorted_tiles_with_wide_id_spans(ctx, tpw):
+    # ids spread over 2^24 global entries: tiles span more than 2^23 ids, so
+    # the plan keeps (id, offset) pairs instead of packed words
+    rng = np.random.default_rng(5)
+    NG, NL = (1 << 24) + 3, 5000
+    ref_map = rng.integers(0, NG, NL).astype(np.int64)
+    ref_map[::11] = -1
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
+    bs.bs_ctx_set_tune(ctx, "scatter", tpw, 1 << 30, 0)
+    xL = dev_uniform(NL, 11)
+    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
+    assert np.array_equal(bits(to_host(xL)), bits(ref))
+
+
 def test_scatter_with_no_global_entries(ctx):
     # every local entry masked: nothing is written, whatever the variant
     ref_map = np.full(1000, -1, dtype=np.int32)
