@@ -327,16 +327,16 @@ def mixed_cg(ctx, bs, bsgen, torch, seed, reps, m=225, shift=0.01, tol=1e-10):
     return out
 
 
-# gather row order: lattice tiles of GATHER_TILE^3 points (no sub-boxes); among the fastest in a sweep at
-# K = 128, N = 7 (boxes matched to the elements read fewer lines but fragment the x_G stores)
-GATHER_TILE, GATHER_SUB = 128, 0
+# gather row order: lattice tiles of GATHER_TILE^3 points, boxes of GATHER_BOX points inside (0: none);
+# 126 = 18 elements of degree 7, boxes one element thick in y and z (slabs along x)
+GATHER_TILE, GATHER_BOX = 126, (126, 7, 7)
 
 
 def gather_sweep(args, np, torch, bs, bsgen):
     """Gather on the K^3, N = 7 mesh in each row order: global order
     (variant 1), the scatter tiles' visiting order (variant 0), and
-    lattice tiles of the given sizes ("tile" or "tile:sub", variant 0 after
-    bs_gs_order_rows),
+    lattice tiles of the given sizes ("tile", "tile:side" for cubic boxes or
+    "tile:bxXbyXbz", variant 0 after bs_gs_order_rows),
     with and without the XCD renumbering.  --mesh chooses the element
     layout: random (permuted and oriented, the benchmark's), orient
     (lexicographic, oriented) or ident (lexicographic, unrotated).  One
@@ -377,8 +377,9 @@ def gather_sweep(args, np, torch, bs, bsgen):
     ms = run(0)
     emit("visiting", 0, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
     for spec in [t for t in args.gather_sweep.split(",") if t]:
-        tile, _, sub = spec.partition(":")
-        bs.bs_gs_order_rows(plan, M, M, M, int(tile), int(sub or 0))
+        tile, _, box = spec.partition(":")
+        box = tuple(int(v) for v in box.split("x")) if "x" in box else int(box or 0)
+        bs.bs_gs_order_rows(plan, M, M, M, int(tile), box)
         for v in (0, 4):
             ms = run(v)
             emit(f"lattice tiles {spec}", v, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
@@ -478,7 +479,7 @@ def main():
                     help="only the mixed-precision CG time-to-solution (225^3 shifted 7-point operator)")
     ap.add_argument("--no-cg", action="store_true", help="skip the mixed-precision CG section")
     ap.add_argument("--batch-only", action="store_true", help="only the batched step over 1024 box-mesh instances")
-    ap.add_argument("--gather-sweep", default="", help="comma-separated lattice tile sizes (tile or tile:sub): time the gather's row orders")
+    ap.add_argument("--gather-sweep", default="", help="comma-separated lattice tile sizes (tile, tile:side or tile:bxXbyXbz): time the gather's row orders")
     ap.add_argument("--mesh", default="random", choices=("random", "orient", "ident"),
                     help="element layout for --gather-sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
@@ -539,7 +540,7 @@ def main():
     del d_map, perm, orient
     # plan set-up: rows of the gather in lattice tiles (same bits, better cache reuse)
     M = K * N + 1
-    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_SUB)
+    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
     bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, 0)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -632,7 +633,7 @@ def main():
                                 f"(N_L={NL}, N_G={n}; elements permuted and oriented from the seed)"),
                    "n": n, "n_local": NL, "n_global": n, "mesh_K": K, "degree_N": N, "seed": args.seed,
                    "gather_row_order": (f"lattice tiles of {GATHER_TILE}^3 points"
-                                        + (f", boxes of {GATHER_SUB}^3" if GATHER_SUB else "")),
+                                        + (", boxes of {}x{}x{} points".format(*GATHER_BOX) if GATHER_BOX else "")),
                    "alpha": alpha, "beta": beta},
         "per_op": per_op,
         "roofline": roofline,

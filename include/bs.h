@@ -204,18 +204,20 @@ bs_status bs_gs_destroy(bs_gs* gs);
  * lattice-tiled one, for maps whose global ids are lattice points
  * g = X + mx (Y + my Z) (mx*my*mz == n_global): rows in tile x tile x tile
  * blocks of the lattice, blocks in lattice order (x fastest); inside a
- * block, rows in sub x sub x sub boxes, boxes in lattice order (sub == 0,
- * or sub >= tile: one box); ascending g within a box; rows without copies
- * last.  With boxes that match the elements (sub a multiple of the degree
- * N on the meshes of bs_mesh_hex_map), a gather workgroup reads whole runs
- * of each element's local values; the tiles keep the elements around a
- * tile in cache while all their copies are added.  The result is the same
- * (each row is still summed in ascending local index).  Allocates and
- * synchronises `stream`; BS_ERR_INVALID_ARG for sub < 0 or more than
- * 2^32 - 1 boxes, BS_ERR_UNSUPPORTED when the plan has no permuted order
- * (a degree above 255); on failure the previous order stays in place. */
-bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t sub,
-                           void* stream);
+ * block, rows in bx x by x bz boxes, boxes in lattice order (a side of 0,
+ * or above tile, is the tile's: 0, 0, 0 is one box); ascending g within a
+ * box; rows without copies last.  Boxes matched to the elements in y and z
+ * (sides a multiple of the degree N on the meshes of bs_mesh_hex_map, with
+ * tile a multiple of them) let a gather workgroup read longer runs of each
+ * element's local values; the tiles keep the elements around a tile in
+ * cache while all their copies are added.  The result is the same (each
+ * row is still summed in ascending local index).  Allocates and
+ * synchronises `stream`; BS_ERR_INVALID_ARG for a negative side or more
+ * than 2^32 - 1 boxes, BS_ERR_UNSUPPORTED when the plan has no permuted
+ * order (a degree above 255); on failure the previous order stays in
+ * place. */
+bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t bx, int32_t by,
+                           int32_t bz, void* stream);
 
 /* Sizes of a plan: local length, global length, unmasked local entries,
  * largest node degree.  Any output pointer may be NULL. */

@@ -60,7 +60,7 @@ PROTOTYPES = {
     "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
-    "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _i32, _p]),
+    "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _i32, _i32, _i32, _p]),
     "bs_ctx_set_tune_entry": (_st, [_p, _i32, _i32, _i64, _i32, _i32, _i32]),
     "bs_ctx_tune_for": (_st, [_p, _i32, _i32, _i64, _p, _p, _p]),
     "bs_ctx_load_tune": (_st, [_p, ctypes.c_char_p, _p]),
@@ -307,11 +307,13 @@ def bs_gs_degree(plan, deg, stream=None):
     _check(lib.bs_gs_degree(plan.handle, _ptr(deg), _stream(stream)), "bs_gs_degree")
 
 
-def bs_gs_order_rows(plan, mx, my, mz, tile, sub=0, stream=None):
+def bs_gs_order_rows(plan, mx, my, mz, tile, box=0, stream=None):
     """Lattice-tiled row order for gather variant 0 (global ids X + mx (Y + my Z)):
-    tile^3 blocks, sub^3 boxes inside a block (sub=0: none)."""
-    _check(lib.bs_gs_order_rows(plan.handle, int(mx), int(my), int(mz), int(tile), int(sub), _stream(stream)),
-           "bs_gs_order_rows")
+    tile^3 blocks, boxes inside a block (box: one side for cubes, or (bx, by, bz);
+    0: none)."""
+    bx, by, bz = (box, box, box) if isinstance(box, int) else box
+    _check(lib.bs_gs_order_rows(plan.handle, int(mx), int(my), int(mz), int(tile), int(bx), int(by), int(bz),
+                                _stream(stream)), "bs_gs_order_rows")
 
 
 def bs_gs_weights(plan, wL, stream=None):

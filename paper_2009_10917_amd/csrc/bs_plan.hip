@@ -204,12 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t* __restrict__
 // Row keys of a lattice-tiled order: global id g is lattice point
 // (g mod mx, (g / mx) mod my, g / (mx my)); its key is the index of its
 // tile x tile x tile block in lattice order (blocks along x fastest) and,
-// within the block, of its sub x sub x sub box (ns boxes per side, in the
+// within the block, of its bx x by x bz box (nbx x nby x nbz boxes, in the
 // same order); rows without copies get the largest key so that they come
 // last.
 __global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restrict__ rs, int64_t n_global, int64_t mx,
                                                          int64_t my, int64_t tile, int64_t ntx, int64_t nty,
-                                                         int64_t sub, int64_t ns, uint32_t* __restrict__ key) {
+                                                         int64_t bx, int64_t by, int64_t bz, int64_t nbx, int64_t nby,
+                                                         int64_t nbz, uint32_t* __restrict__ key) {
   const int64_t g = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (g >= n_global) return;
   if (rs[g + 1] == rs[g]) {
@@ -218,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_lattice_keys(const int32_t* __restri
   }
   const int64_t x = g % mx, y = (g / mx) % my, z = g / (mx * my);
   const int64_t t = x / tile + ntx * (y / tile + nty * (z / tile));
-  const int64_t b = (x % tile) / sub + ns * ((y % tile) / sub + ns * ((z % tile) / sub));
-  key[g] = static_cast<uint32_t>(t * ns * ns * ns + b);
+  const int64_t b = (x % tile) / bx + nbx * ((y % tile) / by + nby * ((z % tile) / bz));
+  key[g] = static_cast<uint32_t>(t * nbx * nby * nbz + b);
 }
 
 // Per gather block: the entries of its window [bnz0[b], bnz0[b+1]) (at most
@@ -586,7 +587,7 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
 // Rows in visiting order (needs the tile order and the CSR).
 // Lattice description for a tiled gather order (global ids are lattice points).
 struct LatticeOrder {
-  int64_t mx, my, mz, tile, sub;  // sub: side of the boxes inside a tile (tile: none)
+  int64_t mx, my, mz, tile, bx, by, bz;  // box sides inside a tile (tile: none)
 };
 
 // Rows with copies in a permuted order and the CSR in that order: by default
@@ -610,10 +611,11 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   if (ng > 0) hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
   if (lat) {
     const int64_t ntx = (lat->mx + lat->tile - 1) / lat->tile, nty = (lat->my + lat->tile - 1) / lat->tile;
-    const int64_t ns = (lat->tile + lat->sub - 1) / lat->sub;
+    const int64_t nbx = (lat->tile + lat->bx - 1) / lat->bx, nby = (lat->tile + lat->by - 1) / lat->by,
+                  nbz = (lat->tile + lat->bz - 1) / lat->bz;
     if (ng > 0)
       hipLaunchKernelGGL(k_lattice_keys, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, gs->row_starts, ng, lat->mx,
-                         lat->my, lat->tile, ntx, nty, lat->sub, ns, rkey.as<uint32_t>());
+                         lat->my, lat->tile, ntx, nty, lat->bx, lat->by, lat->bz, nbx, nby, nbz, rkey.as<uint32_t>());
   } else {
     if (nt > 0)
       hipLaunchKernelGGL(k_invert, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, gs->tile_order, nt, rank.as<int32_t>());
@@ -771,18 +773,22 @@ extern "C" bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_l
   return BS_OK;
 }
 
-extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t sub,
-                                      void* stream) {
+extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t bx,
+                                      int32_t by, int32_t bz, void* stream) {
   const char* op = "bs_gs_order_rows";
   if (!gs) return fail(BS_ERR_INVALID_ARG, "%s: plan is NULL", op);
   if (mx < 1 || my < 1 || mz < 1 || tile < 1 || mx * my * mz != gs->n_global)
     return fail(BS_ERR_INVALID_ARG, "%s: need mx*my*mz == n_global and tile >= 1", op);
-  if (sub < 0) return fail(BS_ERR_INVALID_ARG, "%s: sub must be >= 0", op);
-  if (sub == 0 || sub > tile) sub = tile;
-  const int64_t ns = (tile + sub - 1) / sub;
+  if (bx < 0 || by < 0 || bz < 0) return fail(BS_ERR_INVALID_ARG, "%s: box sides must be >= 0", op);
+  if (bx == 0 || bx > tile) bx = tile;
+  if (by == 0 || by > tile) by = tile;
+  if (bz == 0 || bz > tile) bz = tile;
+  // boxes per tile, then tiles, as 32-bit keys (each factor < 2^31; checked before every product)
+  const int64_t t64 = tile;
+  const int64_t fxy = ((t64 + bx - 1) / bx) * ((t64 + by - 1) / by);
+  const int64_t nb = (fxy < 0xffffffffLL) ? fxy * ((t64 + bz - 1) / bz) : 0xffffffffLL;
   const int64_t ntiles = ((mx + tile - 1) / tile) * ((my + tile - 1) / tile) * ((mz + tile - 1) / tile);
-  if (ns > 2048 || ntiles >= 0xffffffffLL / (ns * ns * ns))
-    return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
+  if (nb >= 0xffffffffLL || ntiles >= 0xffffffffLL / nb) return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
   if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 255)", op);
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -797,7 +803,7 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   int32_t* old_bnz0 = gs->perm_bnz0;
   const int64_t zero_rows = gs->n_global - gs->n_nzrows;
   Builder B{op, static_cast<hipStream_t>(stream)};
-  const LatticeOrder lat{mx, my, mz, tile, sub};
+  const LatticeOrder lat{mx, my, mz, tile, bx, by, bz};
   build_gather_order(B, gs, zero_rows, &lat);
   if (B.ok()) {
     for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_words), static_cast<void*>(old_segs),

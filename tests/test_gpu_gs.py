@@ -295,16 +295,17 @@ def test_gather_scatter_deterministic(ctx):
 
 
 @pytest.mark.parametrize("remap", [0, 4])
-@pytest.mark.parametrize("K,N,tile,sub", [(6, 5, 1, 0), (6, 5, 4, 0), (7, 3, 7, 0), (5, 7, 64, 0), (9, 2, 5, 0),
+@pytest.mark.parametrize("K,N,tile,box", [(6, 5, 1, 0), (6, 5, 4, 0), (7, 3, 7, 0), (5, 7, 64, 0), (9, 2, 5, 0),
                                           (6, 5, 10, 5), (7, 3, 12, 6), (5, 7, 28, 14), (9, 2, 7, 3), (6, 7, 98, 14),
-                                          (4, 7, 5, 9)])
-def test_gather_lattice_tiled_order(ctx, K, N, tile, sub, remap):
+                                          (4, 7, 5, 9), (6, 7, 42, (42, 7, 7)), (5, 3, 12, (12, 3, 6)),
+                                          (7, 4, 16, (0, 4, 8)), (5, 5, 11, (2, 3, 4))])
+def test_gather_lattice_tiled_order(ctx, K, N, tile, box, remap):
     # the tiled row order changes which rows a workgroup adds, not how a row is summed
     E, NL, NG = mesh.sizes(K, N)
     d_map, ids = device_map(K, N, 5)
     plan = bs.bs_gs_create(ctx, d_map, NG)
     M = K * N + 1
-    bs.bs_gs_order_rows(plan, M, M, M, tile, sub)
+    bs.bs_gs_order_rows(plan, M, M, M, tile, box)
     with_variant(ctx, 0 + remap)
     xL = dev_uniform(NL, 11)
     xG = torch.empty(NG, dtype=torch.float64, device="cuda")
@@ -328,6 +329,8 @@ def test_gather_lattice_order_masked_and_errors(ctx):
         bs.bs_gs_order_rows(plan, M, M, M, 0)
     with pytest.raises(bs.BSError):
         bs.bs_gs_order_rows(plan, M, M, M, 4, -1)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_rows(plan, M, M, M, 4, (0, -2, 0))
     with pytest.raises(bs.BSError):
         bs.bs_gs_order_rows(plan, M, M, M, 1 << 30, 1)  # more boxes than 32-bit keys hold
     bs.bs_gs_order_rows(plan, M, M, M, 3, 2)
