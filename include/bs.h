@@ -96,10 +96,11 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * of blocks.  Gather: 0 = rows in the plan's permuted order (by default
  * grouped by the scatter tiles that hold their copies; bs_gs_order_rows
  * replaces it with lattice tiles; falls back to 1 when a degree exceeds
- * 255), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
+ * 1024), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
  * entries visited in order of their smallest global id, values read in
  * ascending global id and turned around in LDS, 1 = the same tiles read in
- * local order, 2 = local order with `unroll` entries per thread.  The setting applies to every dtype.  Results of the bit-exact
+ * local order (for 0 and 1, `unroll` tiles per workgroup, at most 4),
+ * 2 = local order with `unroll` entries per thread.  The setting applies to every dtype.  Results of the bit-exact
  * operations do not depend on it; reduction results depend on it only
  * through the order of their compensated additions.  Defaults: unroll 1
  * and one-pass grids for element-wise operations and gather/scatter;
@@ -214,7 +215,7 @@ bs_status bs_gs_destroy(bs_gs* gs);
  * row is still summed in ascending local index).  Allocates and
  * synchronises `stream`; BS_ERR_INVALID_ARG for a negative side or more
  * than 2^32 - 1 boxes, BS_ERR_UNSUPPORTED when the plan has no permuted
- * order (a degree above 255); on failure the previous order stays in
+ * order (a degree above 1024); on failure the previous order stays in
  * place. */
 bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t mz, int32_t tile, int32_t bx, int32_t by,
                            int32_t bz, void* stream);

@@ -133,8 +133,8 @@ struct bs_gs {
   // whether that offset starts a row (bit 0).  The rows of block b, as runs
   // of consecutive global ids: perm_runs[2 i] is the run's first row
   // (offset in the block) and perm_runs[2 i + 1] its first global id, for i
-  // in [perm_runoff[b], perm_runoff[b+1]).  Built only when every degree fits
-  // in a byte (has_perm).
+  // in [perm_runoff[b], perm_runoff[b+1]).  Built only when every degree is at most
+  // kStage / 2 (has_perm).
   bool has_perm;
   int32_t* perm_rows;    // [n_global]
   uint32_t* perm_words;  // [n_unmasked]

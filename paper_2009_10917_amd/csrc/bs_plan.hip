@@ -594,7 +594,8 @@ struct LatticeOrder {
 // the visiting order of the scatter tiles, or (lat) lattice tiles.
 void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const LatticeOrder* lat = nullptr) {
   gs->has_perm = false;
-  if (gs->max_degree > 255) return;  // degrees are stored in bytes
+  // a window (chunk + max_degree - 1 entries) must fit the stage, whose offsets take 11 bits
+  if (gs->max_degree > kStage / 2) return;
   const int64_t nl = gs->n_local, ng = gs->n_global, nt = gs->n_tiles;
   const int64_t nz = ng - n_zero_rows;  // rows with copies
   DevBuf rank, rkey, rkey_out, rows0, rows, d32, prs, pcols, scols, words, nseg, segoff, segs, bstart, bnz0;
@@ -789,7 +790,7 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
   const int64_t nb = (fxy < 0xffffffffLL) ? fxy * ((t64 + bz - 1) / bz) : 0xffffffffLL;
   const int64_t ntiles = ((mx + tile - 1) / tile) * ((my + tile - 1) / tile) * ((mz + tile - 1) / tile);
   if (nb >= 0xffffffffLL || ntiles >= 0xffffffffLL / nb) return fail(BS_ERR_INVALID_ARG, "%s: too many tiles", op);
-  if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 255)", op);
+  if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 1024)", op);
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(gs->device);

@@ -280,6 +280,34 @@ def test_gather_windows_near_the_stage_size(ctx, tile, sub):
     assert np.array_equal(bits(to_host(xG)), bits(ref))
 
 
+def test_gather_permuted_order_up_to_degree_1024(ctx):
+    # rows of degree up to 1024 keep the permuted order (windows of up to
+    # 1023 + 1024 entries); one row more than that and variant 0 falls back
+    # to the global order; both give the definition's bits
+    rng = np.random.default_rng(23)
+    NG = 3000
+    deg = rng.integers(1, 9, NG)
+    deg[[5, 1700, NG - 1]] = 1024
+    deg[[6, 7]] = [1000, 999]
+    for extra in (0, 1):
+        d = deg.copy()
+        d[5] += extra
+        ref_map = rng.permutation(np.repeat(np.arange(NG), d))
+        plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
+        assert plan.max_degree == 1024 + extra
+        if extra == 0:
+            bs.bs_gs_order_rows(plan, NG, 1, 1, 64, 0)
+        else:
+            with pytest.raises(bs.BSError):
+                bs.bs_gs_order_rows(plan, NG, 1, 1, 64, 0)
+        rs_ref, ci_ref = mesh.csr_inverse(ref_map, NG)
+        xLh = bsgen.uniform(3, 11, ref_map.size)
+        with_variant(ctx, 0)
+        xG = torch.full((NG,), float("nan"), dtype=torch.float64, device="cuda")
+        bs.bs_gather(ctx, plan, torch.from_numpy(xLh).cuda(), xG)
+        assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, xLh)))
+
+
 def test_gather_scatter_deterministic(ctx):
     K, N = 10, 7
     E, NL, NG = mesh.sizes(K, N)
