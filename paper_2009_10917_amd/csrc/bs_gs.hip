@@ -65,29 +65,28 @@ __device__ __forceinline__ C row_sum(const C* v, int32_t a, int32_t e) {
 // put in LDS at its CSR offset, the rows' starts are recovered from the
 // row-start bits, and every row adds its copies from LDS in CSR order, i.e.
 // in ascending local index, as the definition of x_G = Z^T x_L does.
+// Seven workgroups per CU: 21.5 KB of LDS each, and at most 72 VGPRs.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restrict__ words,
-                                                        const int32_t* __restrict__ segs,
-                                                        const int32_t* __restrict__ segoff,
-                                                        const int32_t* __restrict__ prows,
-                                                        const int32_t* __restrict__ runoff,
-                                                        const int32_t* __restrict__ runs,
-                                                        const int32_t* __restrict__ pbstart,
-                                                        const int32_t* __restrict__ pbnz0,
-                                                        const typename Storage<T>::E* __restrict__ xL,
-                                                        typename Storage<T>::E* __restrict__ xG, int64_t n_pblocks,
-                                                        int64_t n_nzrows, int64_t n_rows, bool remap) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_gather_perm(
+    const uint32_t* __restrict__ words, const int32_t* __restrict__ segs, const int32_t* __restrict__ segoff,
+    const int32_t* __restrict__ prows, const int32_t* __restrict__ runoff, const int32_t* __restrict__ runs,
+    const int32_t* __restrict__ pbstart, const int32_t* __restrict__ pbnz0,
+    const typename Storage<T>::E* __restrict__ xL, typename Storage<T>::E* __restrict__ xG, int64_t n_pblocks,
+    int64_t n_nzrows, int64_t n_rows, bool remap) {
   using S = Storage<T>;
   using C = typename S::C;
   using E = typename S::E;
   static_assert(2 * kRunCap * sizeof(int32_t) <= kStage * sizeof(C), "the run table fits in the value stage");
   constexpr int L = kStage / kBlock;
   static_assert(L == 8, "a thread scans the row-start bytes of 8 offsets as one word");
-  __shared__ C lds[kStage];                   // the window's local values, CSR order
-  __shared__ int32_t sst[kStage + 1];         // the window's segment ids, then its row starts
-  __shared__ uint64_t first64[kStage / 8];    // row-start byte per CSR offset
+  constexpr int kSegCap = 256;
+  __shared__ C lds[kStage];                    // the window's local values, CSR order
+  __shared__ uint64_t sraw[(kStage + 8) / 4];  // row-start bytes (until step 3), then 16-bit row starts
+  __shared__ int32_t lseg[kSegCap];            // the window's segment ids, when they fit (else read in place)
   __shared__ int32_t wsum[kBlock / 64];
-  uint8_t* first = reinterpret_cast<uint8_t*>(first64);
+  uint64_t* first64 = sraw;
+  uint8_t* first = reinterpret_cast<uint8_t*>(sraw);
+  uint16_t* sst = reinterpret_cast<uint16_t*>(sraw);
   const int t = threadIdx.x;
   const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
   if (b >= n_pblocks) {  // rows without copies: +0.0
@@ -122,16 +121,24 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
 #pragma unroll
     for (int k = 0; k < L; ++k) gid[k] = prows[r0 + min(t + k * kBlock, nrows - 1)];
   }
-  for (int i = t; i < ns; i += kBlock) sst[i] = segs[s0 + i];
+  const bool seg_lds = ns <= kSegCap;
+  if (seg_lds)
+    for (int i = t; i < ns; i += kBlock) lseg[i] = segs[s0 + i];
 #pragma unroll
   for (int k = 0; k < L; ++k)
     if (t + k * kBlock < n) first[(wd[k] >> 1) & 2047u] = static_cast<uint8_t>(wd[k] & 1u);
   __syncthreads();
   // 2. the values, in address order
   E v[L];
+  if (seg_lds) {
 #pragma unroll
-  for (int k = 0; k < L; ++k)
-    v[k] = xL[static_cast<int64_t>(sst[wd[k] >> 21]) * 512 + ((wd[k] >> 12) & 511u)];
+    for (int k = 0; k < L; ++k)
+      v[k] = xL[static_cast<int64_t>(lseg[wd[k] >> 21]) * 512 + ((wd[k] >> 12) & 511u)];
+  } else {
+#pragma unroll
+    for (int k = 0; k < L; ++k)
+      v[k] = xL[static_cast<int64_t>(segs[s0 + (wd[k] >> 21)]) * 512 + ((wd[k] >> 12) & 511u)];
+  }
   // 3. meanwhile the rows' global ids from the runs (the last run that
   //    starts at or before the row) and the row starts: thread t reads the
   //    row-start bytes of offsets t*L .. t*L+L-1 (every offset below n was
@@ -165,15 +172,15 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const uint32_t* __restri
     if (lane >= off) incl += y;
   }
   if (lane == 63) wsum[w] = incl;
-  __syncthreads();  // also: every segment id has been read
+  __syncthreads();  // also: every row-start byte has been read
   int32_t before = 0;
 #pragma unroll
   for (int i = 0; i < kBlock / 64; ++i) before += (i < w) ? wsum[i] : 0;
   int32_t row = before + incl - tsum;
 #pragma unroll
   for (int i = 0; i < L; ++i)
-    if (t * L + i < n && ((fl >> (8 * i)) & 1u)) sst[row++] = t * L + i;
-  if (t == 0) sst[nrows] = n;
+    if (t * L + i < n && ((fl >> (8 * i)) & 1u)) sst[row++] = static_cast<uint16_t>(t * L + i);
+  if (t == 0) sst[nrows] = static_cast<uint16_t>(n);
   // 4. the values into LDS at their CSR offsets
 #pragma unroll
   for (int k = 0; k < L; ++k)
