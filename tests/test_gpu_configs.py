@@ -241,5 +241,18 @@ def test_benchmark_size_gather_scatter(ctx):
     bs.bs_gather(ctx, plan, xL, xG)
     ref = ms.gather_rows(lambda i: bsgen.uniform_at(SEED, 11, i))
     assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
+    # the benchmark's gather: lattice-tiled rows in its tiles and boxes, variant 0
+    from bench import GATHER_BOX, GATHER_TILE
+    M = K * N + 1
+    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
+    saved = bs.bs_ctx_get_tune(ctx, "gather")
+    try:
+        bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, 0)
+        xG.fill_(float("nan"))
+        bs.bs_gather(ctx, plan, xL, xG)
+    finally:
+        bs.bs_ctx_set_tune(ctx, "gather", *saved)
+    assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
+    assert not torch.isnan(xG).any()
     bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     assert np.array_equal(bits(at(xL, l)), bits(bsgen.uniform_at(SEED, 12, g)))
