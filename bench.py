@@ -199,11 +199,11 @@ def sweep(args, K_max):
     K_gs = min(64, K_max)
     pts = [_mesh_points(K, 7, args.seed, ctx, bs, bsgen, torch, np, reps) for K in range(2, K_gs + 1, 2)]
     print("# swept gather/scatter over K", file=sys.stderr, flush=True)
-    for op in ("scatter", "gather"):
+    for op in ("scatter", "gather", "gather (lattice rows)"):
         results.append(_fit_record(op + " (N=7)", [p[op] for p in pts], perfmodel))
     # gather / scatter at about 5e7 local nodes for N = 1..15
     pts = [_mesh_points(round(368.4 / (N + 1)), N, args.seed, ctx, bs, bsgen, torch, np, reps) for N in range(1, 16)]
-    for op in ("scatter", "gather"):
+    for op in ("scatter", "gather", "gather (lattice rows)"):
         rec = {"op": op + " (N-sweep, ~5e7 local nodes)", "points": [p[op] for p in pts]}
         print(json.dumps(rec))
         results.append(rec)
@@ -226,15 +226,29 @@ def _mesh_points(K, N, seed, ctx, bs, bsgen, torch, np, reps):
     bsgen.device_uniform(xL, seed, bsgen.STREAM["xL"])
     bsgen.device_uniform(xG, seed, bsgen.STREAM["xG"])
     out = {}
+    M = K * N + 1
+    tile = N * max(1, round(GATHER_TILE / N))  # the benchmark's slabs, one element thick, at degree N
+
+    lat_ctx = bs.bs_ctx_create(0)  # gather variant 0 for every length, leaving ctx's tune table whole
+    bs.bs_ctx_set_tune(lat_ctx, "gather", 1, 1 << 30, 0)
+
+    def lattice_gather():
+        bs.bs_gather(lat_ctx, plan, xL, xG)
+
     for op, fn in (("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL)),
-                   ("gather", lambda: bs.bs_gather(ctx, plan, xL, xG))):
+                   ("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
+                   ("gather (lattice rows)", lattice_gather)):
+        if op == "gather (lattice rows)":
+            bs.bs_gs_order_rows(plan, M, M, M, tile, (tile, N, N))
         t_dev, t_host = _time_calls(fn, reps, torch)
         t_graph = _time_graph(fn, reps, torch)
-        B = alg_bytes(0, NL, NG)[op]
+        B = alg_bytes(0, NL, NG)["gather" if op.startswith("gather") else op]
         out[op] = {"K": K, "N": N, "n_local": NL, "n_global": NG, "bytes": B, "t_event_s": t_dev,
                    "t_host_s": t_host, "t_graph_s": t_graph, "GB_s": B / t_dev / 1e9,
                    "GB_s_host": B / t_host / 1e9, "GB_s_graph": B / t_graph / 1e9}
+    torch.cuda.synchronize()
     plan.close()
+    lat_ctx.close()
     return out
 
 
@@ -260,6 +274,10 @@ def _write_sweep_md(path, results, K_max):
              "(smaller working sets stay in the 256 MB Infinity Cache between calls).", "",
              "Graph columns: the 20 calls captured in one HIP graph and replayed, which removes the host's",
              "per-call cost (Python binding and launch) and leaves the device's own launch latency.", "",
+             "Gather and scatter run on permuted, oriented meshes with the plan's default order and the",
+             "tune table's kernel; \"gather (lattice rows)\" is the same plan after bs_gs_order_rows with",
+             "lattice tiles of about 126 points split into slabs one element thick (tile x N x N), gather",
+             "variant 0, as the benchmark step runs it (same bits, row order only).", "",
              "| operation | T0 (us) | W_max (GB/s) | B_0.8 (MB) | W_max >=1GB (GB/s) | graph T0 (us) | graph W_max (GB/s) | graph T0, <=256MB (us) | best GB/s (size) |",
              "|---|---|---|---|---|---|---|---|---|"]
     for r in results:

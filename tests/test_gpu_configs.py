@@ -245,13 +245,12 @@ def test_benchmark_size_gather_scatter(ctx):
     from bench import GATHER_BOX, GATHER_TILE
     M = K * N + 1
     bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
-    saved = bs.bs_ctx_get_tune(ctx, "gather")
-    try:
-        bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, 0)
-        xG.fill_(float("nan"))
-        bs.bs_gather(ctx, plan, xL, xG)
-    finally:
-        bs.bs_ctx_set_tune(ctx, "gather", *saved)
+    own = bs.bs_ctx_create(0)  # its own context: one launch shape for every length
+    bs.bs_ctx_set_tune(own, "gather", 1, 1 << 30, 0)
+    xG.fill_(float("nan"))
+    bs.bs_gather(own, plan, xL, xG)
+    torch.cuda.synchronize()
+    own.close()
     assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
     assert not torch.isnan(xG).any()
     bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)

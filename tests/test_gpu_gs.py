@@ -27,12 +27,13 @@ def with_variant(ctx, variant, unroll=4):
     bs.bs_ctx_set_tune(ctx, "scatter", unroll, 1 << 30, variant)
 
 
-@pytest.fixture(autouse=True)
-def default_variants(ctx):
-    saved = {op: bs.bs_ctx_get_tune(ctx, op) for op in ("gather", "scatter")}
-    yield
-    for op, (u, g, v) in saved.items():
-        bs.bs_ctx_set_tune(ctx, op, u, g, v)
+@pytest.fixture
+def ctx():
+    # a context per test: tests set one launch shape for every length, which
+    # would otherwise replace the shared context's whole tune table
+    c = bs.bs_ctx_create(0)
+    yield c
+    c.close()
 
 
 def device_map(K, N, seed):
