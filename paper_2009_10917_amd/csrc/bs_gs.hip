@@ -318,7 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ r
 // tile the (global id, local offset) pairs are read in ascending global id
 // (PACKED: one word per pair, id - tile minimum above the 9-bit offset), the
 // values fetched in that order and put in place through LDS, and the tile's
-// entries are written contiguously.
+// entries are written contiguously.  The plan stores the pairs in visiting
+// order, so they are loaded alongside the tile's index, not after it.
 template <class E, int TPW, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __restrict__ order,
                                                            const int32_t* __restrict__ tgid,
@@ -339,8 +340,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
   for (int i = 0; i < TPW; ++i) tile[i] = order[min(t0 + i, n_tiles - 1)];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
-    cnt[i] = (t0 + i < n_tiles) ? tcnt[tile[i]] : 0;
-    if (PACKED) g0[i] = tmin[tile[i]];
+    const int64_t v = min(t0 + i, n_tiles - 1);
+    cnt[i] = (t0 + i < n_tiles) ? tcnt[v] : 0;
+    if (PACKED) g0[i] = tmin[v];
   }
 #pragma unroll
   for (int i = 0; i < TPW; ++i)
@@ -353,13 +355,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int q = min(static_cast<int>(threadIdx.x) + k * kBlock, kTile - 1);
+      const int64_t v = min(t0 + i, n_tiles - 1);
       if (PACKED) {
-        const uint32_t w = dev::ld_nt(tword + tile[i] * kTile + q);
+        const uint32_t w = dev::ld_nt(tword + v * kTile + q);
         g[i][k] = g0[i] + static_cast<int32_t>(w >> 9);
         o[i][k] = static_cast<uint16_t>(w & 511u);
       } else {
-        g[i][k] = dev::ld_nt(tgid + tile[i] * kTile + q);
-        o[i][k] = dev::ld_nt(tloc + tile[i] * kTile + q);
+        g[i][k] = dev::ld_nt(tgid + v * kTile + q);
+        o[i][k] = dev::ld_nt(tloc + v * kTile + q);
       }
     }
   E v[TPW][P];

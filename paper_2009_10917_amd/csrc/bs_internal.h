@@ -102,13 +102,15 @@ struct bs_gs {
   int64_t chunk;
 
   // Scatter: tiles of kTile consecutive local entries, visited in the order
-  // of the smallest global id each references (tile_order); within tile t,
-  // entry k of tile_gid/tile_loc is the k-th smallest (global id, local
-  // offset) pair, masked entries excluded (tile_count[t] valid pairs).
+  // of the smallest global id each references (tile_order[v] is the v-th
+  // tile visited); for the v-th tile visited, entry k of tile_gid/tile_loc
+  // (at v * kTile + k) is its k-th smallest (global id, local offset) pair,
+  // masked entries excluded (tile_count[v] valid pairs): the pairs are
+  // stored in visiting order.
   // When every tile's ids span less than 2^23 (tile_packed), the pairs are
   // kept as one word each instead: tile_word = (id - tile_min[t]) << 9 |
-  // offset, tile_min[t] the tile's smallest id; tile_gid/tile_loc are then
-  // not kept.
+  // offset, tile_min[v] the tile's smallest id (visiting order again);
+  // tile_gid/tile_loc are then not kept.
   int32_t* tile_order;   // [n_tiles]
   int32_t* tile_gid;     // [n_tiles * kTile]
   uint16_t* tile_loc;    // [n_tiles * kTile]

@@ -186,6 +186,32 @@ __global__ __launch_bounds__(kBlock) void k_tile_sort(const int32_t* __restrict_
   }
 }
 
+// The sorted pairs of the tiles in visiting order: entry v of the outputs
+// holds tile order[v] (so that a scatter workgroup reads them by its own
+// position, in parallel with order[v]).
+__global__ __launch_bounds__(kBlock) void k_tile_permute(const int32_t* __restrict__ order,
+                                                         const int32_t* __restrict__ tcnt,
+                                                         const int32_t* __restrict__ tmin,
+                                                         const uint32_t* __restrict__ tword,
+                                                         const int32_t* __restrict__ tgid,
+                                                         const uint16_t* __restrict__ tloc, int32_t* __restrict__ vcnt,
+                                                         int32_t* __restrict__ vmin, uint32_t* __restrict__ vword,
+                                                         int32_t* __restrict__ vgid, uint16_t* __restrict__ vloc) {
+  const int64_t v = blockIdx.x;
+  const int64_t tile = order[v];
+  if (threadIdx.x == 0) {
+    vcnt[v] = tcnt[tile];
+    if (vmin) vmin[v] = tmin[tile];
+  }
+  for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    if (vword) vword[v * kTile + k] = tword[tile * kTile + k];
+    if (vgid) {
+      vgid[v * kTile + k] = tgid[tile * kTile + k];
+      vloc[v * kTile + k] = tloc[tile * kTile + k];
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_invert(const int32_t* __restrict__ order, int64_t n,
                                                    int32_t* __restrict__ rank) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -544,7 +570,7 @@ void build_gather_blocks(Builder& B, bs_gs* gs) {
 void build_scatter_tiles(Builder& B, bs_gs* gs) {
   const int64_t nt = (gs->n_local + kTile - 1) / kTile;
   gs->n_tiles = nt;
-  DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx, tword, tmin, wide;
+  DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx, tword, tmin, wide, vcnt, vmin, vword, vgid, vloc;
   B.need(tgid, nt * kTile * 4, "tile ids");
   B.need(tloc, nt * kTile * 2, "tile offsets");
   B.need(tword, nt * kTile * 4, "tile words");
@@ -573,14 +599,32 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
   gs->tile_packed = B.read(wide.as<int>()) == 0;
+  // the kept form of the pairs, in visiting order
+  B.need(vcnt, nt * 4, "tile counts");
   if (gs->tile_packed) {  // one word per pair
-    gs->tile_word = tword.release<uint32_t>();
-    gs->tile_min = tmin.release<int32_t>();
+    B.need(vmin, nt * 4, "tile minima");
+    B.need(vword, nt * kTile * 4, "tile words");
   } else {
-    gs->tile_gid = tgid.release<int32_t>();
-    gs->tile_loc = tloc.release<uint16_t>();
+    B.need(vgid, nt * kTile * 4, "tile ids");
+    B.need(vloc, nt * kTile * 2, "tile offsets");
   }
-  gs->tile_count = tcnt.release<int32_t>();
+  if (!B.ok()) return;
+  if (nt > 0)
+    hipLaunchKernelGGL(k_tile_permute, dim3(static_cast<unsigned int>(nt)), dim3(kBlock), 0, B.st,
+                       order.as<int32_t>(), tcnt.as<int32_t>(), tmin.as<int32_t>(), tword.as<uint32_t>(),
+                       tgid.as<int32_t>(), tloc.as<uint16_t>(), vcnt.as<int32_t>(), vmin.as<int32_t>(),
+                       vword.as<uint32_t>(), vgid.as<int32_t>(), vloc.as<uint16_t>());
+  B.launched();
+  B.hip(hipStreamSynchronize(B.st));
+  if (!B.ok()) return;
+  if (gs->tile_packed) {
+    gs->tile_word = vword.release<uint32_t>();
+    gs->tile_min = vmin.release<int32_t>();
+  } else {
+    gs->tile_gid = vgid.release<int32_t>();
+    gs->tile_loc = vloc.release<uint16_t>();
+  }
+  gs->tile_count = vcnt.release<int32_t>();
   gs->tile_order = order.release<int32_t>();
 }
 
