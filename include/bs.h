@@ -114,7 +114,10 @@ bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int g
  * look up the plan's local length).  bs_ctx_set_tune replaces them with one
  * entry for every dtype and length; bs_ctx_set_tune_entry inserts or
  * replaces the entry of one (op, dtype, n_min); bs_ctx_tune_for reports
- * the entry used for length n; bs_ctx_get_tune reports the n_min = 0 one.
+ * the entry used for length n; bs_ctx_get_tune reports the n_min = 0 one;
+ * bs_ctx_reset_tune restores what bs_ctx_create set up (the built-in
+ * defaults, then the table beside the library or the one BS_TUNE_FILE
+ * names; on a load error the defaults stay and the error is returned).
  *
  * bs_ctx_load_tune reads a text table, one entry per line:
  *     op dtype n_min unroll grid_cap variant      (# starts a comment)
@@ -132,6 +135,7 @@ bs_status bs_ctx_set_tune_entry(bs_ctx* ctx, int op, bs_dtype dtype, int64_t n_m
 bs_status bs_ctx_tune_for(const bs_ctx* ctx, int op, bs_dtype dtype, int64_t n, int* unroll, int* grid_cap,
                           int* variant);
 bs_status bs_ctx_load_tune(bs_ctx* ctx, const char* path, int* n_entries);
+bs_status bs_ctx_reset_tune(bs_ctx* ctx);
 bs_status bs_ctx_get_tune(const bs_ctx* ctx, int op, bs_dtype dtype, int* unroll, int* grid_cap,
                           int* variant);
 

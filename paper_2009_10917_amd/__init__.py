@@ -64,6 +64,7 @@ PROTOTYPES = {
     "bs_ctx_set_tune_entry": (_st, [_p, _i32, _i32, _i64, _i32, _i32, _i32]),
     "bs_ctx_tune_for": (_st, [_p, _i32, _i32, _i64, _p, _p, _p]),
     "bs_ctx_load_tune": (_st, [_p, ctypes.c_char_p, _p]),
+    "bs_ctx_reset_tune": (_st, [_p]),
     "bs_batch_create": (_st, [_p, _i32, _p, _p, _p, _p, _p]),
     "bs_batch_destroy": (_st, [_p]),
     "bs_batch_info": (_st, [_p, _p, _p, _p, _p, _p]),
@@ -467,6 +468,11 @@ def bs_ctx_tune_for(ctx, op, n, dtype=BS_F64):
     _check(lib.bs_ctx_tune_for(ctx.handle, _op_id(op), int(dtype), int(n), *[ctypes.byref(a) for a in v]),
            "bs_ctx_tune_for")
     return tuple(a.value for a in v)
+
+
+def bs_ctx_reset_tune(ctx):
+    """Restore the tune table the context was created with (defaults, then the installed table)."""
+    _check(lib.bs_ctx_reset_tune(ctx.handle), "bs_ctx_reset_tune")
 
 
 def bs_ctx_load_tune(ctx, path):

@@ -160,9 +160,23 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
     (void)hipSetDevice(prev);
     return s;
   }
-  set_defaults(c);
-  // A tune table next to the library (written by the autotuner), or the one
-  // BS_TUNE_FILE names ("none": keep the defaults).
+  if ((s = bs_ctx_reset_tune(c))) {
+    (void)hipFree(ws);
+    delete c;
+    (void)hipSetDevice(prev);
+    return s;
+  }
+  (void)hipSetDevice(prev);
+  *out = c;
+  return BS_OK;
+}
+
+// The built-in defaults, then a tune table next to the library (written by
+// the autotuner), or the one BS_TUNE_FILE names ("none": keep the defaults).
+extern "C" bs_status bs_ctx_reset_tune(bs_ctx* ctx) {
+  bs_status s;
+  if ((s = check_ctx(ctx, "bs_ctx_reset_tune"))) return s;
+  set_defaults(ctx);
   std::string path;
   if (const char* env = std::getenv("BS_TUNE_FILE")) {
     path = env;
@@ -179,18 +193,10 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
       }
     }
   }
-  if (!path.empty() && path != "none") {
-    int entries = 0;
-    if ((s = bs_ctx_load_tune(c, path.c_str(), &entries))) {
-      (void)hipFree(ws);
-      delete c;
-      (void)hipSetDevice(prev);
-      return s;
-    }
-  }
-  (void)hipSetDevice(prev);
-  *out = c;
-  return BS_OK;
+  if (path.empty() || path == "none") return BS_OK;
+  int entries = 0;
+  if ((s = bs_ctx_load_tune(ctx, path.c_str(), &entries))) set_defaults(ctx);
+  return s;
 }
 
 extern "C" bs_status bs_ctx_destroy(bs_ctx* ctx) {

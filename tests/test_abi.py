@@ -68,6 +68,7 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_gs_info(None, None, None, None, None) == INVALID
     assert L.bs_gs_degree(None, 16, None) == INVALID
     assert L.bs_ctx_set_tune(None, 0, 0, 4, 16, 0) == INVALID
+    assert L.bs_ctx_reset_tune(None) == INVALID
     out = ctypes.c_void_p()
     assert L.bs_gs_create(None, 16, 10, 10, None, ctypes.byref(out)) == INVALID
     assert L.bs_stencil7(None, 0, 3, 0.01, 16, 32, None) == INVALID

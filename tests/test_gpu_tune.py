@@ -102,3 +102,20 @@ def test_installed_table_loads(ctx):
     c = bs.bs_ctx_create(0)
     assert bs.bs_ctx_load_tune(c, path) > 0
     c.close()
+
+
+def test_reset_restores_the_table_set_tune_replaced():
+    # bs_ctx_set_tune leaves one entry for every length; bs_ctx_reset_tune
+    # brings back what bs_ctx_create set up, length by length
+    fresh = bs.bs_ctx_create(0)
+    c = bs.bs_ctx_create(0)
+    lengths = (1, 1 << 16, 1 << 20, 1 << 24, 1 << 27, 1 << 30)
+    ops = ("copy", "axpy", "norm", "dot", "cg_update", "gather", "scatter")
+    want = {(op, d, n): bs.bs_ctx_tune_for(fresh, op, n, d) for op in ops for d in (0, 1, 2) for n in lengths}
+    for op in ops:
+        bs.bs_ctx_set_tune(c, op, 2, 1024, 1 if op in ("gather", "scatter") else 0)
+    bs.bs_ctx_reset_tune(c)
+    got = {(op, d, n): bs.bs_ctx_tune_for(c, op, n, d) for op in ops for d in (0, 1, 2) for n in lengths}
+    assert got == want
+    fresh.close()
+    c.close()
