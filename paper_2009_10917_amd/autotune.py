@@ -11,7 +11,9 @@ bs_ctx_create picks it up; BS_TUNE_FILE overrides it.
 Candidates:
   copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass}
   norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536}
-  cg_update           (the reductions' partial buffer holds 65536 pairs)
+  cg_update           (the reductions' partial buffer holds 65536 pairs), and cap 1
+                      up to 2^20 elements (one workgroup finishes the sum in the
+                      same launch)
   gather, scatter   kernel variant {0, 1, 2}, each with and without the XCD
                     renumbering, on permuted and oriented N = 7 meshes, with
                     plans as bs_gs_create builds them (a caller that applies
@@ -96,6 +98,8 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
             reps = 50 if n <= (1 << 20) else 10
             for op in STREAM_OPS:
                 caps = (256, 1024, 4096, 16384, 65536) if op in REDUCTIONS else (1024, 4096, 16384, 65536, 1 << 30)
+                if op in REDUCTIONS and n <= (1 << 20):
+                    caps = (1,) + caps
                 times = {}
                 for u in (1, 2, 4, 8):
                     for g in caps:
