@@ -183,3 +183,48 @@ def test_gather_scatter_weights(ctx, name):
     o = scalar_out()
     bs.bs_norm(ctx, torch.ones(NL, dtype=dt, device="cuda"), wL, o)
     assert float(to_host(o)[0]) == float(NG)
+
+
+@pytest.mark.parametrize("name", list(DTYPES))
+def test_gather_scatter_every_variant(name):
+    # every gather variant adds each row's copies in the same order in the
+    # same type, so all give the same bits (also after the lattice row
+    # order); every scatter variant copies stored values exactly
+    dt, us = DTYPES[name]
+    K, N = 7, 7
+    E, NL, NG = mesh.sizes(K, N)
+    M = K * N + 1
+    perm, orient = bsgen.permutation(SEED, E), bsgen.orientations(SEED, E)
+    ids = mesh.hex_map(K, N, perm, orient)
+    ids[5::37] = -1
+    c = bs.bs_ctx_create(0)  # its own context: one launch shape for every length
+    plan = bs.bs_gs_create(c, torch.from_numpy(ids.astype(np.int32)).cuda(), NG)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    xL, hxL = stored(dt, NL, 11)
+    S = ops.gather(rs, ci, hxL)
+    A = ops.gather(rs, ci, np.abs(hxL))
+    deg = np.diff(rs)
+    outs = []
+    for order in ("plan", "lattice"):
+        if order == "lattice":
+            bs.bs_gs_order_rows(plan, M, M, M, 21, (21, 7, 7))
+        for v in (0, 1, 2, 4, 5, 6):
+            bs.bs_ctx_set_tune(c, "gather", 1, 1 << 30, v)
+            xG = torch.full((NG,), float("nan"), dtype=dt, device="cuda")
+            bs.bs_gather(c, plan, xL, xG)
+            got = as_f64(xG)
+            assert np.all(np.abs(got - S) <= us * np.abs(S) + deg * U32 * A + 1e-40), (order, v)
+            outs.append(got.view(np.int64).copy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    g2, hg2 = stored(dt, NG, 12)
+    ref = hxL.copy()
+    ref[ids >= 0] = hg2[ids[ids >= 0]]
+    for v in (0, 1, 2, 4, 5, 6):
+        for u in ((1, 2, 4) if v % 4 < 2 else (1, 8)):
+            bs.bs_ctx_set_tune(c, "scatter", u, 1 << 30, v)
+            x2 = xL.clone()
+            bs.bs_scatter(c, plan, g2, x2)
+            assert np.array_equal(as_f64(x2), ref), (v, u)
+    torch.cuda.synchronize()
+    plan.close()
+    c.close()
