@@ -90,10 +90,15 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
  * the number of 256-thread workgroups (kernels grid-stride beyond it;
- * reductions are further capped at 65536); variant (gather and scatter
- * only; other ops ignore it) is a kernel choice plus 4 to keep the
- * hardware's workgroup order instead of giving each XCD a contiguous range
- * of blocks.  Gather: 0 = rows in the plan's permuted order (by default
+ * reductions are further capped at 65536).  variant, for copy, axpy,
+ * norm, dot and cg_update, is the workgroup order: 0 as the hardware
+ * dispatches them (round-robin over the 8 XCDs, so the XCDs interleave 4 KB
+ * slices of each operand), 1 the 256 workgroups one XCD receives in each
+ * group of 2048 take consecutive block numbers (1 MB runs per XCD), 2 each
+ * XCD takes one contiguous range of blocks over the whole grid; other
+ * values act as 0.  For gather and scatter, variant is a kernel choice plus
+ * 4 to keep the hardware's workgroup order instead of giving each XCD a
+ * contiguous range of blocks.  Gather: 0 = rows in the plan's permuted order (by default
  * grouped by the scatter tiles that hold their copies; bs_gs_order_rows
  * replaces it with lattice tiles; falls back to 1 when a degree exceeds
  * 1024), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local

@@ -13,7 +13,8 @@ Candidates:
   norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536}
   cg_update           (the reductions' partial buffer holds 65536 pairs), and cap 1
                       up to 2^20 elements (one workgroup finishes the sum in the
-                      same launch)
+                      same launch); from 2^20 elements on, each shape also with
+                      the two XCD-grouped workgroup orders (variants 1 and 2)
   gather, scatter   kernel variant {0, 1, 2}, each with and without the XCD
                     renumbering, on permuted and oriented N = 7 meshes, with
                     plans as bs_gs_create builds them (a caller that applies
@@ -101,12 +102,16 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
                 if op in REDUCTIONS and n <= (1 << 20):
                     caps = (1,) + caps
                 times = {}
+                # below 2^20 elements a launch has fewer than 2048 workgroups (or one),
+                # where the orders differ little
+                orders = (0, 1, 2) if n >= (1 << 20) else (0,)
                 for u in (1, 2, 4, 8):
                     for g in caps:
-                        bs.bs_ctx_set_tune(ctx, op, u, g, 0)
-                        times[(u, g, 0)] = _time(torch, calls[op], reps)
-                        log.write(json.dumps({"op": op, "dtype": dname, "n": n, "unroll": u, "grid_cap": g,
-                                              "ms": round(times[(u, g, 0)], 5)}) + "\n")
+                        for v in orders:
+                            bs.bs_ctx_set_tune(ctx, op, u, g, v)
+                            times[(u, g, v)] = _time(torch, calls[op], reps)
+                            log.write(json.dumps({"op": op, "dtype": dname, "n": n, "unroll": u, "grid_cap": g,
+                                                  "variant": v, "ms": round(times[(u, g, v)], 5)}) + "\n")
                 choice = _pick(times, DEFAULTS[op])
                 entries.append((op, dname, n_min, *choice))
                 bs.bs_ctx_set_tune(ctx, op, *DEFAULTS[op])

@@ -4,7 +4,8 @@
 // All five stream their operands once through 16-byte packets (dwordx4
 // loads and stores).  A workgroup of 256 threads handles U packets per
 // thread per trip and the grid strides over the vector beyond `grid_cap`
-// workgroups.  Scalar elements that precede the first 16-byte boundary or
+// workgroups, numbered in the dispatch order or grouped per XCD (the tune
+// variant).  Scalar elements that precede the first 16-byte boundary or
 // follow the last full packet are handled by workgroup 0.  When the operands
 // are not mutually 16-byte aligned the same kernels run with one-element
 // packets.
@@ -106,6 +107,10 @@ bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char*
   return check_launch(op);
 }
 
+// Tune variant of a streaming operation -> Span::order (1 and 2 select the
+// XCD-grouped workgroup orders; anything else keeps the dispatch order).
+inline int stream_order(int variant) { return (variant == 1 || variant == 2) ? variant : 0; }
+
 inline int norm_unroll(int u) { return (u >= 8) ? 8 : (u >= 4) ? 4 : (u >= 2) ? 2 : 1; }
 
 // Launch `K<T, V, U>` for the runtime unroll and packet width.
@@ -146,8 +151,9 @@ template <class T> constexpr int dtype_index() { return std::is_same<T, double>:
 
 template <class T>
 bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t st) {
-  const Span sp = make_span<T>(n, {x, y});
+  Span sp = make_span<T>(n, {x, y});
   const Tune& tn = tune_for(ctx, OP_COPY, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
   BS_DISPATCH(k_copy, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
@@ -157,8 +163,9 @@ bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t s
 template <class T>
 bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double beta, void* y, hipStream_t st) {
   using C = typename Storage<T>::C;
-  const Span sp = make_span<T>(n, {x, y});
+  Span sp = make_span<T>(n, {x, y});
   const Tune& tn = tune_for(ctx, OP_AXPY, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
   BS_DISPATCH(k_axpy, T, sp, u, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
@@ -168,8 +175,9 @@ bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double b
 
 template <class T>
 bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double* out, hipStream_t st) {
-  const Span sp = make_span<T>(n, {x, w});
+  Span sp = make_span<T>(n, {x, w});
   const Tune& tn = tune_for(ctx, OP_NORM, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
@@ -184,8 +192,9 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
 
 template <class T>
 bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* out, hipStream_t st) {
-  const Span sp = make_span<T>(n, {x, y});
+  Span sp = make_span<T>(n, {x, y});
   const Tune& tn = tune_for(ctx, OP_DOT, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
@@ -197,8 +206,9 @@ template <class T>
 bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const void* p, void* r, const void* Ap,
                         const void* w, double* out, hipStream_t st) {
   using C = typename Storage<T>::C;
-  const Span sp = make_span<T>(n, {x, p, r, Ap, w});
+  Span sp = make_span<T>(n, {x, p, r, Ap, w});
   const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);

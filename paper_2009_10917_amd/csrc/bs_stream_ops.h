@@ -24,7 +24,28 @@ struct Span {
   int64_t nvec;
   int32_t head;
   int32_t vwidth;
+  int32_t order;  // workgroup order, see logical_block
 };
+
+// Which packets workgroup blockIdx.x streams.  order 0: as dispatched, so
+// the 8 XCDs interleave 4 KB slices of every operand.  order 1: in each group
+// of 2048 workgroups, the 256 that one XCD receives (hardware ids p with the
+// same p % 8) take 256 consecutive block numbers, so each XCD streams 1 MB
+// runs of each operand; a ragged last group keeps the dispatch order.
+// order 2: one contiguous range of blocks per XCD over the whole grid.
+__device__ __forceinline__ int64_t logical_block(const Span& sp) {
+  const uint32_t p = blockIdx.x, G = gridDim.x;
+  if (sp.order == 1) {
+    constexpr uint32_t kGroup = 2048, kX = 8;
+    if (p < G / kGroup * kGroup) {
+      const uint32_t r = p % kGroup;
+      return (p - r) + (r % kX) * (kGroup / kX) + r / kX;
+    }
+    return p;
+  }
+  if (sp.order == 2) return dev::xcd_block(p, G);
+  return p;
+}
 
 // Element handled by thread threadIdx.x of workgroup 0 in the scalar head or
 // tail, or -1.  head < V <= 8 and tail < V, so 32 threads cover both.
@@ -36,16 +57,16 @@ __device__ __forceinline__ int64_t scalar_index(const Span& sp) {
   return -1;
 }
 
-// The streaming loop shared by BS1-BS5.  Thread t of workgroup b owns
-// packets i, i + 256, ..., i + (U-1)*256 with i = b*256*U + t and strides by
-// the whole grid.  Each trip first issues all of its loads (op.load), then
+// The streaming loop shared by BS1-BS5.  Thread t of workgroup b (the
+// logical block number) owns packets i, i + 256, ..., i + (U-1)*256 with
+// i = b*256*U + t and strides by the whole grid.  Each trip first issues all of its loads (op.load), then
 // computes and stores (op.apply), so U packets per operand are in flight.
 // Trips that are entirely in range run without bounds checks; only the last
 // (ragged) trip of a thread checks each packet.
 template <int U, class Op>
 __device__ __forceinline__ void stream_loop(Op& op, const Span& sp) {
   const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock * U;
-  int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock * U + threadIdx.x;
+  int64_t i = logical_block(sp) * kBlock * U + threadIdx.x;
   for (; i + static_cast<int64_t>(U - 1) * kBlock < sp.nvec; i += step) {
     typename Op::Regs r[U];
 #pragma unroll
@@ -246,6 +267,7 @@ Span make_span(int64_t n, std::initializer_list<const void*> ptrs) {
     if (q && reinterpret_cast<uintptr_t>(q) % 16 != m) same = false;
   Span sp;
   sp.n = n;
+  sp.order = 0;
   if (same) {
     int64_t head = m ? static_cast<int64_t>((16 - m) / sizeof(E)) : 0;
     if (head > n) head = n;

@@ -195,6 +195,48 @@ def test_launch_shapes_do_not_change_results(unroll, cap):
         ctx.close()
 
 
+@pytest.fixture(scope="module")
+def order_case():
+    # long enough that unroll 1 launches several groups of 2048 workgroups and a ragged last one
+    n = 9_000_017
+    h = {k: host_uniform(n, s, lo=0.0 if k == "w" else -1.0) for k, s in (("x", 1), ("y", 2), ("p", 3), ("Ap", 4), ("w", 5))}
+    xr, rr, rho = ops.cg_update(0.37, h["x"], h["p"], h["y"], h["Ap"], h["w"])
+    return n, {"axpy": bits(ops.axpy(0.37, h["x"], 0.61, h["y"])), "norm": ops.norm(h["x"], h["w"]),
+               "dot": ops.dot(h["x"], h["y"]), "cg_x": bits(xr), "cg_r": bits(rr), "cg_rho": rho,
+               "x": bits(h["x"])}
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("unroll,cap", [(1, 1 << 30), (4, 65536), (2, 3000), (8, 7)])
+def test_workgroup_orders_do_not_change_results(order_case, order, unroll, cap):
+    # variant 1 and 2 of the streaming operations renumber workgroups per XCD; every
+    # element is still handled once, so vectors stay bit-exact and sums within tolerance
+    n, want = order_case
+    ctx = bs.bs_ctx_create(0)
+    try:
+        for op in ("copy", "axpy", "norm", "dot", "cg_update"):
+            bs.bs_ctx_set_tune(ctx, op, unroll, cap, order)
+            assert bs.bs_ctx_tune_for(ctx, op, n) == (unroll, cap, order)
+        x, y, p, Ap, w = (dev_uniform(n, s, lo=0.0 if s == 5 else -1.0) for s in (1, 2, 3, 4, 5))
+        z = torch.full_like(x, float("nan"))
+        bs.bs_copy(ctx, x, z)
+        assert np.array_equal(bits(to_host(z)), want["x"])
+        o = scalar_out()
+        bs.bs_norm(ctx, x, w, o)
+        assert rel_err(float(to_host(o)[0]), want["norm"]) <= TOL
+        bs.bs_dot(ctx, x, y, o)
+        assert rel_err(float(to_host(o)[0]), want["dot"]) <= TOL
+        r = y.clone()
+        bs.bs_cg_update(ctx, 0.37, z, p, r, Ap, w, o)
+        assert np.array_equal(bits(to_host(z)), want["cg_x"]) and np.array_equal(bits(to_host(r)), want["cg_r"])
+        assert rel_err(float(to_host(o)[0]), want["cg_rho"]) <= TOL
+        bs.bs_axpy(ctx, 0.37, x, 0.61, y)
+        assert np.array_equal(bits(to_host(y)), want["axpy"])
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+
 def test_error_paths(ctx):
     L = bs.lib
     x = torch.zeros(64, dtype=torch.float64, device="cuda")
