@@ -96,9 +96,10 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * slices of each operand), 1 the 256 workgroups one XCD receives in each
  * group of 2048 take consecutive block numbers (1 MB runs per XCD), 2 each
  * XCD takes one contiguous range of blocks over the whole grid; other
- * values act as 0.  For gather and scatter, variant is a kernel choice plus
- * 4 to keep the hardware's workgroup order instead of giving each XCD a
- * contiguous range of blocks.  Gather: 0 = rows in the plan's permuted order (by default
+ * values act as 0.  For gather and scatter, variant is a kernel choice,
+ * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
+ * 256 blocks per XCD in every group of 2048, instead of one contiguous range
+ * of blocks per XCD.  Gather: 0 = rows in the plan's permuted order (by default
  * grouped by the scatter tiles that hold their copies; bs_gs_order_rows
  * replaces it with lattice tiles; falls back to 1 when a degree exceeds
  * 1024), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local

@@ -15,8 +15,9 @@ Candidates:
                       up to 2^20 elements (one workgroup finishes the sum in the
                       same launch); from 2^20 elements on, each shape also with
                       the two XCD-grouped workgroup orders (variants 1 and 2)
-  gather, scatter   kernel variant {0, 1, 2}, each with and without the XCD
-                    renumbering, on permuted and oriented N = 7 meshes, with
+  gather, scatter   kernel variant {0, 1, 2}, each in the three workgroup orders
+                    (one range per XCD, +4 dispatch order, +8 runs of 256 blocks
+                    per XCD), on permuted and oriented N = 7 meshes, with
                     plans as bs_gs_create builds them (a caller that applies
                     bs_gs_order_rows chooses gather variant 0 itself); for the
                     scatter's tile variants (0, 1) also 1, 2 or 4 tiles per
@@ -147,7 +148,7 @@ def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
             for op, call in (("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
                              ("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL))):
                 times = {}
-                for v in (0, 1, 2, 4, 5, 6):
+                for v in (0, 1, 2, 4, 5, 6, 8, 9, 10):
                     unrolls = (1,) if op == "gather" else ((1, 2, 4) if v % 4 < 2 else (1, 4))
                     for u in unrolls:
                         bs.bs_ctx_set_tune(ctx, op, u, 1 << 30, v)

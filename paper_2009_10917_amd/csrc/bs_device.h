@@ -191,5 +191,22 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t p, uint32_t G) {
   return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// In each group of 2048 dispatch ids, the 256 that one XCD receives (the same
+// p % 8) take 256 consecutive block numbers; a ragged last group keeps the
+// dispatch order.  Each XCD works through runs of neighbouring blocks while
+// the grid as a whole still sweeps the data front to back.
+__device__ __forceinline__ uint32_t group_block(uint32_t p, uint32_t G) {
+  constexpr uint32_t kGroup = 2048, X = 8;
+  if (p >= G / kGroup * kGroup) return p;
+  const uint32_t r = p % kGroup;
+  return (p - r) + (r % X) * (kGroup / X) + r / X;
+}
+
+// Block number of dispatch id p under workgroup order 0 (as dispatched),
+// 1 (group_block) or 2 (xcd_block).
+__device__ __forceinline__ uint32_t block_order(uint32_t p, uint32_t G, int order) {
+  return order == 1 ? group_block(p, G) : order == 2 ? xcd_block(p, G) : p;
+}
+
 }  // namespace dev
 }  // namespace bs

@@ -25,9 +25,10 @@
 //   1  the same tiles, read in local order
 //   2  local order over the whole vector, `unroll` entries per thread
 //
-// Unless the tune variant has kNoXcdRemap set, workgroups are renumbered per
-// XCD so that neighbouring blocks, which share cache lines, run on the same
-// XCD's L2.
+// Workgroups are renumbered per XCD so that neighbouring blocks, which share
+// cache lines, run on the same XCD's L2: by default each XCD takes one
+// contiguous range of blocks; the tune variant may instead keep the dispatch
+// order (+4) or give each XCD runs of 256 blocks in every group of 2048 (+8).
 
 #include <type_traits>
 
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
     const int32_t* __restrict__ prows, const int32_t* __restrict__ runoff, const int32_t* __restrict__ runs,
     const int32_t* __restrict__ pbstart, const int32_t* __restrict__ pbnz0,
     const typename Storage<T>::E* __restrict__ xL, typename Storage<T>::E* __restrict__ xG, int64_t n_pblocks,
-    int64_t n_nzrows, int64_t n_rows, bool remap) {
+    int64_t n_nzrows, int64_t n_rows, int wg_order) {
   using S = Storage<T>;
   using C = typename S::C;
   using E = typename S::E;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
   uint8_t* first = reinterpret_cast<uint8_t*>(sraw);
   uint16_t* sst = reinterpret_cast<uint16_t*>(sraw);
   const int t = threadIdx.x;
-  const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t b = dev::block_order(blockIdx.x, gridDim.x, wg_order);
   if (b >= n_pblocks) {  // rows without copies: +0.0
     const int64_t q = n_nzrows + (b - n_pblocks) * kBlock + t;
     if (q < n_rows) dev::st_nt(xG + prows[q], S::store(C(0)));
@@ -201,13 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_nnz(const int32_t* __restrict
                                                        const int32_t* __restrict__ bstart,
                                                        const typename Storage<T>::E* __restrict__ xL,
                                                        typename Storage<T>::E* __restrict__ xG, int64_t chunk,
-                                                       int64_t nnz, bool remap) {
+                                                       int64_t nnz, int wg_order) {
   using S = Storage<T>;
   using C = typename S::C;
   constexpr int L = kStage / kBlock;
   __shared__ C lds[kStage];            // local values of the CSR window
   __shared__ int32_t srs[kStage + 1];  // row starts of the block's rows
-  const int64_t b = remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t b = dev::block_order(blockIdx.x, gridDim.x, wg_order);
   const int64_t w0 = b * chunk;  // CSR window [w0, w0 + kStage)
   // 1. window values: all column ids, then the local values they name
   //    (lanes past the end repeat the last entry, so that no load waits
@@ -264,14 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_nnz(const int32_t* __restrict
 template <class T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ rs, const int32_t* __restrict__ ci,
                                                    const typename Storage<T>::E* __restrict__ xL,
-                                                   typename Storage<T>::E* __restrict__ xG, int32_t n_global, bool remap) {
+                                                   typename Storage<T>::E* __restrict__ xG, int32_t n_global, int wg_order) {
   using S = Storage<T>;
   using C = typename S::C;
   constexpr int R = kBlock * RPT;    // rows per workgroup
   constexpr int CAP = 8 * R;         // staged values: up to an average degree of 8
   constexpr int L = CAP / kBlock;    // staged values per thread
   __shared__ C lds[CAP];
-  const int32_t b = static_cast<int32_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
+  const int32_t b = static_cast<int32_t>(dev::block_order(blockIdx.x, gridDim.x, wg_order));
   const int32_t row0 = b * R;
   const int32_t row1 = min(row0 + R, n_global);
   const int32_t base = rs[row0];
@@ -328,11 +329,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
                                                            const int32_t* __restrict__ tmin,
                                                            const int32_t* __restrict__ tcnt, const E* __restrict__ xG,
                                                            E* __restrict__ xL, int64_t n_local, int64_t n_tiles,
-                                                           bool remap) {
+                                                           int wg_order) {
   constexpr int P = kTile / kBlock;
   __shared__ E val[TPW][kTile];
   __shared__ uint8_t has[TPW][kTile];
-  const int64_t t0 = static_cast<int64_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * TPW;
+  const int64_t t0 = static_cast<int64_t>(dev::block_order(blockIdx.x, gridDim.x, wg_order)) * TPW;
   int64_t tile[TPW];
   int cnt[TPW];
   int32_t g0[TPW];
@@ -404,9 +405,9 @@ template <class E, int TPW>
 __global__ __launch_bounds__(kBlock) void k_scatter_tiles(const int32_t* __restrict__ map,
                                                           const int32_t* __restrict__ order,
                                                           const E* __restrict__ xG, E* __restrict__ xL,
-                                                          int64_t n_local, int64_t n_tiles, bool remap) {
+                                                          int64_t n_local, int64_t n_tiles, int wg_order) {
   constexpr int P = kTile / kBlock;
-  const int64_t t0 = static_cast<int64_t>(remap ? dev::xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * TPW;
+  const int64_t t0 = static_cast<int64_t>(dev::block_order(blockIdx.x, gridDim.x, wg_order)) * TPW;
   int64_t l0[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) l0[i] = static_cast<int64_t>(order[min(t0 + i, n_tiles - 1)]) * kTile + threadIdx.x;
@@ -460,7 +461,7 @@ template <class T>
 bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hipStream_t st) {
   using E = typename Storage<T>::E;
   const Tune& tn = tune_for(ctx, OP_GATHER, dtype_index<T>(), gs->n_local);
-  const bool remap = (tn.variant & kNoXcdRemap) == 0;
+  const int order = gs_order(tn.variant);
   int kind = tn.variant & kVariantMask;
   if (kind == 0 && !gs->has_perm) kind = 1;
   if (kind == 0) {
@@ -471,15 +472,15 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
                          gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff, gs->perm_runs,
                          gs->perm_bstart, gs->perm_bnz0,
                          static_cast<const E*>(xL), static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global,
-                         remap);
+                         order);
   } else if (kind == 1) {
     hipLaunchKernelGGL((k_gather_nnz<T>), dim3(static_cast<unsigned int>(gs->n_blocks)), dim3(kBlock), 0, st,
                        gs->row_starts, gs->col_ids, gs->block_starts, static_cast<const E*>(xL), static_cast<E*>(xG),
-                       gs->chunk, gs->n_unmasked, remap);
+                       gs->chunk, gs->n_unmasked, order);
   } else {
     const unsigned int g = blocks_for(gs->n_global);
     hipLaunchKernelGGL((k_gather<T, 1>), dim3(g), dim3(kBlock), 0, st, gs->row_starts, gs->col_ids,
-                       static_cast<const E*>(xL), static_cast<E*>(xG), static_cast<int32_t>(gs->n_global), remap);
+                       static_cast<const E*>(xL), static_cast<E*>(xG), static_cast<int32_t>(gs->n_global), order);
   }
   return check_launch("bs_gather");
 }
@@ -494,32 +495,32 @@ void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipS
 }
 
 template <class E, int TPW>
-void launch_scatter_sorted(const bs_gs* gs, bool remap, const void* xG, void* xL, hipStream_t st) {
+void launch_scatter_sorted(const bs_gs* gs, int wg_order, const void* xG, void* xL, hipStream_t st) {
   const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
   if (gs->tile_packed)
     hipLaunchKernelGGL((k_scatter_sorted<E, TPW, true>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
                        static_cast<const int32_t*>(nullptr), static_cast<const uint16_t*>(nullptr), gs->tile_word,
                        gs->tile_min, gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
-                       gs->n_tiles, remap);
+                       gs->n_tiles, wg_order);
   else
     hipLaunchKernelGGL((k_scatter_sorted<E, TPW, false>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
                        gs->tile_gid, gs->tile_loc, static_cast<const uint32_t*>(nullptr),
                        static_cast<const int32_t*>(nullptr), gs->tile_count, static_cast<const E*>(xG),
-                       static_cast<E*>(xL), gs->n_local, gs->n_tiles, remap);
+                       static_cast<E*>(xL), gs->n_local, gs->n_tiles, wg_order);
 }
 
 template <class E, int TPW>
-void launch_scatter_tiles(const bs_gs* gs, bool remap, const void* xG, void* xL, hipStream_t st) {
+void launch_scatter_tiles(const bs_gs* gs, int wg_order, const void* xG, void* xL, hipStream_t st) {
   const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
   hipLaunchKernelGGL((k_scatter_tiles<E, TPW>), dim3(grid), dim3(kBlock), 0, st, gs->map, gs->tile_order,
-                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local, gs->n_tiles, remap);
+                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local, gs->n_tiles, wg_order);
 }
 
 template <class T>
 bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hipStream_t st) {
   using E = typename Storage<T>::E;
   const Tune& tn = tune_for(ctx, OP_SCATTER, dtype_index<T>(), gs->n_local);
-  const bool remap = (tn.variant & kNoXcdRemap) == 0;
+  const int order = gs_order(tn.variant);
   const int kind = tn.variant & kVariantMask;
   if (kind <= 1) {
     // tiles per workgroup: the tune entry's unroll, rounded down to 1, 2 or 4
@@ -528,13 +529,13 @@ bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hi
     // and the kernels' padding lanes read xG[0])
     if (gs->n_tiles > 0 && gs->n_global > 0) {
       if (kind == 0) {
-        if (tpw == 4) launch_scatter_sorted<E, 4>(gs, remap, xG, xL, st);
-        else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, remap, xG, xL, st);
-        else launch_scatter_sorted<E, 1>(gs, remap, xG, xL, st);
+        if (tpw == 4) launch_scatter_sorted<E, 4>(gs, order, xG, xL, st);
+        else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, order, xG, xL, st);
+        else launch_scatter_sorted<E, 1>(gs, order, xG, xL, st);
       } else {
-        if (tpw == 4) launch_scatter_tiles<E, 4>(gs, remap, xG, xL, st);
-        else if (tpw == 2) launch_scatter_tiles<E, 2>(gs, remap, xG, xL, st);
-        else launch_scatter_tiles<E, 1>(gs, remap, xG, xL, st);
+        if (tpw == 4) launch_scatter_tiles<E, 4>(gs, order, xG, xL, st);
+        else if (tpw == 2) launch_scatter_tiles<E, 2>(gs, order, xG, xL, st);
+        else launch_scatter_tiles<E, 1>(gs, order, xG, xL, st);
       }
     }
   } else if (tn.unroll >= 8) {

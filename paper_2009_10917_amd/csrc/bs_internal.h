@@ -158,10 +158,16 @@ static_assert(kTile == 2 * kBlock, "scatter tiles hold two entries per thread");
 static_assert(kStage == 8 * kBlock, "gather stages eight values per thread");
 
 // Kernel choice for gather and scatter (Tune::variant & kVariantMask), and
-// the flag that keeps the hardware's workgroup order instead of giving each
-// XCD a contiguous range of blocks.
+// the flags that replace the default workgroup order (each XCD one
+// contiguous range of blocks): kNoXcdRemap keeps the hardware's dispatch
+// order, kGroupOrder gives each XCD runs of 256 blocks in every group of
+// 2048.  At most one of the two may be set.
 constexpr int kVariantMask = 3;
 constexpr int kNoXcdRemap = 4;
+constexpr int kGroupOrder = 8;
+
+// Workgroup order (see dev::block_order) a gather or scatter variant selects.
+inline int gs_order(int variant) { return (variant & kNoXcdRemap) ? 0 : (variant & kGroupOrder) ? 1 : 2; }
 
 void free_plan(bs_gs* gs);
 }  // namespace bs

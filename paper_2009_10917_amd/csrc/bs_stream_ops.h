@@ -27,24 +27,12 @@ struct Span {
   int32_t order;  // workgroup order, see logical_block
 };
 
-// Which packets workgroup blockIdx.x streams.  order 0: as dispatched, so
-// the 8 XCDs interleave 4 KB slices of every operand.  order 1: in each group
-// of 2048 workgroups, the 256 that one XCD receives (hardware ids p with the
-// same p % 8) take 256 consecutive block numbers, so each XCD streams 1 MB
-// runs of each operand; a ragged last group keeps the dispatch order.
-// order 2: one contiguous range of blocks per XCD over the whole grid.
+// Which packets workgroup blockIdx.x streams: its number under the tune's
+// workgroup order.  Order 0 keeps the dispatch order, so the 8 XCDs
+// interleave 4 KB slices of every operand; order 1 gives each XCD 1 MB runs
+// (dev::group_block); order 2 one contiguous range per XCD (dev::xcd_block).
 __device__ __forceinline__ int64_t logical_block(const Span& sp) {
-  const uint32_t p = blockIdx.x, G = gridDim.x;
-  if (sp.order == 1) {
-    constexpr uint32_t kGroup = 2048, kX = 8;
-    if (p < G / kGroup * kGroup) {
-      const uint32_t r = p % kGroup;
-      return (p - r) + (r % kX) * (kGroup / kX) + r / kX;
-    }
-    return p;
-  }
-  if (sp.order == 2) return dev::xcd_block(p, G);
-  return p;
+  return dev::block_order(blockIdx.x, gridDim.x, sp.order);
 }
 
 // Element handled by thread threadIdx.x of workgroup 0 in the scalar head or
@@ -59,8 +47,9 @@ __device__ __forceinline__ int64_t scalar_index(const Span& sp) {
 
 // The streaming loop shared by BS1-BS5.  Thread t of workgroup b (the
 // logical block number) owns packets i, i + 256, ..., i + (U-1)*256 with
-// i = b*256*U + t and strides by the whole grid.  Each trip first issues all of its loads (op.load), then
-// computes and stores (op.apply), so U packets per operand are in flight.
+// i = b*256*U + t and strides by the whole grid.  Each trip first issues
+// all of its loads (op.load), then computes and stores (op.apply), so U
+// packets per operand are in flight.
 // Trips that are entirely in range run without bounds checks; only the last
 // (ragged) trip of a thread checks each packet.
 template <int U, class Op>

@@ -241,12 +241,12 @@ def test_benchmark_size_gather_scatter(ctx):
     bs.bs_gather(ctx, plan, xL, xG)
     ref = ms.gather_rows(lambda i: bsgen.uniform_at(SEED, 11, i))
     assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
-    # the benchmark's gather: lattice-tiled rows in its tiles and boxes, variant 0
-    from bench import GATHER_BOX, GATHER_TILE
+    # the benchmark's gather: lattice-tiled rows in its tiles and boxes, its variant
+    from bench import GATHER_BOX, GATHER_TILE, GATHER_VARIANT
     M = K * N + 1
     bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
     own = bs.bs_ctx_create(0)  # its own context: one launch shape for every length
-    bs.bs_ctx_set_tune(own, "gather", 1, 1 << 30, 0)
+    bs.bs_ctx_set_tune(own, "gather", 1, 1 << 30, GATHER_VARIANT)
     xG.fill_(float("nan"))
     bs.bs_gather(own, plan, xL, xG)
     torch.cuda.synchronize()

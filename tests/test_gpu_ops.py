@@ -258,7 +258,9 @@ def test_error_paths(ctx):
     assert L.bs_ctx_set_tune(h, 0, 0, 3, 16, 0) == INVALID
     assert L.bs_ctx_set_tune(h, 99, 0, 4, 16, 0) == INVALID
     assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 3) == INVALID
-    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 8) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 12) == INVALID  # dispatch order and XCD runs at once
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 11) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 16) == INVALID
     # n == 0 with NULL pointers is a valid no-op; reductions write 0
     assert L.bs_copy(h, 0, 0, None, None, s) == 0
     assert L.bs_dot(h, 0, 0, None, None, o.data_ptr(), s) == 0

@@ -65,6 +65,7 @@ def test_entries_by_length(ctx, tmp_path):
     "paste f64 0 1 1024 0\n",              # operation
     "copy f64 16 1 1024 0\n",              # no n_min 0
     "gather f64 0 1 1024 3\n",             # variant
+    "scatter f64 0 1 1024 12\n",           # both workgroup-order flags
     "copy f64 0 1 1024 0 extra\n",         # trailing text
 ])
 def test_malformed_tables_change_nothing(ctx, tmp_path, text):
