@@ -211,7 +211,7 @@ bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_local, int64
                        void* stream, bs_gs** out);
 bs_status bs_gs_destroy(bs_gs* gs);
 
-/* Replace the plan's permuted row order (gather variant 0) with a
+/* Replace the plan's permuted row order (gather kernel 0: variants 0, 4, 8) with a
  * lattice-tiled one, for maps whose global ids are lattice points
  * g = X + mx (Y + my Z) (mx*my*mz == n_global): rows in tile x tile x tile
  * blocks of the lattice, blocks in lattice order (x fastest); inside a

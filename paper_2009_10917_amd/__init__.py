@@ -309,7 +309,7 @@ def bs_gs_degree(plan, deg, stream=None):
 
 
 def bs_gs_order_rows(plan, mx, my, mz, tile, box=0, stream=None):
-    """Lattice-tiled row order for gather variant 0 (global ids X + mx (Y + my Z)):
+    """Lattice-tiled row order for gather kernel 0 (variants 0, 4, 8; global ids X + mx (Y + my Z)):
     tile^3 blocks, boxes inside a block (box: one side for cubes, or (bx, by, bz);
     0: none)."""
     bx, by, bz = (box, box, box) if isinstance(box, int) else box
