@@ -90,7 +90,7 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
  * the number of 256-thread workgroups (kernels grid-stride beyond it;
- * reductions are further capped at 65536).  variant, for copy, axpy,
+ * reductions are further capped at 1048576).  variant, for copy, axpy,
  * norm, dot and cg_update, is the workgroup order: 0 as the hardware
  * dispatches them (round-robin over the 8 XCDs, so the XCDs interleave 4 KB
  * slices of each operand), 1 the 256 workgroups one XCD receives in each

@@ -10,8 +10,9 @@ bs_ctx_create picks it up; BS_TUNE_FILE overrides it.
 
 Candidates:
   copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass}
-  norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536}
-  cg_update           (the reductions' partial buffer holds 65536 pairs), and cap 1
+  norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536,
+  cg_update           one pass (up to 2^20 workgroups, the reductions' partial
+                      buffer)}, and cap 1
                       up to 2^20 elements (one workgroup finishes the sum in the
                       same launch); from 2^20 elements on, each shape also with
                       the two XCD-grouped workgroup orders (variants 1 and 2)
@@ -99,7 +100,7 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
             }
             reps = 50 if n <= (1 << 20) else 10
             for op in STREAM_OPS:
-                caps = (256, 1024, 4096, 16384, 65536) if op in REDUCTIONS else (1024, 4096, 16384, 65536, 1 << 30)
+                caps = (256, 1024, 4096, 16384, 65536, 1 << 30) if op in REDUCTIONS else (1024, 4096, 16384, 65536, 1 << 30)
                 if op in REDUCTIONS and n <= (1 << 20):
                     caps = (1,) + caps
                 times = {}

@@ -145,7 +145,7 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
   bs_ctx* c = new bs_ctx();
   c->device = device;
   void* ws = nullptr;
-  const size_t bytes = sizeof(double) * 2 * kMaxReduceBlocks;
+  const size_t bytes = sizeof(double) * 2 * kPartialPairs;
   if (hipMalloc(&ws, bytes) != hipSuccess) {
     delete c;
     (void)hipSetDevice(prev);

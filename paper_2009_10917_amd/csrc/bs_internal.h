@@ -60,16 +60,26 @@ struct TuneList {
 };
 
 // Largest number of workgroups a reduction may use: the context's partial
-// buffer holds one compensated pair per workgroup.
+// buffer holds one compensated pair per workgroup.  The CG solver, the
+// operator and the batch keep to kMaxReduceBlocks; norm, dot and the CG
+// update may use up to kMaxStreamBlocks (one-pass grids of long vectors).
 constexpr int kMaxReduceBlocks = 65536;
+constexpr int kMaxStreamBlocks = 1 << 20;
 constexpr int kBlock = 256;
 constexpr int kFinishBlock = 1024;  // threads of the second reduction stage
+// Above kFinishDirect pairs the second stage runs in two launches: workgroup
+// b adds pairs [b*kFinishChunk, (b+1)*kFinishChunk) into pair b of a second
+// area (after the first kMaxStreamBlocks pairs), then one workgroup adds
+// those in order.
+constexpr int kFinishDirect = 16384;
+constexpr int kFinishChunk = 4096;
+constexpr int kPartialPairs = kMaxStreamBlocks + kMaxStreamBlocks / kFinishChunk;
 
 }  // namespace bs
 
 struct bs_ctx {
   int device;
-  double* partials;  // 2 * kMaxReduceBlocks doubles: (sum, compensation) per workgroup
+  double* partials;  // 2 * kPartialPairs doubles: (sum, compensation) per workgroup, then the chunk sums
   bs::TuneList tune[bs::OP_COUNT][3];
 };
 

@@ -14,7 +14,9 @@
 // running error), combine the 64 lanes of a wave by xor-shuffles and the
 // waves of a workgroup through LDS, and store one pair per workgroup; a
 // second launch of one 1024-thread workgroup adds the pairs in index order,
-// as the paper's two-kernel reductions do (Section 5).  Finishing inside the
+// as the paper's two-kernel reductions do (Section 5).  Grids of more than
+// 16384 workgroups (one-pass grids over long vectors) first add their pairs
+// in chunks of 4096, one workgroup per chunk, in one more launch.  Finishing inside the
 // first launch would need an agent-scope fence per workgroup, which on this
 // 8-XCD part costs more than the second launch.
 
@@ -100,10 +102,35 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(const double* __restric
   if (threadIdx.x == 0) *out = r.s + r.c;
 }
 
+// First half of a two-launch second stage (more than kFinishDirect pairs):
+// workgroup b adds pairs [b*kFinishChunk, min((b+1)*kFinishChunk, G)) the
+// same way and stores the compensated pair in sums[b].
+__global__ __launch_bounds__(kFinishBlock) void k_finish_chunks(const double* __restrict__ partials, int G,
+                                                                double* __restrict__ sums) {
+  const int b0 = blockIdx.x * kFinishChunk;
+  const int b1 = min(b0 + kFinishChunk, G);
+  DW<double> r{0.0, 0.0};
+  for (int i = b0 + threadIdx.x; i < b1; i += kFinishBlock)
+    r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  r = dev::block_reduce<kFinishBlock>(r);
+  if (threadIdx.x == 0) {
+    sums[2 * blockIdx.x] = r.s;
+    sums[2 * blockIdx.x + 1] = r.c;
+  }
+}
+
 bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op) {
   bs_status s = check_launch(op);
   if (s || grid == 1) return s;
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, grid, out);
+  if (grid <= kFinishDirect) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, grid, out);
+    return check_launch(op);
+  }
+  const int chunks = (grid + kFinishChunk - 1) / kFinishChunk;  // <= kMaxStreamBlocks / kFinishChunk
+  double* sums = ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks);
+  hipLaunchKernelGGL(k_finish_chunks, dim3(chunks), dim3(kFinishBlock), 0, st, ctx->partials, grid, sums);
+  if ((s = check_launch(op))) return s;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, sums, chunks, out);
   return check_launch(op);
 }
 
@@ -179,7 +206,7 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
   const Tune& tn = tune_for(ctx, OP_NORM, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
+  const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
   if (w)
     BS_DISPATCH_B(k_norm, T, true, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
@@ -196,7 +223,7 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   const Tune& tn = tune_for(ctx, OP_DOT, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
+  const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
   BS_DISPATCH(k_dot, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
   return finish(ctx, g, out, st, "bs_dot");
@@ -210,7 +237,7 @@ bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const voi
   const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int cap = tn.grid_cap < kMaxReduceBlocks ? tn.grid_cap : kMaxReduceBlocks;
+  const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
   if (w)
     BS_DISPATCH_B(k_cg_update, T, true, sp, u, g, st, static_cast<C>(alpha), static_cast<typename Storage<T>::E*>(x),

@@ -211,6 +211,19 @@ def test_benchmark_size_vectors_and_reductions(ctx):
     z.fill_(0.5)
     bs.bs_norm(ctx, z, None, o)
     assert float(to_host(o)[0]) == n * 0.25
+    # the largest reduction grids (2^20 workgroups, striding; 256 chunk sums in the second stage)
+    own = bs.bs_ctx_create(0)
+    try:
+        for op in ("norm", "dot"):
+            bs.bs_ctx_set_tune(own, op, 1, 1 << 30)
+        a2 = scalar_out()
+        bs.bs_dot(own, x, x, a2)
+        assert rel_err(float(to_host(a2)[0]), float(to_host(b2)[0])) <= TOL
+        bs.bs_norm(own, z, None, a2)
+        assert float(to_host(a2)[0]) == n * 0.25
+    finally:
+        torch.cuda.synchronize()
+        own.close()
     del z, y, xs
     # BS5: x, p dense; r, Ap supported on the sample so that r'.r' is exact
     p = dev_uniform(n, S["p"])

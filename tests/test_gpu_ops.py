@@ -237,6 +237,34 @@ def test_workgroup_orders_do_not_change_results(order_case, order, unroll, cap):
         ctx.close()
 
 
+@pytest.mark.parametrize("unroll,cap", [(1, 16384), (1, 16385), (1, 1 << 30), (8, 1 << 30)])
+def test_reductions_past_the_direct_finish(order_case, unroll, cap):
+    # above 16384 workgroups the pairs are first added in chunks of 4096 (cap 16385 leaves a
+    # last chunk of one pair), then the chunk sums in order: sums stay within the tolerance
+    # and repeat bit for bit
+    n, want = order_case
+    ctx = bs.bs_ctx_create(0)
+    try:
+        for op in ("norm", "dot", "cg_update"):
+            bs.bs_ctx_set_tune(ctx, op, unroll, cap)
+        x, y, p, Ap, w = (dev_uniform(n, s, lo=0.0 if s == 5 else -1.0) for s in (1, 2, 3, 4, 5))
+        o1, o2 = scalar_out(), scalar_out()
+        bs.bs_norm(ctx, x, w, o1)
+        bs.bs_norm(ctx, x, w, o2)
+        assert rel_err(float(to_host(o1)[0]), want["norm"]) <= TOL
+        assert bits(to_host(o1)) == bits(to_host(o2))
+        bs.bs_dot(ctx, x, y, o1)
+        bs.bs_dot(ctx, x, y, o2)
+        assert rel_err(float(to_host(o1)[0]), want["dot"]) <= TOL
+        assert bits(to_host(o1)) == bits(to_host(o2))
+        bs.bs_cg_update(ctx, 0.37, x, p, y, Ap, w, o1)
+        assert np.array_equal(bits(to_host(x)), want["cg_x"]) and np.array_equal(bits(to_host(y)), want["cg_r"])
+        assert rel_err(float(to_host(o1)[0]), want["cg_rho"]) <= TOL
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+
 def test_error_paths(ctx):
     L = bs.lib
     x = torch.zeros(64, dtype=torch.float64, device="cuda")
