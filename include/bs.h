@@ -80,8 +80,10 @@ const char* bs_last_error(void);
 /* Library version string (static storage). */
 const char* bs_version(void);
 
-/* Create a context on HIP device `device` (allocates its workspace and
- * synchronises).  *out receives the handle; destroy it with bs_ctx_destroy. */
+/* Create a context on HIP device `device` (allocates its workspace, 16.8 MB
+ * of reduction partials: one pair per workgroup for up to 2^20 workgroups,
+ * plus 256 chunk sums; and synchronises).  *out receives the handle;
+ * destroy it with bs_ctx_destroy. */
 bs_status bs_ctx_create(int device, bs_ctx** out);
 bs_status bs_ctx_destroy(bs_ctx* ctx);
 
