@@ -643,7 +643,7 @@ def main():
     traffic = read_traffic(byt["cg_update"])
     cu, cg_cap, corder = bs.bs_ctx_tune_for(ctx, "cg_update", n)
     cu = 8 if cu >= 8 else 4 if cu >= 4 else 2 if cu >= 2 else 1
-    cg_grid = max(1, min(cg_cap, 1 << 20, -(-(n // 2) // (256 * cu))))
+    cg_grid = max(1, min(cg_cap, 1 << 21, -(-(n // 2) // (256 * cu))))
     roofline = {"bound": "hbm", "kernel": f"k_cg_update<double, 2, {cu}, true>", "workgroups": cg_grid,
                 "workgroup_order": corder, "achieved": cg_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cg_gbs / HBM_PEAK_GBS, 4),

@@ -80,9 +80,9 @@ const char* bs_last_error(void);
 /* Library version string (static storage). */
 const char* bs_version(void);
 
-/* Create a context on HIP device `device` (allocates its workspace, 16.8 MB
- * of reduction partials: one pair per workgroup for up to 2^20 workgroups,
- * plus 256 chunk sums; and synchronises).  *out receives the handle;
+/* Create a context on HIP device `device` (allocates its workspace, 33.6 MB
+ * of reduction partials: one pair per workgroup for up to 2^21 workgroups,
+ * plus 512 chunk sums; and synchronises).  *out receives the handle;
  * destroy it with bs_ctx_destroy. */
 bs_status bs_ctx_create(int device, bs_ctx** out);
 bs_status bs_ctx_destroy(bs_ctx* ctx);
@@ -92,7 +92,7 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
  * the number of 256-thread workgroups (kernels grid-stride beyond it;
- * reductions are further capped at 1048576).  variant, for copy, axpy,
+ * reductions are further capped at 2097152).  variant, for copy, axpy,
  * norm, dot and cg_update, is the workgroup order: 0 as the hardware
  * dispatches them (round-robin over the 8 XCDs, so the XCDs interleave 4 KB
  * slices of each operand), 1 the 256 workgroups one XCD receives in each

@@ -11,7 +11,7 @@ bs_ctx_create picks it up; BS_TUNE_FILE overrides it.
 Candidates:
   copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass}
   norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536,
-  cg_update           one pass (up to 2^20 workgroups, the reductions' partial
+  cg_update           one pass (up to 2^21 workgroups, the reductions' partial
                       buffer)}, and cap 1
                       up to 2^20 elements (one workgroup finishes the sum in the
                       same launch); from 2^20 elements on, each shape also with

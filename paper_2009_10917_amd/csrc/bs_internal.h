@@ -64,7 +64,7 @@ struct TuneList {
 // operator and the batch keep to kMaxReduceBlocks; norm, dot and the CG
 // update may use up to kMaxStreamBlocks (one-pass grids of long vectors).
 constexpr int kMaxReduceBlocks = 65536;
-constexpr int kMaxStreamBlocks = 1 << 20;
+constexpr int kMaxStreamBlocks = 1 << 21;
 constexpr int kBlock = 256;
 constexpr int kFinishBlock = 1024;  // threads of the second reduction stage
 // Above kFinishDirect pairs the second stage runs in two launches: workgroup

@@ -211,7 +211,7 @@ def test_benchmark_size_vectors_and_reductions(ctx):
     z.fill_(0.5)
     bs.bs_norm(ctx, z, None, o)
     assert float(to_host(o)[0]) == n * 0.25
-    # the largest reduction grids (2^20 workgroups, striding; 256 chunk sums in the second stage)
+    # one-pass reduction grids at this length (1,409,638 workgroups; 345 chunk sums in the second stage)
     own = bs.bs_ctx_create(0)
     try:
         for op in ("norm", "dot"):
