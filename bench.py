@@ -45,9 +45,12 @@ def alg_bytes(n, nl, ng, s=8, idx=4):
 
 
 def source_digest():
+    """Digest of what decides the CG-update launch: the streaming kernels'
+    sources, the library's constants and the installed tune table."""
     h = hashlib.sha256()
-    for f in ("bs_device.h", "bs_stream_ops.h", "bs_stream.hip"):
-        with open(os.path.join(ROOT, "paper_2009_10917_amd", "csrc", f), "rb") as fh:
+    pkg = os.path.join(ROOT, "paper_2009_10917_amd")
+    for f in ("csrc/bs_device.h", "csrc/bs_stream_ops.h", "csrc/bs_stream.hip", "csrc/bs_internal.h", "tune_gfx950.txt"):
+        with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
