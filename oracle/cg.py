@@ -20,10 +20,16 @@ iteration stops on the recursive residual first).
 
 ir_cg is the mixed-precision iterative refinement the benchmark
 configuration describes: binary64 outer residual, correction and update;
-inner CG on A d = r / ||r|| with vectors stored in binary32, stopped at a
-relative residual theta = max(inner_tol, 0.5 tol ||b|| / ||r||): the looser
-value applies when it already meets the outer target, so the last step is
-not solved further than needed.
+inner CG on A d = r / ||r|| with vectors stored in binary32 or bfloat16 and
+binary32 arithmetic, stopped at a fixed relative residual inner_tol (or
+after max_inner iterations).  The scaled residual r / ||r|| is rounded once,
+to nearest with ties to even, from binary64 to the storage type.  Inner
+reductions are the correctly rounded exact sums of their terms.
+
+round_storage rounds binary64 values to the nearest value of a storage
+format given by its significand bits and exponent range (ties to even,
+overflow to infinity), as the definition of round-to-nearest says: the
+nearest multiple of the quantum of the value's binade.
 
 TEST INFRASTRUCTURE ONLY: not part of the library path.
 """
@@ -32,7 +38,7 @@ import math
 
 import numpy as np
 
-__all__ = ["stencil7", "eigenvalue", "sine_mode", "cg", "ir_cg"]
+__all__ = ["stencil7", "eigenvalue", "sine_mode", "cg", "ir_cg", "round_storage", "FORMATS"]
 
 
 def stencil7(x, m, shift, dtype=np.float64):
@@ -88,36 +94,88 @@ def cg(b, m, shift, x0=None, tol=1e-10, max_iter=10000):
     return x, j, math.sqrt(float(np.dot(res, res))) / nb
 
 
-def ir_cg(b, m, shift, tol=1e-10, inner_tol=1e-4, max_inner=400, max_outer=50):
-    """Iterative refinement with binary32 inner CG.  Returns (x, outer, inner, relres)."""
+# significand bits (with the hidden bit), smallest normal exponent, largest finite value
+FORMATS = {
+    "f32": (24, -126, (2.0 - 2.0 ** -23) * 2.0 ** 127),
+    "bf16": (8, -126, (2.0 - 2.0 ** -7) * 2.0 ** 127),
+}
+
+
+def round_storage(x, fmt):
+    """Round binary64 values once to the nearest value of format fmt (ties to even).
+
+    For |x| in the binade [2^e, 2^(e+1)) (e clamped below at the smallest
+    normal exponent, where subnormals share its quantum) the representable
+    values are the multiples of q = 2^(e + 1 - p); x / q is exact in
+    binary64 and np.rint rounds it to the nearest integer, ties to even.
+    Results above the largest finite value become infinities.  Returned as
+    binary64 holding the rounded values.
+    """
+    p, emin, vmax = FORMATS[fmt]
+    x = np.asarray(x, dtype=np.float64)
+    _, ex = np.frexp(x)                     # |x| = m 2^ex, m in [0.5, 1)
+    e = np.maximum(ex.astype(np.int64) - 1, emin)
+    q_exp = e + 1 - p
+    y = np.ldexp(np.rint(np.ldexp(x, -q_exp)), q_exp)
+    y = np.where(np.abs(y) > vmax, np.copysign(np.inf, x), y)
+    return np.where(np.isfinite(x), y, x)
+
+
+def _store(x, fmt):
+    """Rounded storage value of binary32 arithmetic results (held as binary32)."""
+    x32 = np.asarray(x, dtype=np.float32)
+    if fmt == "f32":
+        return x32
+    return round_storage(x32.astype(np.float64), fmt).astype(np.float32)
+
+
+def _exact_dot(a, b):
+    """Correctly rounded sum of the exact products a_i b_i (binary32 inputs)."""
+    prod = np.asarray(a, dtype=np.float64) * np.asarray(b, dtype=np.float64)  # exact: 24 + 24 <= 53 bits
+    return math.fsum(prod.tolist())
+
+
+def ir_cg(b, m, shift, tol=1e-10, inner_tol=1e-4, max_inner=400, max_outer=50, inner="f32"):
+    """Iterative refinement with an inner CG stored in `inner` ("f32" or "bf16").
+
+    Returns (x, outer, inner iterations, true relative residual).  Steps:
+    x = 0; repeat: r = b - A x and ||r|| in binary64; stop when
+    ||r|| <= tol ||b|| (or after max_outer steps); r^ = r / ||r|| rounded to
+    the storage type; CG on A d = r^ from d = 0 with every vector stored in
+    that type, each vector operation computed in binary32 and rounded once
+    to storage, alpha and beta from correctly rounded reductions, until
+    ||r_j|| <= inner_tol ||r_0|| or max_inner iterations; x += ||r|| d in
+    binary64.
+    """
+    if inner not in FORMATS:
+        raise ValueError("inner must be 'f32' or 'bf16'")
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
     nb = math.sqrt(float(np.dot(b, b)))
-    outer = inner = 0
+    outer = inner_its = 0
     while outer < max_outer:
         r = b - stencil7(x, m, shift)
         nr = math.sqrt(float(np.dot(r, r)))
         if nr <= tol * nb:
             break
-        theta = max(inner_tol, 0.5 * tol * nb / nr)
-        rh = (r / nr).astype(np.float32)
-        d = np.zeros_like(rh)
-        rl = rh.copy()
+        rl = round_storage(r / nr, inner).astype(np.float32)
+        d = np.zeros_like(rl)
         p = rl.copy()
-        rr = np.float32(np.dot(rl.astype(np.float64), rl.astype(np.float64)))
-        rr0 = rr
+        rr = _exact_dot(rl, rl)
+        stop = inner_tol * inner_tol * rr
         j = 0
-        while j < max_inner and math.sqrt(float(rr)) > theta * math.sqrt(float(rr0)):
-            Ap = stencil7(p, m, shift, dtype=np.float32)
-            alpha = np.float32(rr / np.float32(np.dot(p.astype(np.float64), Ap.astype(np.float64))))
-            d = (d + alpha * p).astype(np.float32)
-            rl = (rl - alpha * Ap).astype(np.float32)
-            rr_new = np.float32(np.dot(rl.astype(np.float64), rl.astype(np.float64)))
-            p = (rl + np.float32(rr_new / rr) * p).astype(np.float32)
+        while j < max_inner and rr > stop:
+            Ap = _store(stencil7(p, m, shift, dtype=np.float32), inner)
+            alpha = np.float32(rr / _exact_dot(p, Ap))
+            d = _store(d + alpha * p, inner)
+            rl = _store(rl - alpha * Ap, inner)
+            rr_new = _exact_dot(rl, rl)
+            beta = np.float32(rr_new / rr)
+            p = _store(np.float32(1.0) * rl + beta * p, inner)
             rr = rr_new
             j += 1
-        inner += j
+        inner_its += j
         x = x + nr * d.astype(np.float64)
         outer += 1
     res = b - stencil7(x, m, shift)
-    return x, outer, inner, math.sqrt(float(np.dot(res, res))) / nb
+    return x, outer, inner_its, math.sqrt(float(np.dot(res, res))) / nb
