@@ -19,6 +19,8 @@ kernels I: Streaming Operations"):
             mixed-precision iterative refinement around it
   batch  -- one step of the batched workload (the seven operations and one
             CG iteration) on one box-mesh instance
+  elem   -- the element operators of Section 2 (GLL Lagrange basis, mass
+            and stiffness blocks, their assembly Z^T A_L Z, lumped mass)
 """
 
-from . import batch, cg, mesh, model, ops  # noqa: F401
+from . import batch, cg, elem, mesh, model, ops  # noqa: F401
