@@ -55,6 +55,25 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def committed_kernel_average(kernel):
+    """Average duration (us) and command of `kernel` in the committed
+    rocprofv3 kernel statistics of the benchmark step, or (None, None)."""
+    path = os.path.join(ROOT, "profiles", "bench_step_kernel_stats_K128.md")
+    if not os.path.exists(path):
+        return None, None
+    cmd = None
+    for line in open(path):
+        if line.strip().startswith("cd /tmp") and cmd is None:
+            cmd = line.strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == kernel:
+            try:
+                return float(cells[2]), cmd
+            except ValueError:
+                return None, cmd
+    return None, cmd
+
+
 def read_traffic(per_launch_alg):
     """HBM bytes per launch of the CG-update kernel from the committed counter
     summary, if it was taken on the current kernel source; else None."""
@@ -74,41 +93,163 @@ def read_traffic(per_launch_alg):
         return None
 
 
-def cpu_baseline(n_sample, K_mesh, N_mesh, seed):
-    """Time the oracle (as it stands) on a bounded sample of the workload."""
-    import numpy as np
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def _cpu_inputs(n_sample, K_mesh, N_mesh, seed):
     import bsgen
-    from oracle import mesh, ops
+    from oracle import mesh
 
     xs = {k: bsgen.uniform(seed, bsgen.STREAM[k], n_sample) for k in ("x", "y", "p", "r", "Ap")}
-    w = bsgen.uniform(seed, bsgen.STREAM["w"], n_sample, lo=0.0)
-    a, b = 0.37, 0.91
+    xs["w"] = bsgen.uniform(seed, bsgen.STREAM["w"], n_sample, lo=0.0)
     E, NL, NG = mesh.sizes(K_mesh, N_mesh)
     ids = mesh.hex_map(K_mesh, N_mesh, bsgen.permutation(seed, E), bsgen.orientations(seed, E))
-    rs, ci = mesh.csr_inverse(ids, NG)
     xL = bsgen.uniform(seed, bsgen.STREAM["xL"], NL)
     xG = bsgen.uniform(seed, bsgen.STREAM["xG"], NG)
+    return xs, ids, xL, xG, NL, NG
+
+
+def _plain_chunk(args):
+    """The seven operations in plain numpy (np.dot and np.add.reduceat
+    reductions, no exact sums) on a slice of the shared inputs: one worker's
+    share of the vectors, of the local entries (scatter) and of the global
+    rows (gather)."""
+    import numpy as np
+    from multiprocessing import shared_memory
+
+    names, shapes, lo, hi, glo, ghi, rlo, rhi, a, b = args
+    shm = {k: shared_memory.SharedMemory(name=v) for k, v in names.items()}
+    arr = {k: np.ndarray(shapes[k], dtype=np.int64 if k in ("ids", "rs", "ci") else np.float64, buffer=shm[k].buf)
+           for k in names}
+    t0 = time.perf_counter()
+    x, y, p, r, Ap, w = (arr[k][lo:hi] for k in ("x", "y", "p", "r", "Ap", "w"))
+    y2 = x.copy()                                   # BS1
+    y2 = a * x + b * y                              # BS2 (into a new array: inputs stay shared)
+    nrm = float(np.dot(w * x, x))                   # BS3 weighted
+    dt = float(np.dot(x, y2))                       # BS4
+    x2 = x + a * p                                  # BS5
+    r2 = r - a * Ap
+    rr = float(np.dot(w * r2, r2))
+    xL = arr["xG"][arr["ids"][glo:ghi]]             # BS7 on this slice of local entries
+    rs = arr["rs"][rlo:rhi + 1]                     # BS6 on this range of global rows (no empty rows here)
+    g = np.add.reduceat(arr["xL"][arr["ci"][rs[0]:rs[-1]]], rs[:-1] - rs[0]) if rhi > rlo else np.zeros(1)
+    out = (time.perf_counter() - t0, nrm + dt + rr + float(y2[:1].sum() + x2[:1].sum() + xL[:1].sum() + g[:1].sum()))
+    for v in shm.values():
+        v.close()
+    return out
+
+
+def _plain_timing(xs, ids, rs, ci, xL, xG, workers, a, b):
+    """Wall time of the plain numpy forms over `workers` processes (one
+    process on one pinned core when workers == 1), inputs in shared memory."""
+    import numpy as np
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
+    data = dict(xs, ids=ids.astype(np.int64), rs=np.asarray(rs, dtype=np.int64), ci=np.asarray(ci, dtype=np.int64),
+                xL=xL, xG=xG)
+    shm, names, shapes = {}, {}, {}
+    try:
+        for k, v in data.items():
+            m = shared_memory.SharedMemory(create=True, size=max(v.nbytes, 1))
+            np.ndarray(v.shape, dtype=v.dtype, buffer=m.buf)[:] = v
+            shm[k], names[k], shapes[k] = m, m.name, v.shape
+        n, nl, ng = xs["x"].size, ids.size, xG.size
+        cuts = [(n * i // workers, n * (i + 1) // workers, nl * i // workers, nl * (i + 1) // workers,
+                 ng * i // workers, ng * (i + 1) // workers) for i in range(workers)]
+        ctx = mp.get_context("spawn")
+        env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+        for k in env_keep:
+            os.environ[k] = "1"
+        try:
+            with ctx.Pool(workers, initializer=_pin_worker, initargs=(workers,)) as pool:
+                pool.map(_plain_chunk, [(names, shapes, *c, a, b) for c in cuts])  # warm-up (imports, pages)
+                t0 = time.perf_counter()
+                pool.map(_plain_chunk, [(names, shapes, *c, a, b) for c in cuts])
+                return time.perf_counter() - t0
+        finally:
+            for k, v in env_keep.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    finally:
+        for m in shm.values():
+            m.close()
+            m.unlink()
+
+
+def _pin_worker(workers):
+    # one core per worker; a single worker runs on the first allowed core
+    try:
+        cores = sorted(os.sched_getaffinity(0))
+        ident = mp_identity()
+        os.sched_setaffinity(0, {cores[ident % len(cores)]} if workers <= len(cores) else set(cores))
+    except (AttributeError, OSError):
+        pass
+
+
+def mp_identity():
+    import multiprocessing as mp
+    ident = mp.current_process()._identity
+    return (ident[0] - 1) if ident else 0
+
+
+def cpu_baseline(n_sample, K_mesh, N_mesh, seed, max_workers=16):
+    """CPU baselines on a bounded sample of the workload (BS1-BS5 on n_sample
+    values, BS6/BS7 on the K_mesh^3, N_mesh permuted and oriented mesh).
+
+    `value` is the oracle as it stands (numpy binary64 with exact fsum
+    reductions) on one thread.  Beside it: the plain numpy forms of the
+    seven operations (np.dot and reduceat reductions, no exact sums) on one
+    pinned core and over all usable cores (a process pool, inputs in shared
+    memory, at most max_workers processes).  All three report algorithmic
+    bytes / wall time."""
+    import numpy as np
+
+    from oracle import mesh, ops
+
+    xs, ids, xL, xG, NL, NG = _cpu_inputs(n_sample, K_mesh, N_mesh, seed)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    a, b = 0.37, 0.91
     t0 = time.perf_counter()
     ops.copy(xs["x"])
     ops.axpy(a, xs["x"], b, xs["y"])
-    ops.norm(xs["x"], w)
+    ops.norm(xs["x"], xs["w"])
     ops.dot(xs["x"], xs["y"])
-    ops.cg_update(a, xs["x"], xs["p"], xs["r"], xs["Ap"], w)
+    ops.cg_update(a, xs["x"], xs["p"], xs["r"], xs["Ap"], xs["w"])
     ops.scatter(ids, xG, xL)
     ops.gather(rs, ci, xL)
     dt = time.perf_counter() - t0
-    byt = alg_bytes(n_sample, NL, NG)
-    total = sum(byt.values())
+    total = sum(alg_bytes(n_sample, NL, NG).values())
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(max_workers, usable))
+    t1 = _plain_timing(xs, ids, rs, ci, xL, xG, 1, a, b)
+    tn = _plain_timing(xs, ids, rs, ci, xL, xG, workers, a, b)
+    sample = (f"BS1-BS5 on n={n_sample} global binary64 values (weighted norm and CG update) and BS7/BS6 on the "
+              f"K={K_mesh}, N={N_mesh} permuted/oriented mesh (N_L={NL}, N_G={NG}); algorithmic bytes / wall time")
     return {
         "value": round(total / dt / 1e9, 4),
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
         "seconds": round(dt, 3),
-        "sample": (f"oracle (numpy binary64, exact fsum reductions), one thread: BS1-BS5 on n={n_sample} "
-                   f"global values and BS6/BS7 on the K={K_mesh}, N={N_mesh} permuted/oriented mesh "
-                   f"(N_L={NL}, N_G={NG}); algorithmic bytes / wall time"),
+        "sample": "oracle as it stands (numpy binary64, exact fsum reductions), one thread: " + sample,
+        "cpu_model": _cpu_model(),
+        "os_cpu_count": os.cpu_count(),
+        "usable_cores": usable,
+        "numpy_one_core": {"value": round(total / t1 / 1e9, 4), "unit": "GB/s", "cores": 1, "seconds": round(t1, 3),
+                           "kind": "plain numpy forms (np.dot / reduceat reductions), one process pinned to one core"},
+        "numpy_all_cores": {"value": round(total / tn / 1e9, 4), "unit": "GB/s", "cores": workers,
+                            "seconds": round(tn, 3),
+                            "kind": f"plain numpy forms over {workers} processes (one core each), shared-memory inputs"},
     }
 
 
@@ -238,7 +379,7 @@ def _mesh_points(K, N, seed, ctx, bs, bsgen, torch, np, reps):
     def lattice_gather():
         bs.bs_gather(lat_ctx, plan, xL, xG)
 
-    for op, fn in (("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL)),
+    for op, fn in (("scatter", lambda: bs.bs_gs_scatter(ctx, plan, xG, xL)),
                    ("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
                    ("gather (lattice rows)", lattice_gather)):
         if op == "gather (lattice rows)":
@@ -262,8 +403,13 @@ def _fit_record(op, pts, perfmodel):
     for tag, key, sel in fits:
         if len(sel) >= 2:
             t0, w = perfmodel.fit_time_model([p["bytes"] for p in sel], [p[key] for p in sel])
+            # the model has a launch cost T0 >= 0 and a finite positive W_max; a fit that
+            # lands outside says the points do not follow T0 + B/W_max (for instance a
+            # bandwidth that keeps rising with size) and its T0 and B_0.8 mean nothing
+            valid = t0 >= 0.0 and 0.0 < w < float("inf")
             rec["fit_" + tag] = {"T0_us": t0 * 1e6, "W_max_GB_s": w / 1e9,
-                                 "B08_MB": perfmodel.fischer_brown_bytes(t0, w) / 1e6, "points": len(sel)}
+                                 "B08_MB": perfmodel.fischer_brown_bytes(t0, w) / 1e6, "points": len(sel),
+                                 "valid": valid}
     print(json.dumps(rec))
     return rec
 
@@ -282,13 +428,21 @@ def _write_sweep_md(path, results, K_max):
              "lattice tiles of about 126 points split into slabs one element thick (tile x N x N), gather",
              "variant 0's kernel with each XCD taking runs of 256 blocks (variant 8), as the benchmark step",
              "runs it (same bits, row order only).", "",
+             "A fit whose T0 comes out negative does not describe its points (the model needs a",
+             "non-negative launch cost); its T0 and B_0.8 cells read \"invalid (T0 < 0)\" and only the",
+             "slope's W_max is shown.", "",
              "| operation | T0 (us) | W_max (GB/s) | B_0.8 (MB) | W_max >=1GB (GB/s) | graph T0 (us) | graph W_max (GB/s) | graph T0, <=256MB (us) | best GB/s (size) |",
              "|---|---|---|---|---|---|---|---|---|"]
     for r in results:
         best = max(r["points"], key=lambda p: p["GB_s"])
         fa, fg = r.get("fit_all"), r.get("fit_ge_1GB")
         ga, gs = r.get("fit_graph_all"), r.get("fit_graph_le_256MB")
-        cell = lambda f, k, fmt: (fmt % f[k]) if f else "-"
+        def cell(f, k, fmt):
+            if not f:
+                return "-"
+            if not f.get("valid", True) and k != "W_max_GB_s":
+                return "invalid (T0 < 0)"
+            return fmt % f[k]
         lines.append(f"| {r['op']} | {cell(fa, 'T0_us', '%.2f')} | {cell(fa, 'W_max_GB_s', '%.0f')} | "
                      f"{cell(fa, 'B08_MB', '%.1f')} | {cell(fg, 'W_max_GB_s', '%.0f')} | {cell(ga, 'T0_us', '%.2f')} | "
                      f"{cell(ga, 'W_max_GB_s', '%.0f')} | {cell(gs, 'T0_us', '%.2f')} | "
@@ -347,6 +501,118 @@ def mixed_cg(ctx, bs, bsgen, torch, seed, reps, m=225, shift=0.01, tol=1e-10):
         f["speedup_vs_f64"] = round(out["f64"]["ms"] / f["ms"], 3) if ok else None
     del b, x
     return out
+
+
+def lowprec_ops(ctx, bs, bsgen, torch, np, seed, reps=20, m=225, K=32, N=7):
+    """The seven operations at n = m^3 = 11,390,625 (the 225^3 grid of the
+    mixed-precision configuration) with vectors stored in binary64, binary32
+    and bfloat16: BS1-BS5 on global vectors (weighted norm and CG update),
+    BS7/BS6 on the N = 7, E = 32^3 mesh (N_L = 16,777,216, N_G = 11,390,625)
+    with the plan's default row order.  Events around `reps` back-to-back
+    calls; algorithmic bytes with the storage size.  Working sets of
+    23-340 MB partly stay in the 256 MB Infinity Cache between calls, so
+    these are not HBM-roofline figures."""
+    n = m ** 3
+    E, NL = K ** 3, K ** 3 * (N + 1) ** 3
+    S = bsgen.STREAM
+    perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
+    orient = torch.from_numpy(bsgen.orientations(seed, E).astype(np.uint8)).cuda()
+    d_map = torch.empty(NL, dtype=torch.int32, device="cuda")
+    bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+    plan = bs.bs_gs_create(ctx, d_map, n)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    res = {"n": n, "n_local": NL, "n_global": n, "mesh": f"N={N}, E={K}^3, permuted and oriented", "reps": reps}
+    for dname, dt, sz in (("f64", torch.float64, 8), ("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        v = {}
+        for k in ("x", "y", "p", "r", "Ap", "w"):
+            t = torch.empty(n, dtype=dt, device="cuda")
+            bsgen.device_uniform(t, seed, S[k], lo=0.0 if k == "w" else -1.0)
+            v[k] = t
+        xL = torch.empty(NL, dtype=dt, device="cuda")
+        bsgen.device_uniform(xL, seed, S["xL"])
+        xG = torch.empty(n, dtype=dt, device="cuda")
+        calls = {
+            "copy": lambda: bs.bs_copy(ctx, v["x"], v["y"]),
+            "axpy": lambda: bs.bs_axpy(ctx, 0.37, v["x"], 1.0, v["y"]),
+            "norm": lambda: bs.bs_norm(ctx, v["x"], v["w"], out[0:1]),
+            "dot": lambda: bs.bs_dot(ctx, v["x"], v["y"], out[1:2]),
+            "cg_update": lambda: bs.bs_cg_update(ctx, 1e-3, v["x"], v["p"], v["r"], v["Ap"], v["w"], out[2:3]),
+            "scatter": lambda: bs.bs_gs_scatter(ctx, plan, v["y"], xL),
+            "gather": lambda: bs.bs_gather(ctx, plan, xL, xG),
+        }
+        byt = alg_bytes(n, NL, n, s=sz)
+        rec = {}
+        for op, fn in calls.items():
+            t_dev, _ = _time_calls(fn, reps, torch)
+            gbs = byt[op] / t_dev / 1e9
+            rec[op] = {"us": round(t_dev * 1e6, 2), "GB_s": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        res[dname] = rec
+        print(f"# lowprec {dname}: " + ", ".join(f"{k} {r['GB_s']}" for k, r in rec.items()), file=sys.stderr,
+              flush=True)
+        del v, xL, xG
+    plan.close()
+    res["errors"] = ("measured errors against the binary64 oracle: profiles/lowprec_errors_n11390625.md "
+                     "(written by tests/lowprec_report.py)")
+    return res
+
+
+# sum-factorised local Helmholtz operator at degree 7 (padded tensor 8^3): the ten contractions
+# of 8 x 8 matrices with the element tensor (forward B_k, B_j, [B; D]_i, Dh_j, Dh_k; backward
+# Dh_k^T, Dh_j^T, [B^T D^T]_i, B^T_j, B^T_k) are 49,152 multiply-adds, plus about 22 flops per
+# quadrature point for the geometric factors and weights; the matrix cores issue 88
+# V_MFMA_F64_16X16X4F64 (2048 flops each, half of some of them on zero rows)
+ELEM_FLOPS_N7 = 2 * 49152 + 22 * 512
+ELEM_MFMA_FLOPS_N7 = 88 * 2048
+FP64_PEAK_TFLOPS = 78.6
+
+
+def elem_ops(ctx, bs, bsgen, torch, np, seed, reps=10, K=64, N=7):
+    """Element operators on the N = 7, E = K^3 mesh (permuted, oriented):
+    the sum-factorised local Helmholtz operator with the scatter fused in
+    (x_L never written), the full y_G = Z^T A_L Z x_G (local operator + BS6
+    gather), and the lumped mass in one pass over the CSR of Z^T, against
+    the unfused scatter + gather it replaces."""
+    E, P = K ** 3, (N + 1) ** 3
+    NL, NG = E * P, (K * N + 1) ** 3
+    perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
+    orient = torch.from_numpy(bsgen.orientations(seed, E).astype(np.uint8)).cuda()
+    d_map = torch.empty(NL, dtype=torch.int32, device="cuda")
+    bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    el = bs.bs_elem_create(ctx, N)
+    h = 1.0 / K
+    geo = torch.tensor([h / 2, 0, 0, h / 2, 0, h / 2, (h / 2) ** 3], dtype=torch.float64).repeat(E).cuda()
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bsgen.device_uniform(xG, seed, bsgen.STREAM["xG"])
+    yG = torch.empty_like(xG)
+    yL = torch.empty(NL, dtype=torch.float64, device="cuda")
+    lam = 0.01
+    calls = {
+        "helmholtz_local": lambda: bs.bs_helmholtz_local(ctx, el, d_map, geo, lam, xG, yL),
+        "helmholtz_apply": lambda: bs.bs_helmholtz_apply(ctx, el, plan, geo, lam, xG, yL, yG),
+        "mass_lumped": lambda: bs.bs_mass_lumped(ctx, el, plan, geo, xG, yG),
+        "scatter_then_gather": lambda: (bs.bs_gs_scatter(ctx, plan, xG, yL), bs.bs_gather(ctx, plan, yL, yG)),
+    }
+    local_bytes = 4 * NL + 8 * NG + 56 * E + 8 * NL       # map, x_G once, geometry, y_L
+    byts = {"helmholtz_local": local_bytes,
+            "helmholtz_apply": local_bytes + alg_bytes(0, NL, NG)["gather"],
+            "mass_lumped": 4 * NL + 4 * (NG + 1) + 8 * NG + 8 * NG + 56 * E,  # CSR, x_G, y_G, geometry
+            "scatter_then_gather": alg_bytes(0, NL, NG)["scatter"] + alg_bytes(0, NL, NG)["gather"]}
+    res = {"K": K, "N": N, "elements": E, "n_local": NL, "n_global": NG, "lambda": lam, "reps": reps}
+    for name, fn in calls.items():
+        t, _ = _time_calls(fn, reps, torch)
+        rec = {"us": round(t * 1e6, 2), "alg_bytes": byts[name], "GB_s": round(byts[name] / t / 1e9, 1),
+               "frac_hbm_peak": round(byts[name] / t / 1e9 / HBM_PEAK_GBS, 4)}
+        if name.startswith("helmholtz"):
+            tf = ELEM_FLOPS_N7 * E / t / 1e12
+            rec.update({"alg_flops": ELEM_FLOPS_N7 * E, "TFLOP_s": round(tf, 2),
+                        "frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 4),
+                        "mfma_issued_TFLOP_s": round(ELEM_MFMA_FLOPS_N7 * E / t / 1e12, 2)})
+        res[name] = rec
+        print(f"# elem {name}: {rec}", file=sys.stderr, flush=True)
+    el.close()
+    plan.close()
+    return res
 
 
 # gather row order: lattice tiles of GATHER_TILE^3 points, boxes of GATHER_BOX points inside (0: none);
@@ -508,6 +774,8 @@ def main():
     ap.add_argument("--mesh", default="random", choices=("random", "orient", "ident"),
                     help="element layout for --gather-sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
+    ap.add_argument("--no-elem", action="store_true", help="skip the element-operator section")
+    ap.add_argument("--elem-only", action="store_true", help="only the element-operator section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
@@ -536,6 +804,9 @@ def main():
     ctx = bs.bs_ctx_create(0)
     if args.cg_only:
         print(json.dumps({"metric": METRIC, "mixed_cg": mixed_cg(ctx, bs, bsgen, torch, args.seed, args.reps)}))
+        return 0
+    if args.elem_only:
+        print(json.dumps({"metric": METRIC, "elem_ops": elem_ops(ctx, bs, bsgen, torch, np, args.seed)}))
         return 0
     if args.batch_only:
         print(json.dumps({"metric": METRIC, "batched": batched(ctx, bs, bsgen, torch, np, args.seed, args.reps)}))
@@ -582,7 +853,7 @@ def main():
             lambda: bs.bs_norm(ctx, x, w, out[0:1], hs),
             lambda: bs.bs_dot(ctx, x, y, out[1:2], hs),
             lambda: bs.bs_cg_update(ctx, alpha, x, p, r, Ap, w, out[2:3], hs),
-            lambda: bs.bs_scatter(ctx, plan, xG, xL, hs),
+            lambda: bs.bs_gs_scatter(ctx, plan, xG, xL, hs),
             lambda: bs.bs_gather(ctx, plan, xL, xG_out, hs),
         )
 
@@ -651,7 +922,16 @@ def main():
                 "workgroup_order": corder, "achieved": cg_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cg_gbs / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": byt["cg_update"],
-                "avg_launch_ms": round(per_ms["cg_update"], 4)}
+                "avg_launch_ms": round(per_ms["cg_update"], 4),
+                "achieved_source": "HIP events around each launch in this run (launch stream)"}
+    avg_us, _ = committed_kernel_average(roofline["kernel"])
+    if avg_us:
+        a2 = byt["cg_update"] / (avg_us * 1e-6) / 1e9
+        roofline["committed_stats"] = {
+            "file": "profiles/bench_step_kernel_stats_K128.md", "avg_launch_us": avg_us,
+            "achieved": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4),
+            "note": "rocprofv3 kernel-trace average from a separate process; buffer placement moves a "
+                    "kernel's time by up to ~13% between processes"}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -670,7 +950,10 @@ def main():
     del x, y, p, r, Ap, w, xL, xG, xG_out
     plan.close()
     torch.cuda.synchronize()
+    if not args.no_elem:
+        result["elem_ops"] = elem_ops(ctx, bs, bsgen, torch, np, args.seed)
     if not args.no_cg:
+        result["lowprec_ops"] = lowprec_ops(ctx, bs, bsgen, torch, np, args.seed)
         result["mixed_cg"] = mixed_cg(ctx, bs, bsgen, torch, args.seed, args.reps)
     if not args.no_batch:
         result["batched"] = batched(ctx, bs, bsgen, torch, np, args.seed, args.reps)

@@ -180,6 +180,28 @@ bs_status bs_cg_update(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, voi
                        const void* p, void* r, const void* Ap, const void* w,
                        double* d_rr, void* stream);
 
+/* Device-scalar forms of BS2 and BS5 for a CG iteration that stays on the
+ * device (Algorithm 1, steps 7-11: alpha = r.r / p.Ap, the fused update,
+ * beta = r'.r' / r.r and the direction update p = r + beta p), so that a
+ * caller with an operator of its own can capture whole iterations into a
+ * graph without reading a scalar back.  Each scalar is
+ *     s = h * (num / den)
+ * evaluated in binary64 as fl(h * fl(num / den)), where num = *d_num and
+ * den = *d_den are device doubles read by the kernel when it starts (a
+ * NULL pointer reads as 1.0, so with both NULL s = h), then rounded once to
+ * the arithmetic type, exactly as bs_axpy / bs_cg_update round their host
+ * scalars: with h = 1 and d_den = NULL the results equal those of the host
+ * forms called with *d_num, bit for bit.  Division follows IEEE (den = 0
+ * gives an infinity or NaN; the caller tests for breakdown).  The scalar
+ * pointers must be 8-byte aligned; bs_cg_update_dev's d_rr must not be one
+ * of them.  Otherwise as bs_axpy and bs_cg_update. */
+bs_status bs_axpy_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const double* d_alpha_num,
+                      const double* d_alpha_den, const void* x, double beta, const double* d_beta_num,
+                      const double* d_beta_den, void* y, void* stream);
+bs_status bs_cg_update_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const double* d_alpha_num,
+                           const double* d_alpha_den, void* x, const void* p, void* r, const void* Ap,
+                           const void* w, double* d_rr, void* stream);
+
 /* Scatter map of a structured K x K x K hex mesh of degree N (Section 2,
  * eq. scatter_def): for element slot s (0 <= s < K^3) and local node
  * (i,j,k) (0 <= i,j,k <= N), local index l = s*(N+1)^3 + i + (N+1)*(j + (N+1)*k)
@@ -254,10 +276,84 @@ bs_status bs_gs_weights(const bs_gs* gs, bs_dtype dtype, void* d_wL, void* strea
 bs_status bs_gather(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xL, void* xG,
                     void* stream);
 
-/* BS7 (Table 1; Listing 5): x_L[l] = x_G[map[l]] where map[l] >= 0; masked
- * entries of x_L are left untouched.  Bit-exact copy of the values. */
-bs_status bs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
-                     void* stream);
+/* BS7 (Table 1; Listing 5; eq. scatter_def): x_L[l] = x_G[d_map[l]] for
+ * 0 <= l < n_local where 0 <= d_map[l] < n_global; other entries of x_L are
+ * left untouched (negative ids are masked, as in Listing 5; ids >= n_global
+ * are treated the same way, so a bad id never reads outside x_G).  d_map
+ * (int32[n_local], device) is read directly, as the listing's scatterIds:
+ * no plan is needed.  Bit-exact copy of the values.  x_L must not overlap
+ * x_G or d_map.  The tune entry of the scatter (op 6) gives the entries per
+ * thread (unroll) and the grid cap. */
+bs_status bs_scatter(bs_ctx* ctx, bs_dtype dtype, int64_t n_local, const int32_t* d_map, int64_t n_global,
+                     const void* xG, void* xL, void* stream);
+
+/* BS7 through a plan (Table 1; Listing 5; Section 5): the same result as
+ * bs_scatter with the plan's map, by the kernel the tune entry selects
+ * (sorted tiles visited in order of their smallest global id, by default).
+ * The plan's map was validated when the plan was built. */
+bs_status bs_gs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Element operators of the Helmholtz problem inside the scattered form
+ * (Section 2, eqs. helm_var, global_system, assembled_stiff, assembled_mass):
+ * y_G = Z^T A_L Z x_G with A_L block diagonal, binary64.
+ *
+ * Basis: tensor-product Lagrange polynomials through the N+1 Gauss-Lobatto-
+ * Legendre (GLL) points per axis, local node i + (N+1)(j + (N+1) k) as in
+ * bs_mesh_hex_map.  Element integrals use the N+1 point Gauss-Legendre rule
+ * (exact for products of degree-N polynomials) on affine hexahedra, whose
+ * geometry is given per element e as seven doubles
+ *     d_geo[7e .. 7e+6] = (G11, G12, G13, G22, G23, G33, |J|),
+ * G = |J| J^-1 J^-T (for an axis-aligned cube of side h in any orientation,
+ * G = (h/2) I and |J| = (h/2)^3).  Then
+ *     A^e = S^e + lambda M^e,  S^e = sum_dd' A_d^T W G_dd' A_d',
+ *     M^e = |J| Bq^T W Bq,
+ * A_1 = B x B x D (derivative along i), A_2 = B x D x B, A_3 = D x B x B,
+ * B[a][i] = l_i(xi_a), D[a][i] = l_i'(xi_a) at the Gauss points xi_a,
+ * W the product Gauss weights.  The lumped mass puts the GLL rule on the
+ * nodes: the diagonal block d_l = |J| w_i w_j w_k (GLL weights).
+ * ------------------------------------------------------------------------- */
+
+typedef struct bs_elem bs_elem; /* the 1D rules and basis tables of degree N */
+
+/* Rules and basis tables of degree N in [1, 15] on the context's device
+ * (the local Helmholtz operator supports N <= 7; the lumped mass any N).
+ * Nodes and weights come from Newton iterations in extended precision,
+ * rounded to binary64.  Allocates and synchronises. */
+bs_status bs_elem_create(bs_ctx* ctx, int N, bs_elem** out);
+bs_status bs_elem_destroy(bs_elem* el);
+
+/* Host copies of the rules (N+1 values each; any pointer may be NULL):
+ * GLL nodes and weights, Gauss-Legendre nodes and weights, ascending. */
+bs_status bs_elem_rules(const bs_elem* el, double* gll_x, double* gll_w, double* gauss_x, double* gauss_w);
+
+/* y_L = A_L Z x_G for n_elem elements whose local nodes are numbered
+ * e (N+1)^3 + i + (N+1)(j + (N+1) k): each element's values are read
+ * through d_map[n_elem (N+1)^3] from x_G (ids outside [0, n_global) read
+ * 0, as for masked nodes) and never stored as x_L (the scatter is fused
+ * into the operator); y_L (binary64[n_elem (N+1)^3]) receives A^e u^e.
+ * Sum-factorised on the matrix cores (MFMA); the result equals the dense
+ * blocks' product up to rounding (it is not bit-reproducible against a
+ * different evaluation order).  BS_ERR_UNSUPPORTED for N > 7.  y_L must
+ * not overlap the inputs.  Asynchronous. */
+bs_status bs_helmholtz_local(bs_ctx* ctx, const bs_elem* el, int64_t n_elem, const int32_t* d_map,
+                             int64_t n_global, const double* d_geo, double lambda, const double* xG, double* yL,
+                             void* stream);
+
+/* y_G = Z^T A_L Z x_G on a plan: bs_helmholtz_local with the plan's map
+ * into the caller's work vector yL_work (binary64[n_local]), then the
+ * gather (BS6) of yL_work into y_G.  Asynchronous. */
+bs_status bs_helmholtz_apply(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* d_geo, double lambda,
+                             const double* xG, double* yL_work, double* yG, void* stream);
+
+/* Lumped mass y_G = Z^T D_L Z x_G without a local vector: y_G[g] adds
+ * fl(d_l x_G[g]) over the copies l of g in ascending l from +0.0 (the
+ * gather's order, Listing 4), d_l = fl(fl(fl(w_i w_j) w_k) |J_e|) computed
+ * from the column's element e and node (i, j, k).  One pass over the CSR
+ * of Z^T: reads x_G once, writes y_G once.  Asynchronous. */
+bs_status bs_mass_lumped(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* d_geo, const double* xG,
+                         double* yG, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Conjugate gradients built from the operations above (Algorithm 1), on the

@@ -55,8 +55,17 @@ PROTOTYPES = {
     "bs_gs_degree": (_st, [_p, _p, _p]),
     "bs_gs_weights": (_st, [_p, _i32, _p, _p]),
     "bs_gather": (_st, [_p, _p, _i32, _p, _p, _p]),
-    "bs_scatter": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "bs_scatter": (_st, [_p, _i32, _i64, _p, _i64, _p, _p, _p]),
+    "bs_gs_scatter": (_st, [_p, _p, _i32, _p, _p, _p]),
+    "bs_axpy_dev": (_st, [_p, _i32, _i64, _d, _p, _p, _p, _d, _p, _p, _p, _p]),
+    "bs_cg_update_dev": (_st, [_p, _i32, _i64, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "bs_stencil7": (_st, [_p, _i32, _i64, _d, _p, _p, _p]),
+    "bs_elem_create": (_st, [_p, _i32, ctypes.POINTER(_p)]),
+    "bs_elem_destroy": (_st, [_p]),
+    "bs_elem_rules": (_st, [_p, _p, _p, _p, _p]),
+    "bs_helmholtz_local": (_st, [_p, _p, _i64, _p, _i64, _p, _d, _p, _p, _p]),
+    "bs_helmholtz_apply": (_st, [_p, _p, _p, _p, _d, _p, _p, _p, _p]),
+    "bs_mass_lumped": (_st, [_p, _p, _p, _p, _p, _p, _p]),
     "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
@@ -122,15 +131,28 @@ def _check(status, where):
         raise BSError(status, where, lib.bs_last_error().decode())
 
 
-def _ptr(t):
-    """Device address of a tensor (or an int address, or None)."""
+def _ptr(t, device=None):
+    """Device address of a tensor (or an int address, or None).
+
+    Tensors must be contiguous and on a HIP device (the kernels dereference
+    the address, so a host tensor is rejected here, before any launch), and
+    on `device` when it is given."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if not t.is_cuda:
+        raise ValueError(f"tensors passed to the library must be on a HIP device, not {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"tensor on device {t.device.index}, expected device {device}")
     if not t.is_contiguous():
         raise ValueError("tensors passed to the library must be contiguous")
     return t.data_ptr()
+
+
+def _ptrs(owner, *ts):
+    """Addresses of tensors that must all be on owner's (context or plan) device."""
+    return [_ptr(t, owner.device) for t in ts]
 
 
 def _dtype_id(t):
@@ -220,12 +242,14 @@ def bs_ctx_get_tune(ctx, op, dtype=BS_F64):
 
 def bs_copy(ctx, x, y, stream=None):
     _same(x, y, "bs_copy")
-    _check(lib.bs_copy(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(y), _stream(stream)), "bs_copy")
+    px, py = _ptrs(ctx, x, y)
+    _check(lib.bs_copy(ctx.handle, _dtype_id(x), x.numel(), px, py, _stream(stream)), "bs_copy")
 
 
 def bs_axpy(ctx, alpha, x, beta, y, stream=None):
     _same(x, y, "bs_axpy")
-    _check(lib.bs_axpy(ctx.handle, _dtype_id(x), x.numel(), float(alpha), _ptr(x), float(beta), _ptr(y),
+    px, py = _ptrs(ctx, x, y)
+    _check(lib.bs_axpy(ctx.handle, _dtype_id(x), x.numel(), float(alpha), px, float(beta), py,
                        _stream(stream)), "bs_axpy")
 
 
@@ -239,15 +263,15 @@ def bs_norm(ctx, x, w, out, stream=None):
     _out(out, "bs_norm")
     if w is not None:
         _same(x, w, "bs_norm")
-    _check(lib.bs_norm(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(w), _ptr(out), _stream(stream)),
-           "bs_norm")
+    px, pw, po = _ptrs(ctx, x, w, out)
+    _check(lib.bs_norm(ctx.handle, _dtype_id(x), x.numel(), px, pw, po, _stream(stream)), "bs_norm")
 
 
 def bs_dot(ctx, x, y, out, stream=None):
     _out(out, "bs_dot")
     _same(x, y, "bs_dot")
-    _check(lib.bs_dot(ctx.handle, _dtype_id(x), x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream(stream)),
-           "bs_dot")
+    px, py, po = _ptrs(ctx, x, y, out)
+    _check(lib.bs_dot(ctx.handle, _dtype_id(x), x.numel(), px, py, po, _stream(stream)), "bs_dot")
 
 
 def bs_cg_update(ctx, alpha, x, p, r, Ap, w, out, stream=None):
@@ -256,8 +280,43 @@ def bs_cg_update(ctx, alpha, x, p, r, Ap, w, out, stream=None):
         _same(x, v, "bs_cg_update " + nm)
     if w is not None:
         _same(x, w, "bs_cg_update w")
-    _check(lib.bs_cg_update(ctx.handle, _dtype_id(x), x.numel(), float(alpha), _ptr(x), _ptr(p), _ptr(r),
-                            _ptr(Ap), _ptr(w), _ptr(out), _stream(stream)), "bs_cg_update")
+    ptrs = _ptrs(ctx, x, p, r, Ap, w, out)
+    _check(lib.bs_cg_update(ctx.handle, _dtype_id(x), x.numel(), float(alpha), *ptrs, _stream(stream)),
+           "bs_cg_update")
+
+
+def _scalar(t, what):
+    """A device binary64 scalar given as a float64 device tensor of one element (or None)."""
+    import torch
+    if t is None:
+        return None
+    if t.dtype != torch.float64 or t.numel() != 1:
+        raise ValueError(f"{what}: expected a float64 device tensor of one element")
+    return t
+
+
+def bs_axpy_dev(ctx, x, y, alpha=1.0, alpha_num=None, alpha_den=None, beta=1.0, beta_num=None, beta_den=None,
+                stream=None):
+    """y = a x + b y with a = alpha * (alpha_num / alpha_den) and b = beta * (beta_num / beta_den)
+    read on the device (one-element float64 tensors; None reads as 1)."""
+    _same(x, y, "bs_axpy_dev")
+    sc = [_scalar(t, "bs_axpy_dev") for t in (alpha_num, alpha_den, beta_num, beta_den)]
+    px, py, an, ad, bn, bd = _ptrs(ctx, x, y, *sc)
+    _check(lib.bs_axpy_dev(ctx.handle, _dtype_id(x), x.numel(), float(alpha), an, ad, px, float(beta), bn, bd, py,
+                           _stream(stream)), "bs_axpy_dev")
+
+
+def bs_cg_update_dev(ctx, x, p, r, Ap, w, out, alpha=1.0, alpha_num=None, alpha_den=None, stream=None):
+    """BS5 with alpha = alpha * (alpha_num / alpha_den) read on the device."""
+    _out(out, "bs_cg_update_dev")
+    for v, nm in ((p, "p"), (r, "r"), (Ap, "Ap")):
+        _same(x, v, "bs_cg_update_dev " + nm)
+    if w is not None:
+        _same(x, w, "bs_cg_update_dev w")
+    sc = [_scalar(t, "bs_cg_update_dev") for t in (alpha_num, alpha_den)]
+    an, ad, px, pp, pr, pa, pw, po = _ptrs(ctx, *sc, x, p, r, Ap, w, out)
+    _check(lib.bs_cg_update_dev(ctx.handle, _dtype_id(x), x.numel(), float(alpha), an, ad, px, pp, pr, pa, pw, po,
+                                _stream(stream)), "bs_cg_update_dev")
 
 
 def bs_mesh_hex_map(K, N, perm, orient, out, stream=None):
@@ -283,7 +342,7 @@ def bs_mesh_hex_map_host(K, N, perm=None, orient=None):
 
 def bs_gs_create(ctx, d_map, n_global, stream=None):
     h = _p()
-    _check(lib.bs_gs_create(ctx.handle, _ptr(d_map), d_map.numel(), int(n_global), _stream(stream),
+    _check(lib.bs_gs_create(ctx.handle, _ptr(d_map, ctx.device), d_map.numel(), int(n_global), _stream(stream),
                             ctypes.byref(h)), "bs_gs_create")
     plan = Plan(h.value, ctx.device)
     for k, v in bs_gs_info(plan).items():
@@ -300,12 +359,12 @@ def bs_gs_info(plan):
 def bs_gs_csr(plan, row_starts, col_ids, stream=None):
     plan.expect(row_starts, plan.n_global + 1, "bs_gs_csr row_starts")
     plan.expect(col_ids, plan.n_unmasked, "bs_gs_csr col_ids")
-    _check(lib.bs_gs_csr(plan.handle, _ptr(row_starts), _ptr(col_ids), _stream(stream)), "bs_gs_csr")
+    _check(lib.bs_gs_csr(plan.handle, *_ptrs(plan, row_starts, col_ids), _stream(stream)), "bs_gs_csr")
 
 
 def bs_gs_degree(plan, deg, stream=None):
     plan.expect(deg, plan.n_global, "bs_gs_degree")
-    _check(lib.bs_gs_degree(plan.handle, _ptr(deg), _stream(stream)), "bs_gs_degree")
+    _check(lib.bs_gs_degree(plan.handle, _ptr(deg, plan.device), _stream(stream)), "bs_gs_degree")
 
 
 def bs_gs_order_rows(plan, mx, my, mz, tile, box=0, stream=None):
@@ -319,19 +378,30 @@ def bs_gs_order_rows(plan, mx, my, mz, tile, box=0, stream=None):
 
 def bs_gs_weights(plan, wL, stream=None):
     plan.expect(wL, plan.n_local, "bs_gs_weights")
-    _check(lib.bs_gs_weights(plan.handle, _dtype_id(wL), _ptr(wL), _stream(stream)), "bs_gs_weights")
+    _check(lib.bs_gs_weights(plan.handle, _dtype_id(wL), _ptr(wL, plan.device), _stream(stream)), "bs_gs_weights")
 
 
 def bs_gather(ctx, plan, xL, xG, stream=None):
     plan.expect(xL, plan.n_local, "bs_gather xL")
     plan.expect(xG, plan.n_global, "bs_gather xG")
-    _check(lib.bs_gather(ctx.handle, plan.handle, _dtype_id(xL), _ptr(xL), _ptr(xG), _stream(stream)), "bs_gather")
+    pl, pg = _ptrs(plan, xL, xG)
+    _check(lib.bs_gather(ctx.handle, plan.handle, _dtype_id(xL), pl, pg, _stream(stream)), "bs_gather")
 
 
-def bs_scatter(ctx, plan, xG, xL, stream=None):
-    plan.expect(xL, plan.n_local, "bs_scatter xL")
-    plan.expect(xG, plan.n_global, "bs_scatter xG")
-    _check(lib.bs_scatter(ctx.handle, plan.handle, _dtype_id(xG), _ptr(xG), _ptr(xL), _stream(stream)),
+def bs_gs_scatter(ctx, plan, xG, xL, stream=None):
+    plan.expect(xL, plan.n_local, "bs_gs_scatter xL")
+    plan.expect(xG, plan.n_global, "bs_gs_scatter xG")
+    pg, pl = _ptrs(plan, xG, xL)
+    _check(lib.bs_gs_scatter(ctx.handle, plan.handle, _dtype_id(xG), pg, pl, _stream(stream)), "bs_gs_scatter")
+
+
+def bs_scatter(ctx, d_map, xG, xL, stream=None):
+    """x_L[l] = x_G[d_map[l]] for ids in [0, len(xG)); other entries of xL untouched."""
+    import torch
+    if d_map.dtype != torch.int32 or d_map.numel() != xL.numel() or xG.dtype != xL.dtype:
+        raise ValueError("bs_scatter: map must be int32 with one entry per local value, xG and xL one dtype")
+    pm, pg, pl = _ptrs(ctx, d_map, xG, xL)
+    _check(lib.bs_scatter(ctx.handle, _dtype_id(xG), xL.numel(), pm, xG.numel(), pg, pl, _stream(stream)),
            "bs_scatter")
 
 
@@ -339,8 +409,83 @@ def bs_stencil7(ctx, m, shift, x, y, stream=None):
     _same(x, y, "bs_stencil7")
     if x.numel() != m ** 3:
         raise ValueError("bs_stencil7: vectors must have m^3 entries")
-    _check(lib.bs_stencil7(ctx.handle, _dtype_id(x), m, float(shift), _ptr(x), _ptr(y), _stream(stream)),
+    _check(lib.bs_stencil7(ctx.handle, _dtype_id(x), m, float(shift), *_ptrs(ctx, x, y), _stream(stream)),
            "bs_stencil7")
+
+
+# ---------------------------------------------------------------- element operators
+
+class Elem:
+    """A bs_elem: the 1D rules and basis tables of degree N."""
+
+    def __init__(self, handle, device, N):
+        self.handle = handle
+        self.device = device
+        self.N = N
+        self.P = (N + 1) ** 3
+
+    def close(self):
+        if self.handle:
+            lib.bs_elem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bs_elem_create(ctx, N):
+    h = _p()
+    _check(lib.bs_elem_create(ctx.handle, int(N), ctypes.byref(h)), "bs_elem_create")
+    return Elem(h.value, ctx.device, int(N))
+
+
+def bs_elem_rules(el):
+    """(gll_x, gll_w, gauss_x, gauss_w) as numpy arrays of N+1 values."""
+    import numpy as np
+    out = [np.empty(el.N + 1) for _ in range(4)]
+    _check(lib.bs_elem_rules(el.handle, *[a.ctypes.data for a in out]), "bs_elem_rules")
+    return tuple(out)
+
+
+def _f64(t, n, what):
+    import torch
+    if t is None or t.dtype != torch.float64 or t.numel() != n:
+        raise ValueError(f"{what}: expected a float64 device tensor of {n} entries")
+
+
+def bs_helmholtz_local(ctx, el, d_map, geo, lam, xG, yL, stream=None):
+    """y_L = A_L Z x_G for the elements of d_map (int32, n_elem (N+1)^3 entries)."""
+    import torch
+    if d_map.dtype != torch.int32 or d_map.numel() % el.P:
+        raise ValueError("bs_helmholtz_local: map must be int32 with whole elements")
+    E = d_map.numel() // el.P
+    _f64(geo, 7 * E, "bs_helmholtz_local geo")
+    _f64(yL, E * el.P, "bs_helmholtz_local yL")
+    _f64(xG, xG.numel(), "bs_helmholtz_local xG")
+    pm, pg, px, py = _ptrs(ctx, d_map, geo, xG, yL)
+    _check(lib.bs_helmholtz_local(ctx.handle, el.handle, E, pm, xG.numel(), pg, float(lam), px, py,
+                                  _stream(stream)), "bs_helmholtz_local")
+
+
+def bs_helmholtz_apply(ctx, el, plan, geo, lam, xG, yL_work, yG, stream=None):
+    _f64(geo, 7 * (plan.n_local // el.P), "bs_helmholtz_apply geo")
+    _f64(xG, plan.n_global, "bs_helmholtz_apply xG")
+    _f64(yG, plan.n_global, "bs_helmholtz_apply yG")
+    _f64(yL_work, plan.n_local, "bs_helmholtz_apply yL_work")
+    pg, px, pw, py = _ptrs(ctx, geo, xG, yL_work, yG)
+    _check(lib.bs_helmholtz_apply(ctx.handle, el.handle, plan.handle, pg, float(lam), px, pw, py, _stream(stream)),
+           "bs_helmholtz_apply")
+
+
+def bs_mass_lumped(ctx, el, plan, geo, xG, yG, stream=None):
+    _f64(geo, 7 * (plan.n_local // el.P), "bs_mass_lumped geo")
+    _f64(xG, plan.n_global, "bs_mass_lumped xG")
+    _f64(yG, plan.n_global, "bs_mass_lumped yG")
+    pg, px, py = _ptrs(ctx, geo, xG, yG)
+    _check(lib.bs_mass_lumped(ctx.handle, el.handle, plan.handle, pg, px, py, _stream(stream)), "bs_mass_lumped")
 
 
 def _solver_vectors(m, b, x, what):
@@ -354,7 +499,7 @@ def bs_cg_solve(ctx, m, shift, b, x, tol=1e-10, max_iter=100000, stream=None, ch
     """Binary64 CG on the 7-point operator; returns the result record as a dict."""
     _solver_vectors(m, b, x, "bs_cg_solve")
     res = CgResult()
-    st = lib.bs_cg_solve(ctx.handle, m, float(shift), _ptr(b), _ptr(x), float(tol), int(max_iter),
+    st = lib.bs_cg_solve(ctx.handle, m, float(shift), *_ptrs(ctx, b, x), float(tol), int(max_iter),
                          ctypes.byref(res), _stream(stream))
     if check:
         _check(st, "bs_cg_solve")
@@ -368,7 +513,7 @@ def bs_cg_ir_solve(ctx, inner_dtype, m, shift, b, x, tol=1e-10, inner_tol=1e-4, 
     """Mixed-precision iterative refinement; inner_dtype is BS_F32, BS_BF16 or BS_F64."""
     _solver_vectors(m, b, x, "bs_cg_ir_solve")
     res = CgResult()
-    st = lib.bs_cg_ir_solve(ctx.handle, int(inner_dtype), m, float(shift), _ptr(b), _ptr(x), float(tol),
+    st = lib.bs_cg_ir_solve(ctx.handle, int(inner_dtype), m, float(shift), *_ptrs(ctx, b, x), float(tol),
                             float(inner_tol), int(max_inner), int(max_outer), ctypes.byref(res), _stream(stream))
     if check:
         _check(st, "bs_cg_ir_solve")
@@ -414,7 +559,7 @@ def bs_batch_create(ctx, n_local, n_global, d_map, stream=None):
     if nl.size != ng.size or d_map.numel() != int(nl.sum()):
         raise ValueError("bs_batch_create: sizes and map disagree")
     h = _p()
-    _check(lib.bs_batch_create(ctx.handle, int(nl.size), nl.ctypes.data, ng.ctypes.data, _ptr(d_map),
+    _check(lib.bs_batch_create(ctx.handle, int(nl.size), nl.ctypes.data, ng.ctypes.data, _ptr(d_map, ctx.device),
                                _stream(stream), ctypes.byref(h)), "bs_batch_create")
     b = Batch(h.value, int(nl.size))
     v = [_i64() for _ in range(4)] + [ctypes.c_int32()]
@@ -447,9 +592,9 @@ def bs_batch_step(ctx, batch, vectors, alpha, beta, out, mode=BS_BATCH_PER_PHASE
     _out(out, "bs_batch_step")
     if out.numel() < 8 * batch.n_inst:
         raise ValueError("bs_batch_step: out needs 8 doubles per instance")
-    v = BatchVectors(*[_ptr(vectors[k]) for k in BATCH_GLOBAL + BATCH_LOCAL])
+    v = BatchVectors(*_ptrs(ctx, *[vectors[k] for k in BATCH_GLOBAL + BATCH_LOCAL]))
     _check(lib.bs_batch_step(ctx.handle, batch.handle, dt, int(mode), ctypes.byref(v), float(alpha), float(beta),
-                             _ptr(out), _stream(stream)), "bs_batch_step")
+                             _ptr(out, ctx.device), _stream(stream)), "bs_batch_step")
 
 
 # ---------------------------------------------------------------- tune tables

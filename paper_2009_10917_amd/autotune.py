@@ -147,7 +147,7 @@ def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
             bsgen.device_uniform(xG, seed, 12)
             reps = 50 if NL <= (1 << 22) else 5
             for op, call in (("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
-                             ("scatter", lambda: bs.bs_scatter(ctx, plan, xG, xL))):
+                             ("scatter", lambda: bs.bs_gs_scatter(ctx, plan, xG, xL))):
                 times = {}
                 for v in (0, 1, 2, 4, 5, 6, 8, 9, 10):
                     unrolls = (1,) if op == "gather" else ((1, 2, 4) if v % 4 < 2 else (1, 4))

@@ -146,14 +146,33 @@ __global__ __launch_bounds__(kBlock) void k_direction(const CgState* st, const t
 
 // ---------------------------------------------------------------- precision changes
 
-// out = round(r * s) in the narrow storage (binary64 -> binary32 -> bfloat16)
+// binary64 -> binary32 rounded to odd: truncate, and set the last bit when
+// the truncation was inexact.  Binary32 keeps 16 more significand bits than
+// bfloat16, so rounding this value to nearest-even bfloat16 gives the
+// binary64 value rounded once to nearest-even bfloat16 (Boldo and
+// Melquiond, "Emulation of FMA and correctly rounded sums: proved
+// algorithms using rounding to odd", IEEE Trans. Computers 2008).
+__device__ __forceinline__ float to_f32_odd(double v) {
+  const float t = __double2float_rz(v);
+  if (static_cast<double>(t) == v || v != v) return t;
+  return __uint_as_float(__float_as_uint(t) | 1u);
+}
+
+template <class T>
+__device__ __forceinline__ typename Storage<T>::E round_once(double v) {
+  if constexpr (std::is_same<T, dev::bf16>::value) {
+    return Storage<T>::store(to_f32_odd(v));
+  } else {
+    return Storage<T>::store(static_cast<typename Storage<T>::C>(v));
+  }
+}
+
+// out = r * s rounded once, to nearest with ties to even, to the storage type
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_scale_to(const double* __restrict__ r, double s, int64_t n,
                                                      typename Storage<T>::E* __restrict__ out) {
-  using S = Storage<T>;
-  using C = typename S::C;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) out[i] = S::store(static_cast<C>(r[i] * s));
+  if (i < n) out[i] = round_once<T>(r[i] * s);
 }
 
 // x = x + s * d  (binary64 x, narrow d)

@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_tiles(const int32_t* __restr
 
 template <class E, int U>
 __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ map, const E* __restrict__ xG,
-                                                    E* __restrict__ xL, int64_t n_local) {
+                                                    E* __restrict__ xL, int64_t n_local, int64_t n_global) {
   const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock * U;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock * U + threadIdx.x; i < n_local; i += step) {
     int32_t id[U];
@@ -446,10 +446,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (id[u] >= 0) v[u] = xG[id[u]];
+      if (id[u] >= 0 && id[u] < n_global) v[u] = xG[id[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (id[u] >= 0) dev::st_nt(xL + i + static_cast<int64_t>(u) * kBlock, v[u]);
+      if (id[u] >= 0 && id[u] < n_global) dev::st_nt(xL + i + static_cast<int64_t>(u) * kBlock, v[u]);
   }
 }
 
@@ -486,12 +486,23 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
 }
 
 template <class E, int U>
-void launch_scatter_map(const bs_gs* gs, int cap, const void* xG, void* xL, hipStream_t st) {
+void launch_scatter_map(const int32_t* map, int64_t n_local, int64_t n_global, int cap, const void* xG, void* xL,
+                        hipStream_t st) {
   const int64_t per = static_cast<int64_t>(kBlock) * U;
-  int64_t g = (gs->n_local + per - 1) / per;
+  int64_t g = (n_local + per - 1) / per;
   if (g > cap) g = cap;
-  hipLaunchKernelGGL((k_scatter<E, U>), dim3(static_cast<unsigned int>(g)), dim3(kBlock), 0, st, gs->map,
-                     static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local);
+  hipLaunchKernelGGL((k_scatter<E, U>), dim3(static_cast<unsigned int>(g)), dim3(kBlock), 0, st, map,
+                     static_cast<const E*>(xG), static_cast<E*>(xL), n_local, n_global);
+}
+
+// Plain scatter from a map (local order, `unroll` entries per thread).
+template <class E>
+void scatter_by_map(int unroll, const int32_t* map, int64_t n_local, int64_t n_global, int cap, const void* xG,
+                    void* xL, hipStream_t st) {
+  if (unroll >= 8) launch_scatter_map<E, 8>(map, n_local, n_global, cap, xG, xL, st);
+  else if (unroll >= 4) launch_scatter_map<E, 4>(map, n_local, n_global, cap, xG, xL, st);
+  else if (unroll >= 2) launch_scatter_map<E, 2>(map, n_local, n_global, cap, xG, xL, st);
+  else launch_scatter_map<E, 1>(map, n_local, n_global, cap, xG, xL, st);
 }
 
 template <class E, int TPW>
@@ -538,16 +549,10 @@ bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hi
         else launch_scatter_tiles<E, 1>(gs, order, xG, xL, st);
       }
     }
-  } else if (tn.unroll >= 8) {
-    launch_scatter_map<E, 8>(gs, tn.grid_cap, xG, xL, st);
-  } else if (tn.unroll >= 4) {
-    launch_scatter_map<E, 4>(gs, tn.grid_cap, xG, xL, st);
-  } else if (tn.unroll >= 2) {
-    launch_scatter_map<E, 2>(gs, tn.grid_cap, xG, xL, st);
   } else {
-    launch_scatter_map<E, 1>(gs, tn.grid_cap, xG, xL, st);
+    scatter_by_map<E>(tn.unroll, gs->map, gs->n_local, gs->n_global, tn.grid_cap, xG, xL, st);
   }
-  return check_launch("bs_scatter");
+  return check_launch("bs_gs_scatter");
 }
 
 bs_status check_gs_op(const char* op, bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xL,
@@ -583,10 +588,10 @@ extern "C" bs_status bs_gather(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, con
   return fail(BS_ERR_INVALID_ARG, "bs_gather: unknown dtype");
 }
 
-extern "C" bs_status bs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
-                                void* stream) {
+extern "C" bs_status bs_gs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, const void* xG, void* xL,
+                                   void* stream) {
   bs_status s;
-  if ((s = check_gs_op("bs_scatter", ctx, gs, dtype, xL, xG))) return s;
+  if ((s = check_gs_op("bs_gs_scatter", ctx, gs, dtype, xL, xG))) return s;
   if (gs->n_local == 0) return BS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {
@@ -594,5 +599,34 @@ extern "C" bs_status bs_scatter(bs_ctx* ctx, const bs_gs* gs, bs_dtype dtype, co
     case BS_F32: return run_scatter<float>(ctx, gs, xG, xL, st);
     case BS_BF16: return run_scatter<bf16>(ctx, gs, xG, xL, st);
   }
-  return fail(BS_ERR_INVALID_ARG, "bs_scatter: unknown dtype");
+  return fail(BS_ERR_INVALID_ARG, "bs_gs_scatter: unknown dtype");
+}
+
+extern "C" bs_status bs_scatter(bs_ctx* ctx, bs_dtype dtype, int64_t n_local, const int32_t* d_map,
+                                int64_t n_global, const void* xG, void* xL, void* stream) {
+  const char* op = "bs_scatter";
+  bs_status s;
+  if ((s = check_ctx(ctx, op)) || (s = check_dtype(op, dtype))) return s;
+  if (n_local < 0 || n_global < 0) return fail(BS_ERR_INVALID_ARG, "%s: negative length", op);
+  if (n_local > 0 && !d_map) return fail(BS_ERR_INVALID_ARG, "%s: d_map is NULL", op);
+  if (d_map && !aligned_to(d_map, 4)) return fail(BS_ERR_INVALID_ARG, "%s: d_map is not 4-byte aligned", op);
+  if ((s = check_vec(op, "xL", xL, n_local, dtype)) || (s = check_vec(op, "xG", xG, n_global, dtype))) return s;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(xL), b = reinterpret_cast<uintptr_t>(xG),
+                  c = reinterpret_cast<uintptr_t>(d_map);
+  const uintptr_t na = static_cast<uintptr_t>(n_local) * dtype_size(dtype);
+  const uintptr_t nb = static_cast<uintptr_t>(n_global) * dtype_size(dtype);
+  const uintptr_t nc = static_cast<uintptr_t>(n_local) * 4;
+  if (na && nb && a < b + nb && b < a + na) return fail(BS_ERR_INVALID_ARG, "%s: xL and xG overlap", op);
+  if (na && a < c + nc && c < a + na) return fail(BS_ERR_INVALID_ARG, "%s: xL overlaps the map", op);
+  if (n_local == 0) return BS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the plain kernel in local order; its entries per thread and grid cap
+  // come from the scatter's tune entry
+  const Tune& tn = tune_for(ctx, OP_SCATTER, static_cast<int>(dtype), n_local);
+  switch (dtype) {
+    case BS_F64: scatter_by_map<double>(tn.unroll, d_map, n_local, n_global, tn.grid_cap, xG, xL, st); break;
+    case BS_F32: scatter_by_map<float>(tn.unroll, d_map, n_local, n_global, tn.grid_cap, xG, xL, st); break;
+    case BS_BF16: scatter_by_map<uint16_t>(tn.unroll, d_map, n_local, n_global, tn.grid_cap, xG, xL, st); break;
+  }
+  return check_launch(op);
 }

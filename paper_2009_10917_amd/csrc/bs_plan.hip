@@ -15,10 +15,9 @@
 // The last two are orderings of work only: no vector is renumbered, and the
 // results of gather and scatter are the same bits whichever order is used.
 
-#include <hipcub/hipcub.hpp>
-
 #include "bs_device.h"
 #include "bs_internal.h"
+#include "bs_prim.h"
 
 namespace bs {
 namespace {
@@ -472,16 +471,21 @@ struct Builder {
     hip(hipStreamSynchronize(st));
     return h;
   }
-  // hipcub call with its own scratch allocation
-  template <class F>
-  void cub(F f) {
+  // out[i] = in[0] + ... + in[i-1] (the library's own scan)
+  void scan(const int32_t* in, int32_t* out, int64_t n) {
+    if (ok()) s = scan_exclusive_i32(in, out, n, st, op);
+  }
+  // stable sort of (key, value) pairs by the low `bits` key bits into
+  // k1/v1 (k0/v0 are clobbered)
+  void sort(uint32_t* k0, uint32_t* k1, int32_t* v0, int32_t* v1, int64_t n, int bits) {
     if (!ok()) return;
-    size_t bytes = 0;
-    hip(f(nullptr, bytes));
-    DevBuf tmp;
-    need(tmp, bytes, "scratch");
-    if (ok()) hip(f(tmp.p, bytes));
-    hip(hipStreamSynchronize(st));  // the scratch is freed on return
+    bool in_alt = false;
+    s = sort_pairs_u32(k0, k1, v0, v1, n, bits, st, op, &in_alt);
+    if (ok() && !in_alt && n > 0) {  // an even number of passes ended in k0/v0
+      hip(hipMemcpyAsync(k1, k0, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+      hip(hipMemcpyAsync(v1, v0, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      hip(hipStreamSynchronize(st));
+    }
   }
 };
 
@@ -517,18 +521,14 @@ void build_csr(Builder& B, bs_gs* gs, const int32_t* d_map) {
   }
   int32_t* dg = deg.as<int32_t>();
   int32_t* rsp = rs.as<int32_t>();
-  B.cub([&](void* t, size_t& b) {
-    return hipcub::DeviceScan::ExclusiveSum(t, b, dg, rsp, static_cast<int>(ng + 1), B.st);
-  });
+  B.scan(dg, rsp, ng + 1);
   if (nl > 0) {
     const int bits = sort_bits(static_cast<uint64_t>(ng));
     uint32_t* k0 = keys.as<uint32_t>();
     uint32_t* k1 = keys_out.as<uint32_t>();
     int32_t* v0 = vals.as<int32_t>();
     int32_t* v1 = vals_out.as<int32_t>();
-    B.cub([&](void* t, size_t& b) {
-      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(nl), 0, bits, B.st);
-    });
+    B.sort(k0, k1, v0, v1, nl, bits);
   }
   if (!B.ok()) return;
   gs->n_unmasked = B.read(rsp + ng);
@@ -592,9 +592,7 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
     uint32_t* k1 = tkey_out.as<uint32_t>();
     int32_t* v0 = tidx.as<int32_t>();
     int32_t* v1 = order.as<int32_t>();
-    B.cub([&](void* t, size_t& b) {
-      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(nt), 0, 32, B.st);
-    });
+    B.sort(k0, k1, v0, v1, nt, 32);
   }
   B.hip(hipStreamSynchronize(B.st));
   if (!B.ok()) return;
@@ -676,16 +674,14 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
     uint32_t* k1 = rkey_out.as<uint32_t>();
     int32_t* v0 = rows0.as<int32_t>();
     int32_t* v1 = rows.as<int32_t>();
-    B.cub([&](void* t, size_t& b) {
-      return hipcub::DeviceRadixSort::SortPairs(t, b, k0, k1, v0, v1, static_cast<int>(ng), 0, 32, B.st);
-    });
+    B.sort(k0, k1, v0, v1, ng, 32);
   }
   hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(nz + 1)), dim3(kBlock), 0, B.st, rows.as<int32_t>(), nz,
                      gs->row_starts, d32.as<int32_t>());
   B.launched();
   int32_t* dp = d32.as<int32_t>();
   int32_t* pp = prs.as<int32_t>();
-  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, dp, pp, static_cast<int>(nz + 1), B.st); });
+  B.scan(dp, pp, nz + 1);
   if (nz > 0)
     hipLaunchKernelGGL(k_perm_cols, dim3(blocks_for(nz)), dim3(kBlock), 0, B.st, rows.as<int32_t>(), nz,
                        gs->row_starts, gs->col_ids, prs.as<int32_t>(), pcols.as<int32_t>());
@@ -708,7 +704,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.launched();
   int32_t* ns = nseg.as<int32_t>();
   int32_t* so = segoff.as<int32_t>();
-  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, ns, so, static_cast<int>(nb + 1), B.st); });
+  B.scan(ns, so, nb + 1);
   const int64_t total_segs = B.ok() ? static_cast<int64_t>(B.read(so + nb)) : 0;
   B.need(segs, (total_segs > 0 ? total_segs : 1) * 4, "window segments");
   if (!B.ok()) return;
@@ -728,7 +724,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.launched();
   int32_t* nr = nruns.as<int32_t>();
   int32_t* ro = runoff.as<int32_t>();
-  B.cub([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, nr, ro, static_cast<int>(nb + 1), B.st); });
+  B.scan(nr, ro, nb + 1);
   const int64_t total_runs = B.ok() ? static_cast<int64_t>(B.read(ro + nb)) : 0;
   B.need(runs, (total_runs > 0 ? total_runs : 1) * 8, "row runs");
   if (!B.ok()) return;

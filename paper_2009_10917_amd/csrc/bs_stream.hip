@@ -89,6 +89,45 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(typename Storage<T>::C alp
   dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
+// ---------------------------------------------------------------- device scalars
+
+// Scalar of the device-scalar forms: h * (num / den) in binary64, a NULL
+// pointer reading as 1.0 (so with both NULL the host value h alone).  Every
+// thread reads the two doubles when the kernel starts; they were written by
+// an earlier kernel on the stream.
+struct DevScalar {
+  double h;
+  const double* num;
+  const double* den;
+};
+
+__device__ __forceinline__ double dev_scalar(const DevScalar& s) {
+  double q = s.num ? *s.num : 1.0;
+  if (s.den) q = q / *s.den;
+  return s.h * q;
+}
+
+template <class T, int V, int U>
+__global__ __launch_bounds__(kBlock) void k_axpy_dev(DevScalar a, const typename Storage<T>::E* __restrict__ x,
+                                                     DevScalar b, typename Storage<T>::E* __restrict__ y, Span sp) {
+  using C = typename Storage<T>::C;
+  AxpyOp<T, V> op{{}, static_cast<C>(dev_scalar(a)), static_cast<C>(dev_scalar(b)), x, y, sp.head};
+  stream_loop<U>(op, sp);
+}
+
+template <class T, int V, int U, bool W>
+__global__ __launch_bounds__(kBlock) void k_cg_update_dev(DevScalar a, typename Storage<T>::E* __restrict__ x,
+                                                          const typename Storage<T>::E* __restrict__ p,
+                                                          typename Storage<T>::E* __restrict__ r,
+                                                          const typename Storage<T>::E* __restrict__ Ap,
+                                                          const typename Storage<T>::E* __restrict__ w, Span sp,
+                                                          double* partials, double* out) {
+  using C = typename Storage<T>::C;
+  CgOp<T, V, W> op{{}, static_cast<C>(dev_scalar(a)), x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
+  stream_loop<U>(op, sp);
+  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+}
+
 // ---------------------------------------------------------------- host side
 
 
@@ -250,6 +289,42 @@ bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const voi
   return finish(ctx, g, out, st, "bs_cg_update");
 }
 
+template <class T>
+bs_status run_axpy_dev(bs_ctx* ctx, int64_t n, DevScalar a, const void* x, DevScalar b, void* y, hipStream_t st) {
+  using E = typename Storage<T>::E;
+  Span sp = make_span<T>(n, {x, y});
+  const Tune& tn = tune_for(ctx, OP_AXPY, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
+  const int u = norm_unroll(tn.unroll);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
+  BS_DISPATCH(k_axpy_dev, T, sp, u, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
+  return check_launch("bs_axpy_dev");
+}
+
+template <class T>
+bs_status run_cg_update_dev(bs_ctx* ctx, int64_t n, DevScalar a, void* x, const void* p, void* r, const void* Ap,
+                            const void* w, double* out, hipStream_t st) {
+  using E = typename Storage<T>::E;
+  Span sp = make_span<T>(n, {x, p, r, Ap, w});
+  const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
+  sp.order = stream_order(tn.variant);
+  const int u = norm_unroll(tn.unroll);
+  const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
+  if (w)
+    BS_DISPATCH_B(k_cg_update_dev, T, true, sp, u, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w), sp, ctx->partials, out);
+  else
+    BS_DISPATCH_B(k_cg_update_dev, T, false, sp, u, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p), sp, ctx->partials, out);
+  return finish(ctx, g, out, st, "bs_cg_update_dev");
+}
+
+bs_status check_scalar_ptr(const char* op, const char* name, const double* d) {
+  if (d && !aligned_to(d, 8)) return fail(BS_ERR_INVALID_ARG, "%s: %s is not 8-byte aligned", op, name);
+  return BS_OK;
+}
+
 // Pointer [p, p + n*s) and [q, q + m*s) overlap?
 inline bool overlap(const void* p, int64_t nb, const void* q, int64_t mb) {
   if (!p || !q || nb == 0 || mb == 0) return false;
@@ -332,4 +407,47 @@ extern "C" bs_status bs_cg_update(bs_ctx* ctx, bs_dtype dtype, int64_t n, double
       overlap(r, nb, p, nb) || overlap(r, nb, Ap, nb) || overlap(r, nb, w, nb))
     return fail(BS_ERR_INVALID_ARG, "bs_cg_update: x or r overlaps another operand");
   BS_TYPED(dtype, run_cg_update<T>(ctx, n, alpha, x, p, r, Ap, w, d_rr, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" bs_status bs_axpy_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const double* d_alpha_num,
+                                 const double* d_alpha_den, const void* x, double beta, const double* d_beta_num,
+                                 const double* d_beta_den, void* y, void* stream) {
+  bs_status s;
+  const char* op = "bs_axpy_dev";
+  if ((s = check_ctx(ctx, op)) || (s = check_dtype(op, dtype)) || (s = check_vec(op, "x", x, n, dtype)) ||
+      (s = check_vec(op, "y", y, n, dtype)) || (s = check_scalar_ptr(op, "d_alpha_num", d_alpha_num)) ||
+      (s = check_scalar_ptr(op, "d_alpha_den", d_alpha_den)) || (s = check_scalar_ptr(op, "d_beta_num", d_beta_num)) ||
+      (s = check_scalar_ptr(op, "d_beta_den", d_beta_den)))
+    return s;
+  const int64_t nb = n * dtype_size(dtype);
+  if (overlap(x, nb, y, nb)) return fail(BS_ERR_INVALID_ARG, "%s: y overlaps x", op);
+  for (const double* q : {d_alpha_num, d_alpha_den, d_beta_num, d_beta_den})
+    if (overlap(q, 8, y, nb)) return fail(BS_ERR_INVALID_ARG, "%s: y overlaps a scalar", op);
+  if (n == 0) return BS_OK;
+  const DevScalar a{alpha, d_alpha_num, d_alpha_den}, b{beta, d_beta_num, d_beta_den};
+  BS_TYPED(dtype, run_axpy_dev<T>(ctx, n, a, x, b, y, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" bs_status bs_cg_update_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha,
+                                      const double* d_alpha_num, const double* d_alpha_den, void* x, const void* p,
+                                      void* r, const void* Ap, const void* w, double* d_rr, void* stream) {
+  bs_status s;
+  const char* op = "bs_cg_update_dev";
+  if ((s = check_ctx(ctx, op)) || (s = check_dtype(op, dtype)) || (s = check_vec(op, "x", x, n, dtype)) ||
+      (s = check_vec(op, "p", p, n, dtype)) || (s = check_vec(op, "r", r, n, dtype)) ||
+      (s = check_vec(op, "Ap", Ap, n, dtype)) || (s = check_scalar_ptr(op, "d_alpha_num", d_alpha_num)) ||
+      (s = check_scalar_ptr(op, "d_alpha_den", d_alpha_den)))
+    return s;
+  if (w && (s = check_vec(op, "w", w, n, dtype))) return s;
+  if (!d_rr) return fail(BS_ERR_INVALID_ARG, "%s: d_rr is NULL", op);
+  if (!aligned_to(d_rr, 8)) return fail(BS_ERR_INVALID_ARG, "%s: d_rr is not 8-byte aligned", op);
+  if (d_rr == d_alpha_num || d_rr == d_alpha_den) return fail(BS_ERR_INVALID_ARG, "%s: d_rr is a scalar input", op);
+  const int64_t nb = n * dtype_size(dtype);
+  if (overlap(x, nb, r, nb) || overlap(x, nb, p, nb) || overlap(x, nb, Ap, nb) || overlap(x, nb, w, nb) ||
+      overlap(r, nb, p, nb) || overlap(r, nb, Ap, nb) || overlap(r, nb, w, nb))
+    return fail(BS_ERR_INVALID_ARG, "%s: x or r overlaps another operand", op);
+  for (const double* q : {d_alpha_num, d_alpha_den, static_cast<const double*>(d_rr)})
+    if (overlap(q, 8, x, nb) || overlap(q, 8, r, nb)) return fail(BS_ERR_INVALID_ARG, "%s: x or r overlaps a scalar", op);
+  const DevScalar a{alpha, d_alpha_num, d_alpha_den};
+  BS_TYPED(dtype, run_cg_update_dev<T>(ctx, n, a, x, p, r, Ap, w, d_rr, static_cast<hipStream_t>(stream)));
 }

@@ -64,7 +64,10 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_dot(None, 0, 10, 16, 32, 64, None) == INVALID
     assert L.bs_cg_update(None, 0, 10, 1.0, 16, 32, 48, 64, None, 80, None) == INVALID
     assert L.bs_gather(None, None, 0, 16, 32, None) == INVALID
-    assert L.bs_scatter(None, None, 0, 16, 32, None) == INVALID
+    assert L.bs_scatter(None, 0, 16, 16, 16, 32, 64, None) == INVALID
+    assert L.bs_gs_scatter(None, None, 0, 16, 32, None) == INVALID
+    assert L.bs_axpy_dev(None, 0, 10, 1.0, 16, None, 32, 1.0, None, None, 48, None) == INVALID
+    assert L.bs_cg_update_dev(None, 0, 10, 1.0, 16, 24, 32, 48, 64, 80, None, 96, None) == INVALID
     assert L.bs_gs_info(None, None, None, None, None) == INVALID
     assert L.bs_gs_degree(None, 16, None) == INVALID
     assert L.bs_ctx_set_tune(None, 0, 0, 4, 16, 0) == INVALID
@@ -112,3 +115,39 @@ def test_host_map_rejects_out_of_range_entries():
     orient[5] = 24
     with pytest.raises(bs.BSError):
         bs.bs_mesh_hex_map_host(2, 2, None, orient)
+
+
+class _FakeOwner:
+    """Stands in for a context or plan: the binding checks tensors before it
+    touches the handle, so no device is needed."""
+    handle = None
+    device = 0
+    n_local = n_global = 4
+
+    def expect(self, t, n, what):
+        pass
+
+
+def test_binding_rejects_host_tensors_before_any_launch():
+    import torch
+    c = _FakeOwner()
+    x = torch.zeros(4, dtype=torch.float64)
+    y = torch.zeros(4, dtype=torch.float64)
+    out = torch.zeros(1, dtype=torch.float64)
+    m = torch.zeros(4, dtype=torch.int32)
+    calls = [
+        lambda: bs.bs_copy(c, x, y),
+        lambda: bs.bs_axpy(c, 1.0, x, 1.0, y),
+        lambda: bs.bs_norm(c, x, None, out),
+        lambda: bs.bs_dot(c, x, y, out),
+        lambda: bs.bs_cg_update(c, 1.0, x, y, x.clone(), y.clone(), None, out),
+        lambda: bs.bs_axpy_dev(c, x, y, alpha_num=out),
+        lambda: bs.bs_cg_update_dev(c, x, y, x.clone(), y.clone(), None, out, alpha_num=out.clone()),
+        lambda: bs.bs_gather(c, c, x, y),
+        lambda: bs.bs_gs_scatter(c, c, x, y),
+        lambda: bs.bs_scatter(c, m, x, y),
+        lambda: bs.bs_stencil7(c, 1, 0.01, x[:1], y[:1]),
+    ]
+    for f in calls:
+        with pytest.raises(ValueError, match="HIP device"):
+            f()

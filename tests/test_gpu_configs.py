@@ -82,7 +82,7 @@ def test_small_mesh_all_seven_ops(ctx):
     assert float(to_host(o)[0]) == float(NG)
     xG = bsgen.uniform(SEED, 12, NG)
     xL = torch.empty(NL, dtype=torch.float64, device="cuda")
-    bs.bs_scatter(ctx, plan, torch.from_numpy(xG).cuda(), xL)
+    bs.bs_gs_scatter(ctx, plan, torch.from_numpy(xG).cuda(), xL)
     assert np.array_equal(bits(to_host(xL)), bits(ops.scatter(ids, xG, np.zeros(NL))))
     # local weighted norm of a scattered field equals its global norm
     bs.bs_norm(ctx, xL, d_w, o)
@@ -116,7 +116,7 @@ def test_k48_n7_permuted_oriented_in_full(ctx):
     assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, xLh)))
     xGh = bsgen.uniform(SEED, 12, NG)
     xL = dev_uniform(NL, 11)
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     assert np.array_equal(bits(to_host(xL)), bits(ops.scatter(ids, xGh, xLh)))
 
 
@@ -149,11 +149,11 @@ def test_degree_sweep_sampled(ctx, N, K):
     ref = ms.gather_rows(lambda idx: bsgen.uniform_at(SEED, 11, idx))
     assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
     # scatter on sampled slots, bit for bit
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     assert np.array_equal(bits(at(xL, l)), bits(bsgen.uniform_at(SEED, 12, g)))
     # gather(scatter(f)) = deg * f over the whole mesh, for dyadic f
     f = (torch.arange(NG, device="cuda", dtype=torch.float64) % 97) * 0.125 - 6.0
-    bs.bs_scatter(ctx, plan, f, xL)
+    bs.bs_gs_scatter(ctx, plan, f, xL)
     bs.bs_gather(ctx, plan, xL, xG)
     assert torch.equal(xG, f * deg.double())
 
@@ -266,5 +266,5 @@ def test_benchmark_size_gather_scatter(ctx):
     own.close()
     assert np.array_equal(bits(at(xG, ms.g)), bits(ref))
     assert not torch.isnan(xG).any()
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     assert np.array_equal(bits(at(xL, l)), bits(bsgen.uniform_at(SEED, 12, g)))

@@ -42,9 +42,9 @@ def test_captured_step_replays_match_eager(ctx):
 
     def step(v):
         # one CG-like pass of streaming operations on local vectors
-        bs.bs_scatter(ctx, plan, v["xG"], v["pL"])
+        bs.bs_gs_scatter(ctx, plan, v["xG"], v["pL"])
         bs.bs_gather(ctx, plan, v["pL"], v["Ap"])
-        bs.bs_scatter(ctx, plan, v["Ap"], v["ApL"])
+        bs.bs_gs_scatter(ctx, plan, v["Ap"], v["ApL"])
         bs.bs_dot(ctx, v["pL"], v["ApL"], v["out"][0:1])
         bs.bs_cg_update(ctx, 0.01, v["x"], v["pL"], v["r"], v["ApL"], w, v["out"][1:2])
         bs.bs_axpy(ctx, 1.0, v["r"], 0.5, v["p"])

@@ -88,11 +88,11 @@ def test_map_plan_gather_scatter(ctx, K, N, seed):
         bs.bs_gather(ctx, plan, xL, xG)
         assert np.array_equal(bits(to_host(xG)), bits(g_ref)), variant
         xG2 = dev_uniform(NG, 12)
-        bs.bs_scatter(ctx, plan, xG2, xL)
+        bs.bs_gs_scatter(ctx, plan, xG2, xL)
         assert np.array_equal(bits(to_host(xL)), bits(s_ref)), variant
     # gather(scatter(1)) is the degree, exactly
     ones = torch.ones(NG, dtype=torch.float64, device="cuda")
-    bs.bs_scatter(ctx, plan, ones, xL)
+    bs.bs_gs_scatter(ctx, plan, ones, xL)
     bs.bs_gather(ctx, plan, xL, xG)
     assert np.array_equal(to_host(xG), deg_ref.astype(np.float64))
     plan.close()
@@ -115,7 +115,7 @@ def test_masked_entries(ctx, variant):
     bs.bs_gather(ctx, plan, xL, xG)
     assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs_ref, ci_ref, host_uniform(NL, 11))))
     xG2 = dev_uniform(NG, 12)
-    bs.bs_scatter(ctx, plan, xG2, xL)
+    bs.bs_gs_scatter(ctx, plan, xG2, xL)
     assert np.array_equal(bits(to_host(xL)), bits(ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))))
     w = torch.empty(NL, dtype=torch.float64, device="cuda")
     bs.bs_gs_weights(plan, w)
@@ -184,7 +184,7 @@ def test_scatter_map_order_unrolls(ctx, unroll):
     plan = bs.bs_gs_create(ctx, d_map, NG)
     with_variant(ctx, 2, unroll=unroll)
     xL = dev_uniform(NL, 11)
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
@@ -204,7 +204,7 @@ def test_scatter_tiles_per_workgroup(ctx, variant, tpw):
     plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
     bs.bs_ctx_set_tune(ctx, "scatter", tpw, 1 << 30, variant)
     xL = dev_uniform(NL, 11)
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
@@ -220,7 +220,7 @@ def test_scatter_sorted_tiles_with_wide_id_spans(ctx, tpw):
     plan = bs.bs_gs_create(ctx, torch.from_numpy(ref_map.astype(np.int32)).cuda(), NG)
     bs.bs_ctx_set_tune(ctx, "scatter", tpw, 1 << 30, 0)
     xL = dev_uniform(NL, 11)
-    bs.bs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
+    bs.bs_gs_scatter(ctx, plan, dev_uniform(NG, 12), xL)
     ref = ops.scatter(ref_map, host_uniform(NG, 12), host_uniform(NL, 11))
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
@@ -232,7 +232,7 @@ def test_scatter_with_no_global_entries(ctx):
     for variant in (0, 1, 2):
         bs.bs_ctx_set_tune(ctx, "scatter", 4, 1 << 30, variant)
         xL = torch.full((1000,), 3.0, dtype=torch.float64, device="cuda")
-        bs.bs_scatter(ctx, plan, torch.empty(0, dtype=torch.float64, device="cuda"), xL)
+        bs.bs_gs_scatter(ctx, plan, torch.empty(0, dtype=torch.float64, device="cuda"), xL)
         assert np.array_equal(to_host(xL), np.full(1000, 3.0))
 
 

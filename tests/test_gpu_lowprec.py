@@ -169,7 +169,7 @@ def test_gather_scatter_weights(ctx, name):
     assert np.all(np.abs(got - S) <= us * np.abs(S) + deg * U32 * A + 1e-40)
     # scatter copies stored values exactly
     g2, hg2 = stored(dt, NG, 12)
-    bs.bs_scatter(ctx, plan, g2, xL)
+    bs.bs_gs_scatter(ctx, plan, g2, xL)
     assert np.array_equal(as_f64(xL), hg2[ids])
     # weights round 1/deg to the storage type
     wL = torch.empty(NL, dtype=dt, device="cuda")
@@ -223,7 +223,7 @@ def test_gather_scatter_every_variant(name):
         for u in ((1, 2, 4) if v % 4 < 2 else (1, 8)):
             bs.bs_ctx_set_tune(c, "scatter", u, 1 << 30, v)
             x2 = xL.clone()
-            bs.bs_scatter(c, plan, g2, x2)
+            bs.bs_gs_scatter(c, plan, g2, x2)
             assert np.array_equal(as_f64(x2), ref), (v, u)
     torch.cuda.synchronize()
     plan.close()
