@@ -36,6 +36,8 @@ Readings (the paper gives the forms, not the quadrature or the geometry):
 TEST INFRASTRUCTURE ONLY: not part of the library path.
 """
 
+from fractions import Fraction
+
 import numpy as np
 from numpy.polynomial import legendre as L
 
@@ -43,23 +45,74 @@ __all__ = ["gll", "gauss", "lagrange_basis", "element_1d", "element_blocks", "ge
            "apply_local", "apply_assembled", "lumped_weights", "apply_lumped", "node_coordinates"]
 
 
+def _legendre_exact(n, x):
+    """(P_n(x), P_{n-1}(x)) at a rational x by the three-term recurrence
+    (k P_k = (2k - 1) x P_{k-1} - (k - 1) P_{k-2}), in exact arithmetic."""
+    p0, p1 = Fraction(1), x
+    if n == 0:
+        return p0, Fraction(0)
+    for k in range(2, n + 1):
+        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+    return p1, p0
+
+
+def _dlegendre_exact(n, x):
+    """P_n'(x) from (1 - x^2) P_n' = n (P_{n-1} - x P_n), x != +-1."""
+    pn, pm = _legendre_exact(n, x)
+    return n * (pm - x * pn) / (1 - x * x)
+
+
+_ONE = 1 << 256
+
+
+def _polish(x0, f, df, steps=3):
+    """Newton steps on f from the double x0, each evaluated in exact rational
+    arithmetic and its result rounded to a multiple of 2^-256 (so the
+    numbers stay small); from a start within 1e-13 the second step is
+    already below 1e-50."""
+    x = Fraction(float(x0))
+    for _ in range(steps):
+        x = x - f(x) / df(x)
+        x = Fraction(round(x * _ONE), _ONE)
+    return x
+
+
 def gll(N):
     """GLL nodes and weights on [-1, 1]: the ends and the roots of P_N',
-    weights 2 / (N (N+1) P_N(x)^2)."""
+    weights 2 / (N (N+1) P_N(x)^2), each rounded once to binary64.  numpy's
+    companion-matrix roots are only a starting point (they miss the roots by
+    up to tens of units in the last place); Newton steps on P_N' in exact
+    rational arithmetic, with P_N'' from the Legendre equation
+    (1 - x^2) P_N'' = 2 x P_N' - N (N+1) P_N, take each root far below
+    binary64 resolution before it is rounded."""
     if N < 1:
         raise ValueError("degree N >= 1")
     cN = np.zeros(N + 1)
     cN[N] = 1.0
-    inner = np.sort(np.real(L.legroots(L.legder(cN)))) if N >= 2 else np.zeros(0)
-    x = np.concatenate([[-1.0], inner, [1.0]])
-    pN = L.legval(x, cN)
-    w = 2.0 / (N * (N + 1) * pN * pN)
+    guess = np.sort(np.real(L.legroots(L.legder(cN)))) if N >= 2 else np.zeros(0)
+
+    def f(x):
+        return _dlegendre_exact(N, x)
+
+    def df(x):
+        pn, _ = _legendre_exact(N, x)
+        return (2 * x * f(x) - N * (N + 1) * pn) / (1 - x * x)
+
+    roots = [Fraction(-1)] + [_polish(g, f, df) for g in guess] + [Fraction(1)]
+    x = np.array([float(r) for r in roots])
+    w = np.array([float(Fraction(2) / (N * (N + 1) * _legendre_exact(N, r)[0] ** 2)) for r in roots])
     return x, w
 
 
 def gauss(q):
-    """Gauss-Legendre nodes and weights (q points, exact to degree 2q - 1)."""
-    return L.leggauss(q)
+    """Gauss-Legendre nodes and weights (q points, exact to degree 2q - 1):
+    the roots of P_q and 2 / ((1 - x^2) P_q'(x)^2), polished from numpy's
+    values by exact Newton steps and rounded once to binary64."""
+    guess, _ = L.leggauss(q)
+    roots = [_polish(g, lambda x: _legendre_exact(q, x)[0], lambda x: _dlegendre_exact(q, x)) for g in guess]
+    x = np.array([float(r) for r in roots])
+    w = np.array([float(Fraction(2) / ((1 - r * r) * _dlegendre_exact(q, r) ** 2)) for r in roots])
+    return x, w
 
 
 def lagrange_basis(nodes, pts):

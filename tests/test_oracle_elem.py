@@ -9,6 +9,7 @@ so u^T M u and u^T S u are exact integrals).
 """
 
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -25,6 +26,60 @@ def test_gll_closed_forms():
     x, w = elem.gll(3)
     s = 1 / math.sqrt(5)
     assert np.allclose(x, [-1, -s, s, 1], atol=1e-15) and np.allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], atol=1e-15)
+
+
+def _legendre_q(n, x):
+    """P_n(x) and P_n'(x) at a rational x, exactly (the explicit sum
+    P_n(x) = 2^-n sum_k (-1)^k C(n,k) C(2n-2k,n) x^(n-2k), not the
+    recurrence the oracle uses)."""
+    p = sum((-1) ** k * math.comb(n, k) * math.comb(2 * n - 2 * k, n) * x ** (n - 2 * k) for k in range(n // 2 + 1))
+    dp = sum((-1) ** k * math.comb(n, k) * math.comb(2 * n - 2 * k, n) * (n - 2 * k) * x ** (n - 2 * k - 1)
+             for k in range(n // 2 + 1) if n - 2 * k > 0)
+    return p / Fraction(2) ** n, dp / Fraction(2) ** n
+
+
+def _brackets_a_root(f, x):
+    """f changes sign between the midpoints from x to its binary64
+    neighbours, so x is the root rounded to nearest (or f(x) = 0)."""
+    lo = (Fraction(x) + Fraction(np.nextafter(x, -np.inf))) / 2
+    hi = (Fraction(x) + Fraction(np.nextafter(x, np.inf))) / 2
+    return f(Fraction(x)) == 0 or (f(lo) > 0) != (f(hi) > 0)
+
+
+@pytest.mark.parametrize("N", [2, 3, 5, 7, 10, 15])
+def test_rule_nodes_are_correctly_rounded_roots(N):
+    # interior GLL nodes are the roots of P_N', Gauss nodes those of P_{N+1}
+    x, _ = elem.gll(N)
+    for a in range(1, N):
+        assert _brackets_a_root(lambda t: _legendre_q(N, t)[1], x[a]), (N, a)
+    xq, _ = elem.gauss(N + 1)
+    for a in range(N + 1):
+        assert _brackets_a_root(lambda t: _legendre_q(N + 1, t)[0], xq[a]), (N, a)
+
+
+@pytest.mark.parametrize("N", [3, 7, 15])
+def test_rule_weights_within_an_ulp(N):
+    # GLL: w = 2 / (N (N+1) P_N(x)^2), evaluated exactly at the rounded node
+    # (P_N is stationary at the GLL nodes, so the rounding of the node moves
+    # it by far less than an ulp).  Gauss: w = 2 / ((1 - x^2) P_q'(x)^2) is
+    # monotone over the half-ulp interval around the rounded node that holds
+    # the exact root, so the exact weight lies between its values at the two
+    # ends; the oracle's weight is within one ulp of that interval.
+    x, w = elem.gll(N)
+    for a in range(N + 1):
+        ref = float(Fraction(2) / (N * (N + 1) * _legendre_q(N, Fraction(x[a]))[0] ** 2))
+        assert abs(w[a] - ref) <= np.spacing(ref), (N, a)
+    xq, wq = elem.gauss(N + 1)
+
+    def wg(t):
+        return Fraction(2) / ((1 - t * t) * _legendre_q(N + 1, t)[1] ** 2)
+
+    for a in range(N + 1):
+        lo = (Fraction(xq[a]) + Fraction(np.nextafter(xq[a], -np.inf))) / 2
+        hi = (Fraction(xq[a]) + Fraction(np.nextafter(xq[a], np.inf))) / 2
+        w_lo, w_hi = sorted((wg(lo), wg(hi)))
+        u = Fraction(float(np.spacing(wq[a])))
+        assert w_lo - u <= Fraction(wq[a]) <= w_hi + u, (N, a)
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 5, 7, 11, 15])
