@@ -200,8 +200,8 @@ __device__ __forceinline__ int pad_at(int s, int col) {
 
 // acc[t] (+)= A * In for the 4 column tiles of one contraction along X:
 // chunk h reads In at (s = 4h + l/16, col = 16t + l%16); A's operand for
-// chunk h is a[h].  Output lane l holds rows 4(l/16) + v, v = 0..3, of
-// column 16t + l%16.
+// chunk h is a[h].  The binary64 accumulator is interleaved: register v of
+// lane l holds row l/16 + 4v of column 16t + l%16.
 template <int X, int KC>
 __device__ __forceinline__ void contract(const double* __restrict__ in, const double (&a)[KC], dvec4 (&acc)[4]) {
   const int l = threadIdx.x & 63;
@@ -215,25 +215,28 @@ __device__ __forceinline__ void contract(const double* __restrict__ in, const do
   }
 }
 
+// Rows row_off .. row_off + 7 of the accumulator go to rows 0..7 of out
+// (row_off is 0 or 8, so registers v = row_off / 4 and row_off / 4 + 1).
 template <int X>
 __device__ __forceinline__ void store_rows(double* __restrict__ out, const dvec4 (&acc)[4], int row_off) {
   const int l = threadIdx.x & 63;
-  const int r0 = 4 * (l >> 4) - row_off;
-  if (r0 < 0 || r0 >= kAx) return;
+  const int v0 = row_off >> 2;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[pad_at<X>(r0 + v, 16 * t + (l & 15))] = acc[t][v];
+    for (int v = 0; v < 2; ++v) out[pad_at<X>((l >> 4) + 4 * v, 16 * t + (l & 15))] = acc[t][v0 + v];
 }
 
 template <int X>
 __device__ __forceinline__ void load_rows(const double* __restrict__ in, dvec4 (&acc)[4]) {
   const int l = threadIdx.x & 63;
-  const int r0 = 4 * (l >> 4);
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 4; ++t) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[t][v] = (r0 < kAx) ? in[pad_at<X>(r0 + v, 16 * t + (l & 15))] : 0.0;
+    for (int v = 0; v < 2; ++v) acc[t][v] = in[pad_at<X>((l >> 4) + 4 * v, 16 * t + (l & 15))];
+    acc[t][2] = 0.0;
+    acc[t][3] = 0.0;
+  }
 }
 
 __device__ __forceinline__ void zero(dvec4 (&acc)[4]) {
@@ -356,15 +359,15 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
   __syncthreads();
   zero(acc);
   contract<2, 2>(b3, aBt, acc);
-  // y along k: lane l holds node k = 4(l/16) + v at (i, j) = (col % 8, col / 8)
-  const int r0 = 4 * (l >> 4);
-  if (live && r0 < kAx) {
+  // y along k: register v < 2 of lane l holds node k = l/16 + 4v at
+  // (i, j) = (col % 8, col / 8); registers 2 and 3 hold the padding rows
+  if (live) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int col = 16 * t + (l & 15), i = col & 7, j = col >> 3;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = r0 + v;
+      for (int v = 0; v < 2; ++v) {
+        const int k = (l >> 4) + 4 * v;
         if (i < P1 && j < P1 && k < P1) dev::st_nt(yL + e * P + i + P1 * (j + P1 * k), acc[t][v]);
       }
     }
