@@ -202,6 +202,27 @@ bs_status bs_cg_update_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha,
                            const double* d_alpha_den, void* x, const void* p, void* r, const void* Ap,
                            const void* w, double* d_rr, void* stream);
 
+/* BS5 for callers that cannot allocate device memory (code under graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the result of
+ * bs_cg_update with no context.  The per-workgroup partial sums go to a
+ * static device array of the library instead of a context's workspace:
+ * 65,536 compensated pairs plus 16 chunk sums (1 MiB + 256 B per device,
+ * held until the process ends), with the launch shape fixed at 4 packets
+ * per thread and at most 65,536 workgroups, grid-striding over longer
+ * vectors, so every length fits; a grid that would need more pairs is
+ * rejected with BS_ERR_INVALID_ARG.  Nothing is allocated and nothing in the
+ * array needs to start at zero (each call writes every pair it reads).  The
+ * first call on a device looks the array's address up once (with that
+ * device current).  Calls on one device share the array: calls that overlap
+ * in time on one GPU (different streams, or threads) race and must be
+ * serialised by the caller.  Results: x and r bit-identical to bs_cg_update;
+ * *d_rr equal to bs_cg_update's under the same launch shape (its built-in
+ * shape for the CG update) and within 1e-14 of the exact sum otherwise.
+ * Arguments, validation and aliasing rules as bs_cg_update; the vectors and
+ * d_rr must be on the current device. */
+bs_status bs_cg_update_noalloc(bs_dtype dtype, int64_t n, double alpha, void* x, const void* p, void* r,
+                               const void* Ap, const void* w, double* d_rr, void* stream);
+
 /* Scatter map of a structured K x K x K hex mesh of degree N (Section 2,
  * eq. scatter_def): for element slot s (0 <= s < K^3) and local node
  * (i,j,k) (0 <= i,j,k <= N), local index l = s*(N+1)^3 + i + (N+1)*(j + (N+1)*k)

@@ -59,6 +59,7 @@ PROTOTYPES = {
     "bs_gs_scatter": (_st, [_p, _p, _i32, _p, _p, _p]),
     "bs_axpy_dev": (_st, [_p, _i32, _i64, _d, _p, _p, _p, _d, _p, _p, _p, _p]),
     "bs_cg_update_dev": (_st, [_p, _i32, _i64, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "bs_cg_update_noalloc": (_st, [_i32, _i64, _d, _p, _p, _p, _p, _p, _p, _p]),
     "bs_stencil7": (_st, [_p, _i32, _i64, _d, _p, _p, _p]),
     "bs_elem_create": (_st, [_p, _i32, ctypes.POINTER(_p)]),
     "bs_elem_destroy": (_st, [_p]),
@@ -283,6 +284,21 @@ def bs_cg_update(ctx, alpha, x, p, r, Ap, w, out, stream=None):
     ptrs = _ptrs(ctx, x, p, r, Ap, w, out)
     _check(lib.bs_cg_update(ctx.handle, _dtype_id(x), x.numel(), float(alpha), *ptrs, _stream(stream)),
            "bs_cg_update")
+
+
+def bs_cg_update_noalloc(alpha, x, p, r, Ap, w, out, stream=None):
+    """BS5 without a context: the library's static reduction buffer on the
+    current device (calls overlapping on one device race)."""
+    import torch
+    _out(out, "bs_cg_update_noalloc")
+    for v, nm in ((p, "p"), (r, "r"), (Ap, "Ap")):
+        _same(x, v, "bs_cg_update_noalloc " + nm)
+    if w is not None:
+        _same(x, w, "bs_cg_update_noalloc w")
+    dev = torch.cuda.current_device()
+    ptrs = [_ptr(t, dev) for t in (x, p, r, Ap, w, out)]
+    _check(lib.bs_cg_update_noalloc(_dtype_id(x), x.numel(), float(alpha), *ptrs, _stream(stream)),
+           "bs_cg_update_noalloc")
 
 
 def _scalar(t, what):

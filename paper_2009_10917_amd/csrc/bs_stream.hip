@@ -20,6 +20,7 @@
 // first launch would need an agent-scope fence per workgroup, which on this
 // 8-XCD part costs more than the second launch.
 
+#include <mutex>
 #include <type_traits>
 
 #include "bs_stream_ops.h"
@@ -158,19 +159,25 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chunks(const double* __
   }
 }
 
-bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op) {
+// Second stage over `grid` pairs in `partials`; `sums` holds the chunk sums
+// of the two-launch form (grid / kFinishChunk pairs, rounded up).
+bs_status finish_on(const double* partials, double* sums, int grid, double* out, hipStream_t st, const char* op) {
   bs_status s = check_launch(op);
   if (s || grid == 1) return s;
   if (grid <= kFinishDirect) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, grid, out);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, partials, grid, out);
     return check_launch(op);
   }
-  const int chunks = (grid + kFinishChunk - 1) / kFinishChunk;  // <= kMaxStreamBlocks / kFinishChunk
-  double* sums = ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks);
-  hipLaunchKernelGGL(k_finish_chunks, dim3(chunks), dim3(kFinishBlock), 0, st, ctx->partials, grid, sums);
+  const int chunks = (grid + kFinishChunk - 1) / kFinishChunk;
+  hipLaunchKernelGGL(k_finish_chunks, dim3(chunks), dim3(kFinishBlock), 0, st, partials, grid, sums);
   if ((s = check_launch(op))) return s;
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, sums, chunks, out);
   return check_launch(op);
+}
+
+bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op) {
+  // chunks <= kMaxStreamBlocks / kFinishChunk
+  return finish_on(ctx->partials, ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), grid, out, st, op);
 }
 
 // Tune variant of a streaming operation -> Span::order (1 and 2 select the
@@ -268,25 +275,74 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   return finish(ctx, g, out, st, "bs_dot");
 }
 
+// BS5 with an explicit launch shape and reduction buffers: `partials` holds
+// at least `cap` pairs, `sums` at least cap / kFinishChunk (rounded up).
+template <class T>
+bs_status launch_cg_update(int64_t n, double alpha, void* x, const void* p, void* r, const void* Ap, const void* w,
+                           double* out, int unroll, int cap, int variant, double* partials, double* sums,
+                           hipStream_t st, const char* op) {
+  using C = typename Storage<T>::C;
+  using E = typename Storage<T>::E;
+  Span sp = make_span<T>(n, {x, p, r, Ap, w});
+  sp.order = stream_order(variant);
+  const int u = norm_unroll(unroll);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
+  if (g > cap)
+    return fail(BS_ERR_INVALID_ARG, "%s: %d workgroups need more reduction pairs than the %d the buffer holds", op, g,
+                cap);
+  if (w)
+    BS_DISPATCH_B(k_cg_update, T, true, sp, u, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+                  static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w),
+                  sp, partials, out);
+  else
+    BS_DISPATCH_B(k_cg_update, T, false, sp, u, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+                  static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p),
+                  sp, partials, out);
+  return finish_on(partials, sums, g, out, st, op);
+}
+
 template <class T>
 bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const void* p, void* r, const void* Ap,
                         const void* w, double* out, hipStream_t st) {
-  using C = typename Storage<T>::C;
-  Span sp = make_span<T>(n, {x, p, r, Ap, w});
   const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
-  sp.order = stream_order(tn.variant);
-  const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
-  if (w)
-    BS_DISPATCH_B(k_cg_update, T, true, sp, u, g, st, static_cast<C>(alpha), static_cast<typename Storage<T>::E*>(x),
-                  static_cast<const typename Storage<T>::E*>(p), static_cast<typename Storage<T>::E*>(r), static_cast<const typename Storage<T>::E*>(Ap),
-                  static_cast<const typename Storage<T>::E*>(w), sp, ctx->partials, out);
-  else
-    BS_DISPATCH_B(k_cg_update, T, false, sp, u, g, st, static_cast<C>(alpha), static_cast<typename Storage<T>::E*>(x),
-                  static_cast<const typename Storage<T>::E*>(p), static_cast<typename Storage<T>::E*>(r), static_cast<const typename Storage<T>::E*>(Ap),
-                  static_cast<const typename Storage<T>::E*>(p), sp, ctx->partials, out);
-  return finish(ctx, g, out, st, "bs_cg_update");
+  return launch_cg_update<T>(n, alpha, x, p, r, Ap, w, out, tn.unroll, cap, tn.variant, ctx->partials,
+                             ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), st, "bs_cg_update");
+}
+
+// ---------------------------------------------------------------- allocation-free BS5
+
+// Reduction buffer of bs_cg_update_noalloc: kNoAllocPairs per-workgroup
+// pairs, then the chunk sums of the second stage.  One copy per device, held
+// until the process ends.  Host code never passes `scratch` itself (in host
+// code it names a host-side stand-in): it passes the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int kNoAllocPairs = kMaxReduceBlocks;
+constexpr int kNoAllocSums = (kNoAllocPairs + kFinishChunk - 1) / kFinishChunk;
+constexpr int kNoAllocUnroll = 4;  // the built-in launch shape of the CG update
+static __device__ __align__(256) double scratch[2 * (kNoAllocPairs + kNoAllocSums)];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+bs_status scratch_for_current_device(double** out, const char* op) {
+  int device = -1;
+  if (bs_status s = check_hip(hipGetDevice(&device), op)) return s;
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(BS_ERR_UNSUPPORTED, "%s: device %d is beyond the %d devices the scratch table holds", op, device,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (bs_status s = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), op)) return s;
+    if (!ptr) return fail(BS_ERR_HIP, "%s: no device address for the scratch buffer", op);
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return BS_OK;
 }
 
 template <class T>
@@ -407,6 +463,27 @@ extern "C" bs_status bs_cg_update(bs_ctx* ctx, bs_dtype dtype, int64_t n, double
       overlap(r, nb, p, nb) || overlap(r, nb, Ap, nb) || overlap(r, nb, w, nb))
     return fail(BS_ERR_INVALID_ARG, "bs_cg_update: x or r overlaps another operand");
   BS_TYPED(dtype, run_cg_update<T>(ctx, n, alpha, x, p, r, Ap, w, d_rr, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" bs_status bs_cg_update_noalloc(bs_dtype dtype, int64_t n, double alpha, void* x, const void* p, void* r,
+                                          const void* Ap, const void* w, double* d_rr, void* stream) {
+  bs_status s;
+  const char* op = "bs_cg_update_noalloc";
+  if ((s = check_dtype(op, dtype)) || (s = check_vec(op, "x", x, n, dtype)) || (s = check_vec(op, "p", p, n, dtype)) ||
+      (s = check_vec(op, "r", r, n, dtype)) || (s = check_vec(op, "Ap", Ap, n, dtype)))
+    return s;
+  if (w && (s = check_vec(op, "w", w, n, dtype))) return s;
+  if (!d_rr) return fail(BS_ERR_INVALID_ARG, "bs_cg_update_noalloc: d_rr is NULL");
+  if (!aligned_to(d_rr, 8)) return fail(BS_ERR_INVALID_ARG, "bs_cg_update_noalloc: d_rr is not 8-byte aligned");
+  const int64_t nb = n * dtype_size(dtype);
+  if (overlap(x, nb, r, nb) || overlap(x, nb, p, nb) || overlap(x, nb, Ap, nb) || overlap(x, nb, w, nb) ||
+      overlap(r, nb, p, nb) || overlap(r, nb, Ap, nb) || overlap(r, nb, w, nb))
+    return fail(BS_ERR_INVALID_ARG, "bs_cg_update_noalloc: x or r overlaps another operand");
+  double* buf = nullptr;
+  if ((s = scratch_for_current_device(&buf, op))) return s;
+  double* sums = buf + 2 * static_cast<size_t>(kNoAllocPairs);
+  BS_TYPED(dtype, launch_cg_update<T>(n, alpha, x, p, r, Ap, w, d_rr, kNoAllocUnroll, kNoAllocPairs, 0, buf, sums,
+                                      static_cast<hipStream_t>(stream), op));
 }
 
 extern "C" bs_status bs_axpy_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const double* d_alpha_num,

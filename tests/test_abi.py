@@ -68,6 +68,10 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_gs_scatter(None, None, 0, 16, 32, None) == INVALID
     assert L.bs_axpy_dev(None, 0, 10, 1.0, 16, None, 32, 1.0, None, None, 48, None) == INVALID
     assert L.bs_cg_update_dev(None, 0, 10, 1.0, 16, 24, 32, 48, 64, 80, None, 96, None) == INVALID
+    # the context-free CG update validates before it looks up its buffer
+    assert L.bs_cg_update_noalloc(0, 10, 1.0, None, 32, 48, 64, None, 80, None) == INVALID
+    assert L.bs_cg_update_noalloc(7, 10, 1.0, 16, 32, 48, 64, None, 80, None) == INVALID
+    assert L.bs_cg_update_noalloc(0, 10, 1.0, 16, 32, 48, 64, None, None, None) == INVALID
     assert L.bs_gs_info(None, None, None, None, None) == INVALID
     assert L.bs_gs_degree(None, 16, None) == INVALID
     assert L.bs_ctx_set_tune(None, 0, 0, 4, 16, 0) == INVALID
