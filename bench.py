@@ -618,8 +618,8 @@ def elem_ops(ctx, bs, bsgen, torch, np, seed, reps=10, K=64, N=7):
 # gather row order: lattice tiles of GATHER_TILE^3 points, boxes of GATHER_BOX points inside (0: none);
 # 126 = 18 elements of degree 7, boxes one element thick in y and z (slabs along x)
 GATHER_TILE, GATHER_BOX = 126, (126, 7, 7)
-# gather kernel on those rows: the plan's row order (variant 0) with each XCD taking runs of 256
-# blocks in every group of 2048 (+8)
+# gather kernel: the plan's permuted row order (variant 0) with each XCD taking runs of 256 blocks
+# in every group of 2048 (+8)
 GATHER_VARIANT = 8
 
 
@@ -834,9 +834,11 @@ def main():
     bs.bs_mesh_hex_map(K, N, perm, orient, d_map)
     plan = bs.bs_gs_create(ctx, d_map, n)
     del d_map, perm, orient
-    # plan set-up: rows of the gather in lattice tiles (same bits, better cache reuse)
+    # the gather runs in the plan's own row order, derived from the map alone
+    # (groups of consecutive tiles of the scatter's visiting order); the
+    # lattice-tiled order, which needs the ids to be lattice points, is timed
+    # after the step as a structured-mesh extra
     M = K * N + 1
-    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
     bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, GATHER_VARIANT)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -913,6 +915,19 @@ def main():
     per_op["cg_update"]["GDOF_s"] = round(n / (per_ms["cg_update"] * 1e-3) / 1e9, 3)
     value = step_bytes / (ms_step * 1e-3) / 1e9
 
+    # structured-mesh extra (not part of the step): the gather in lattice-tiled rows
+    bs.bs_gs_order_rows(plan, M, M, M, GATHER_TILE, GATHER_BOX)
+    torch.cuda.synchronize()
+    bs.bs_gather(ctx, plan, xL, xG_out, hs)
+    lat_t, _ = _time_calls(lambda: bs.bs_gather(ctx, plan, xL, xG_out, hs), max(args.steps, 5), torch)
+    lat_gbs = byt["gather"] / lat_t / 1e9
+    per_op["gather"]["row_order"] = "plan default (map only)"
+    per_op["gather_lattice_rows"] = {
+        "ms": round(lat_t * 1e3, 4), "GB_s": round(lat_gbs, 1), "frac_hbm_peak": round(lat_gbs / HBM_PEAK_GBS, 4),
+        "alg_bytes": byt["gather"], "in_step": False,
+        "row_order": ("lattice tiles of {}^3 points, boxes of {}x{}x{} (needs global ids that are lattice points; "
+                      "bs_gs_order_rows)").format(GATHER_TILE, *GATHER_BOX)}
+
     cg_gbs = per_op["cg_update"]["GB_s"]
     traffic = read_traffic(byt["cg_update"])
     cu, cg_cap, corder = bs.bs_ctx_tune_for(ctx, "cg_update", n)
@@ -941,8 +956,9 @@ def main():
                                 f"weights uniform[0,1)); BS7 scatter and BS6 gather on the N=7, E={K}^3 hex mesh "
                                 f"(N_L={NL}, N_G={n}; elements permuted and oriented from the seed)"),
                    "n": n, "n_local": NL, "n_global": n, "mesh_K": K, "degree_N": N, "seed": args.seed,
-                   "gather_row_order": (f"lattice tiles of {GATHER_TILE}^3 points"
-                                        + (", boxes of {}x{}x{} points".format(*GATHER_BOX) if GATHER_BOX else "")),
+                   "gather_row_order": ("plan default, from the map alone: rows in groups of 9 consecutive "
+                                        "512-entry tiles of the scatter's visiting order (tiles by smallest global "
+                                        "id), ascending global id within a group"),
                    "gather_variant": GATHER_VARIANT, "alpha": alpha, "beta": beta},
         "per_op": per_op,
         "roofline": roofline,

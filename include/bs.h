@@ -102,9 +102,10 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
  * 256 blocks per XCD in every group of 2048, instead of one contiguous range
  * of blocks per XCD.  Gather: 0 = rows in the plan's permuted order (by default
- * grouped by the scatter tiles that hold their copies; bs_gs_order_rows
- * replaces it with lattice tiles; falls back to 1 when a degree exceeds
- * 1024), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
+ * in groups of 9 consecutive scatter tiles of the visiting order, each row
+ * in the first group holding one of its copies, rows of a group in ascending
+ * global id; bs_gs_order_rows and bs_gs_order_elements replace it; falls
+ * back to 1 when a degree exceeds 1024), 1 = rows in global order, 2 = fixed blocks of 256 rows.  Scatter: 0 = tiles of 512 local
  * entries visited in order of their smallest global id, values read in
  * ascending global id and turned around in LDS, 1 = the same tiles read in
  * local order (for 0 and 1, `unroll` tiles per workgroup, at most 4),
@@ -255,6 +256,31 @@ bs_status bs_mesh_hex_map_host(int64_t K, int N, const int32_t* perm, const uint
 bs_status bs_gs_create(bs_ctx* ctx, const int32_t* d_map, int64_t n_local, int64_t n_global,
                        void* stream, bs_gs** out);
 bs_status bs_gs_destroy(bs_gs* gs);
+
+/* Replace the plan's permuted row order (gather kernel 0: variants 0, 4, 8)
+ * and its scatter tile order with ones grouped by elements (Section 5: each
+ * workgroup of the gather sums the rows of a few neighbouring elements, so
+ * that their local values are read while in cache).  Elements are the
+ * n_local / nodes_per_element runs of consecutive local indices (as in
+ * Listings 4 and 5, local index e * nodes_per_element + node).  Elements are
+ * visited in groups of elements_per_group consecutive visiting ranks; each
+ * row is keyed by the smallest group of an element holding one of its
+ * copies, and the rows of one group stay in ascending global id (so that a
+ * workgroup writes x_G in runs wherever the global numbering has them).
+ * d_elem_rank (device int32[n_elem], values in [0, 2^31)) gives the visiting
+ * ranks; when it is NULL the library derives them from the map alone:
+ * elements sharing a face are neighbours, and the element graph is ordered
+ * by recursive bisection at the median of breadth-first distances from a
+ * far element of each part (no coordinates and no numbering of the global
+ * ids are used).  That form needs nodes_per_element = (N+1)^3, N >= 1, with
+ * the local node numbering of bs_mesh_hex_map, copies the 8 n_elem corner
+ * ids to the host and takes host time roughly linear in n_elem (seconds at
+ * 2 million elements).  The scatter (bs_gs_scatter) visits its tiles in the
+ * same groups.  Gather and scatter results are the same bits in every
+ * order.  Allocates and synchronises `stream`; BS_ERR_INVALID_ARG if
+ * n_local is not a multiple of nodes_per_element or elements_per_group < 1. */
+bs_status bs_gs_order_elements(bs_gs* gs, int64_t nodes_per_element, const int32_t* d_elem_rank,
+                               int64_t elements_per_group, void* stream);
 
 /* Replace the plan's permuted row order (gather kernel 0: variants 0, 4, 8) with a
  * lattice-tiled one, for maps whose global ids are lattice points

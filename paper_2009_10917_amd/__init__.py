@@ -71,6 +71,7 @@ PROTOTYPES = {
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
     "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _i32, _i32, _i32, _p]),
+    "bs_gs_order_elements": (_st, [_p, _i64, _p, _i64, _p]),
     "bs_ctx_set_tune_entry": (_st, [_p, _i32, _i32, _i64, _i32, _i32, _i32]),
     "bs_ctx_tune_for": (_st, [_p, _i32, _i32, _i64, _p, _p, _p]),
     "bs_ctx_load_tune": (_st, [_p, ctypes.c_char_p, _p]),
@@ -390,6 +391,18 @@ def bs_gs_order_rows(plan, mx, my, mz, tile, box=0, stream=None):
     bx, by, bz = (box, box, box) if isinstance(box, int) else box
     _check(lib.bs_gs_order_rows(plan.handle, int(mx), int(my), int(mz), int(tile), int(bx), int(by), int(bz),
                                 _stream(stream)), "bs_gs_order_rows")
+
+
+def bs_gs_order_elements(plan, nodes_per_element, elem_rank=None, group=1, stream=None):
+    """Gather rows and scatter tiles grouped by elements: elem_rank (int32 device tensor, one visiting
+    rank per element) or, when None, an order the library derives from the map's connectivity;
+    `group` elements of consecutive ranks are visited together."""
+    import torch
+    if elem_rank is not None:
+        if elem_rank.dtype != torch.int32 or elem_rank.numel() != plan.n_local // int(nodes_per_element):
+            raise ValueError("bs_gs_order_elements: elem_rank must be int32 with one entry per element")
+    _check(lib.bs_gs_order_elements(plan.handle, int(nodes_per_element), _ptr(elem_rank, plan.device), int(group),
+                                    _stream(stream)), "bs_gs_order_elements")
 
 
 def bs_gs_weights(plan, wL, stream=None):

@@ -37,7 +37,7 @@ LIBS = {
     os.path.join(PKG, "libbs.so"): [
         os.path.join(PKG, "csrc", f)
         for f in ("bs_host.hip", "bs_stream.hip", "bs_mesh.hip", "bs_plan.hip", "bs_gs.hip", "bs_cg.hip", "bs_batch.hip",
-                  "bs_elem.hip", "bs_prim.hip")
+                  "bs_elem.hip", "bs_prim.hip", "bs_order.hip")
     ],
     os.path.join(ROOT, "bsgen", "libbsgen.so"): [os.path.join(ROOT, "bsgen", "csrc", "bsgen.hip")],
 }

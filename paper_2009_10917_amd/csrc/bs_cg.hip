@@ -41,11 +41,18 @@ namespace bs {
 namespace {
 
 using namespace ops;
+using stencil::cg_alpha;
+using stencil::cg_beta;
+using stencil::CgLink;
 using stencil::CgState;
 using stencil::Op7;
 using stencil::store_partial;
 
 constexpr int kBatch = 16;  // iterations per captured graph (even)
+// Workgroups of the update and direction kernels (grid-stride): every
+// workgroup of the next kernel adds their partial sums, so they stay few.
+constexpr int kUpdateBlocks = 1024;
+constexpr int kDirectionBlocks = 2048;
 
 // Storage types whose CG folds the direction update into the operator.
 template <class T>
@@ -60,13 +67,6 @@ template <> struct DtypeOf<dev::bf16> { static constexpr bs_dtype v = BS_BF16; }
 template <class T>
 constexpr bs_dtype dtype_of() {
   return DtypeOf<T>::v;
-}
-
-__device__ __forceinline__ double sum_partials(const double* partials, int G) {
-  DW<double> r{0.0, 0.0};
-  for (int i = threadIdx.x; i < G; i += kFinishBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
-  r = dev::block_reduce<kFinishBlock>(r);
-  return r.s + r.c;  // valid in thread 0
 }
 
 template <class T>
@@ -84,63 +84,42 @@ bs_status launch_stencil(int64_t m, double shift, const void* x, void* y, hipStr
 
 __global__ void k_cg_init(CgState* st, const double* rr, double stop_rr, int32_t max_iters) {
   if (threadIdx.x == 0) {
-    st->rr = *rr;
+    st->rr_slot[0] = st->rr_slot[1] = st->rr = *rr;
     st->stop_rr = stop_rr;
     st->iters = 0;
     st->max_iters = max_iters;
+    st->fresh = 1;
     st->done = (*rr <= stop_rr || max_iters <= 0) ? 1 : 0;
     st->alpha = st->beta = st->pAp = 0.0;
   }
 }
 
-__global__ __launch_bounds__(kFinishBlock) void k_after_pAp(const double* __restrict__ partials, int G,
-                                                             CgState* st) {
-  if (st->done) return;
-  const double pAp = sum_partials(partials, G);
-  if (threadIdx.x == 0) {
-    st->pAp = pAp;
-    if (pAp > 0.0) {
-      st->alpha = st->rr / pAp;
-    } else {
-      st->done = 2;  // A is not positive definite on p (or p vanished)
-    }
-  }
-}
-
-__global__ __launch_bounds__(kFinishBlock) void k_after_update(const double* __restrict__ partials, int G,
-                                                                CgState* st) {
-  if (st->done) return;
-  const double rr_new = sum_partials(partials, G);
-  if (threadIdx.x == 0) {
-    st->beta = rr_new / st->rr;
-    st->rr = rr_new;
-    st->iters += 1;
-    if (!__builtin_isfinite(rr_new))
-      st->done = 2;  // overflow or NaN: further iterations cannot recover
-    else if (rr_new <= st->stop_rr || st->iters >= st->max_iters)
-      st->done = 1;
-  }
-}
-
+// x += alpha p, r -= alpha Ap and the partial sums of r.r, with alpha =
+// r.r / p.Ap formed at the head from the operator's partial sums.
 template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_cg_step(const CgState* st, typename Storage<T>::E* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums, typename Storage<T>::E* __restrict__ x,
                                                     const typename Storage<T>::E* __restrict__ p,
                                                     typename Storage<T>::E* __restrict__ r,
                                                     const typename Storage<T>::E* __restrict__ Ap, Span sp,
                                                     double* partials) {
   using C = typename Storage<T>::C;
-  if (st->done) return;
-  CgOp<T, V, false> op{{}, static_cast<C>(st->alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
+  double alpha = 0.0;
+  if (!cg_alpha(st, op_sums, &alpha)) return;
+  CgOp<T, V, false> op{{}, static_cast<C>(alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
   store_partial(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials);
 }
 
+// p = r + beta p, with beta = r'.r' / r.r formed at the head from the
+// update's partial sums (and the stopping test).
 template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_direction(const CgState* st, const typename Storage<T>::E* __restrict__ r,
+__global__ __launch_bounds__(kBlock) void k_direction(CgState* st, CgLink upd_sums,
+                                                      const typename Storage<T>::E* __restrict__ r,
                                                       typename Storage<T>::E* __restrict__ p, Span sp) {
   using C = typename Storage<T>::C;
-  if (st->done) return;
-  AxpyOp<T, V> op{{}, C(1), static_cast<C>(st->beta), r, p, sp.head};
+  double beta = 0.0;
+  if (!cg_beta(st, upd_sums, &beta)) return;
+  AxpyOp<T, V> op{{}, C(1), static_cast<C>(beta), r, p, sp.head};
   stream_loop<U>(op, sp);
 }
 
@@ -226,24 +205,29 @@ struct CgEngine {
     if (exec) (void)hipGraphExecDestroy(exec);
   }
 
+  // The operator's partial sums (p.Ap) go to the first kMaxReduceBlocks
+  // pairs of the context's buffer, the update's (r.r) to the next ones.
+  double* op_partials() const { return ctx->partials; }
+  double* upd_partials() const { return ctx->partials + 2 * static_cast<size_t>(kMaxReduceBlocks); }
+
   void enqueue_iteration(int parity) {
     E* p_old = (kFuse && parity) ? p2 : p;
     E* p_cur = kFuse ? (parity ? p : p2) : p;
-    op.enqueue(st, shift, p_old, r, p_cur, Ap, ctx->partials, state);
-    hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, static_cast<int>(op.blocks),
-                       state);
+    const CgLink from_update{upd_partials(), g_upd, parity};  // the direction of this iteration
+    const CgLink from_op{op_partials(), static_cast<int32_t>(op.blocks), parity};
+    op.enqueue(st, shift, p_old, r, p_cur, Ap, op_partials(), state, from_update);
     if (sp.vwidth == 1)
-      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p_cur, r, Ap, sp,
-                         ctx->partials);
+      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r, Ap, sp,
+                         upd_partials());
     else
-      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, x, p_cur, r, Ap, sp,
-                         ctx->partials);
-    hipLaunchKernelGGL(k_after_update, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g_upd, state);
+      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r, Ap,
+                         sp, upd_partials());
     if constexpr (!kFuse) {
+      const CgLink next{upd_partials(), g_upd, parity ^ 1};  // the direction of the next iteration
       if (sp.vwidth == 1)
-        hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+        hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, next, r, p, sp);
       else
-        hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, r, p, sp);
+        hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, next, r, p, sp);
     }
   }
 
@@ -251,8 +235,8 @@ struct CgEngine {
     sp = make_span<T>(n, {x, r, p, p2, Ap});
     if (!op.prepare(m, ctx->device))
       return fail(BS_ERR_INVALID_ARG, "cg: grid side %lld is too large", static_cast<long long>(m));
-    g_upd = grid_for(sp, 4, kMaxReduceBlocks);
-    g_dir = grid_for(sp, 1, 1 << 30);
+    g_upd = grid_for(sp, 4, kUpdateBlocks);
+    g_dir = grid_for(sp, 1, kDirectionBlocks);
     // capture kBatch iterations into one graph
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager fallback

@@ -251,6 +251,17 @@ __device__ __forceinline__ void operand(const double* __restrict__ tab, int whic
   for (int h = 0; h < KC; ++h) a[h] = tab[which * kTabSize + (l & 15) * 16 + 4 * h + (l >> 4)];
 }
 
+// Each element's tensor lives in its wave's own LDS buffers, so only the
+// lanes of one wave exchange data between contractions: a wave's LDS
+// operations are performed in order, and the fences and the wave barrier keep
+// the compiler from moving them across this point (the waves of a workgroup
+// never wait for one another).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wave per element; four elements per workgroup.  map/xG give the
 // element's values (the fused scatter), yL receives A^e u.
 __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
@@ -296,22 +307,22 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
     const double* q = geo + 7 * e;
     g = Geo{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
   }
-  __syncthreads();
+  wave_sync();
   dvec4 acc[4];
   // U = (B, B, B) u and G1 = (B, B, D) u: along k, along j, then [B; D] along i
   zero(acc);
   contract<2, 2>(b0, aB, acc);
   store_rows<2>(b1, acc, 0);
-  __syncthreads();
+  wave_sync();
   zero(acc);
   contract<1, 2>(b1, aB, acc);
   store_rows<1>(b0, acc, 0);
-  __syncthreads();
+  wave_sync();
   zero(acc);
   contract<0, 2>(b0, aBD, acc);
   store_rows<0>(b1, acc, 0);  // U
   store_rows<0>(b2, acc, 8);  // G1
-  __syncthreads();
+  wave_sync();
   // G2 = Dh along j of U, G3 = Dh along k of U
   zero(acc);
   contract<1, 2>(b1, aDh, acc);
@@ -319,7 +330,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
   zero(acc);
   contract<2, 2>(b1, aDh, acc);
   store_rows<2>(b3, acc, 0);
-  __syncthreads();
+  wave_sync();
   // quadrature-point values: V0 (b1), V1 (b2), V2 (b0), V3 (b3), in place
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -332,18 +343,18 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
     b0[ad] = W * ((g.g12 * d1 + g.g22 * d2) + g.g23 * d3);
     b3[ad] = W * ((g.g13 * d1 + g.g23 * d2) + g.g33 * d3);
   }
-  __syncthreads();
+  wave_sync();
   // W1 = V0 + Dh_k^T V3, then W2 = W1 + Dh_j^T V2 (accumulated in place in b1)
   load_rows<2>(b1, acc);
   contract<2, 2>(b3, aDhT, acc);
-  __syncthreads();
+  wave_sync();
   store_rows<2>(b1, acc, 0);
-  __syncthreads();
+  wave_sync();
   load_rows<1>(b1, acc);
   contract<1, 2>(b0, aDhT, acc);
-  __syncthreads();
+  wave_sync();
   store_rows<1>(b1, acc, 0);
-  __syncthreads();
+  wave_sync();
   // Y3 = B^T W2 + D^T V1 along i (K = 16: W2 then V1)
   zero(acc);
   {
@@ -352,11 +363,11 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
     contract<0, 2>(b2, hi, acc);
   }
   store_rows<0>(b0, acc, 0);
-  __syncthreads();
+  wave_sync();
   zero(acc);
   contract<1, 2>(b0, aBt, acc);
   store_rows<1>(b3, acc, 0);
-  __syncthreads();
+  wave_sync();
   zero(acc);
   contract<2, 2>(b3, aBt, acc);
   // y along k: register v < 2 of lane l holds node k = l/16 + 4v at

@@ -10,10 +10,12 @@
 // whole rows from LDS.  The window start is known from the block index, so
 // the column-id and value loads are issued at once rather than after the
 // row starts arrive.
-//   0  rows in visiting order: rows grouped by the first visited scatter
-//      tile that holds one of their copies, so that a row's copies lie in
-//      tiles whose cache lines are still in L2 (the default; needs every
-//      degree to fit in a byte, otherwise kernel 1 runs)
+//   0  rows in the plan's permuted order: by default in groups of 9
+//      consecutive scatter tiles of the visiting order (each row in the
+//      first group holding one of its copies, ascending global id within a
+//      group), so that a row's copies lie in tiles whose cache lines are
+//      still in L2 and x_G is written in runs (needs every degree to fit in
+//      a byte, otherwise kernel 1 runs)
 //   1  rows in global order
 //   2  fixed blocks of 256 rows in global order
 //

@@ -130,9 +130,10 @@ struct bs_gs {
   int32_t* tile_count;   // [n_tiles]
   int64_t n_tiles;
 
-  // Gather, rows in a permuted order: by default grouped by the first tile
-  // (in tile_order) that holds one of their copies, or in lattice blocks
-  // (bs_gs_order_rows); perm_rows lists rows with copies first, then rows
+  // Gather, rows in a permuted order: by default in groups of consecutive
+  // tiles of tile_order (each row in the first group holding one of its
+  // copies), or in lattice blocks (bs_gs_order_rows), or by element groups
+  // (bs_gs_order_elements); perm_rows lists rows with copies first, then rows
   // without copies.  Nonzero-balanced blocks as above: block b adds rows
   // [perm_bstart[b], perm_bstart[b+1]), whose nonzeros are the CSR positions
   // [perm_bnz0[b], perm_bnz0[b+1]) (at most kStage of them, since chunk +

@@ -9,20 +9,33 @@
 //   scatter tiles     tiles of kTile local entries, visited in order of the
 //                     smallest global id each references; inside a tile the
 //                     entries sorted by global id (bitonic sort in LDS)
-//   gather order      rows grouped by the first visited tile holding one of
-//                     their copies, as a permuted CSR with byte degrees
+//   gather order      rows in groups of kRowGroupTiles consecutive visited
+//                     tiles (each row in the first group holding one of its
+//                     copies, ascending global id within a group), as a
+//                     permuted CSR with byte degrees
 //
 // The last two are orderings of work only: no vector is renumbered, and the
 // results of gather and scatter are the same bits whichever order is used.
 
+#include <new>
+#include <string>
+#include <vector>
+
 #include "bs_device.h"
 #include "bs_internal.h"
+#include "bs_order.h"
 #include "bs_prim.h"
 
 namespace bs {
 namespace {
 
 inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n + kBlock - 1) / kBlock); }
+
+constexpr int64_t kOrderLeaf = 16;  // elements per part where the bisection of the element graph stops
+// Default gather order: rows keyed by groups of this many consecutive tiles
+// of the scatter's visiting order (tiles sorted by their smallest global id),
+// rows of a group in ascending global id.
+constexpr int32_t kRowGroupTiles = 9;
 
 // Device memory owned until released.
 struct DevBuf {
@@ -217,13 +230,53 @@ __global__ __launch_bounds__(kBlock) void k_invert(const int32_t* __restrict__ o
   if (i < n) rank[order[i]] = static_cast<int32_t>(i);
 }
 
-// key[g] = smallest visiting rank of a tile holding a copy of row g.
+// key[g] = smallest group (visiting rank / group) of a tile holding a copy
+// of row g.
 __global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t* __restrict__ map, int64_t n_local,
-                                                     const int32_t* __restrict__ tile_rank, uint32_t* __restrict__ key) {
+                                                     const int32_t* __restrict__ tile_rank, int32_t group,
+                                                     uint32_t* __restrict__ key) {
   const int64_t l = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (l >= n_local) return;
   const int32_t g = map[l];
-  if (g >= 0) atomicMin(&key[g], static_cast<uint32_t>(tile_rank[l / kTile]));
+  if (g >= 0) atomicMin(&key[g], static_cast<uint32_t>(tile_rank[l / kTile] / group));
+}
+
+// key[t] = smallest group of an element overlapping tile t (local entries
+// [t kTile, (t + 1) kTile) of n_local).
+__global__ __launch_bounds__(kBlock) void k_tile_elem_keys(int64_t n_tiles, int64_t n_local, int64_t P,
+                                                           const int32_t* __restrict__ elem_rank, int64_t group,
+                                                           uint32_t* __restrict__ key) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t l0 = t * kTile;
+  const int64_t l1 = (l0 + kTile < n_local ? l0 + kTile : n_local) - 1;
+  uint32_t k = 0xffffffffu;
+  for (int64_t e = l0 / P; e <= l1 / P; ++e) k = min(k, static_cast<uint32_t>(elem_rank[e] / group));
+  key[t] = k;
+}
+
+// key[g] = smallest group (visiting rank / group) of an element holding a
+// copy of row g (elements: runs of P consecutive local entries).
+__global__ __launch_bounds__(kBlock) void k_elem_row_keys(const int32_t* __restrict__ map, int64_t n_local, int64_t P,
+                                                          const int32_t* __restrict__ elem_rank, int64_t group,
+                                                          uint32_t* __restrict__ key) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (l >= n_local) return;
+  const int32_t g = map[l];
+  if (g >= 0) atomicMin(&key[g], static_cast<uint32_t>(elem_rank[l / P] / group));
+}
+
+// The 8 corner ids of each element of degree N: corner c is local node
+// N * (c & 1, (c >> 1) & 1, c >> 2) (local index i + (N+1)(j + (N+1) k)).
+__global__ __launch_bounds__(kBlock) void k_elem_corners(const int32_t* __restrict__ map, int64_t n_elem, int N,
+                                                         int32_t* __restrict__ corners) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= n_elem * 8) return;
+  const int64_t e = t >> 3;
+  const int c = static_cast<int>(t & 7);
+  const int64_t P1 = N + 1;
+  const int64_t off = N * ((c & 1) + P1 * (((c >> 1) & 1) + P1 * (c >> 2)));
+  corners[t] = map[e * P1 * P1 * P1 + off];
 }
 
 // Row keys of a lattice-tiled order: global id g is lattice point
@@ -566,8 +619,17 @@ void build_gather_blocks(Builder& B, bs_gs* gs) {
   if (B.ok()) gs->block_starts = bstart.release<int32_t>();
 }
 
-// Sorted tiles and their visiting order.
-void build_scatter_tiles(Builder& B, bs_gs* gs) {
+// Element visiting ranks for a gather or scatter order (elements: runs of P
+// local entries).
+struct ElementOrder {
+  const int32_t* rank;  // device, [n_local / P]
+  int64_t P;
+  int64_t group;  // elements of consecutive ranks visited as one group
+};
+
+// Sorted tiles and their visiting order: by the smallest global id of each
+// tile, or (eo) by the smallest rank of an element the tile overlaps.
+void build_scatter_tiles(Builder& B, bs_gs* gs, const ElementOrder* eo = nullptr) {
   const int64_t nt = (gs->n_local + kTile - 1) / kTile;
   gs->n_tiles = nt;
   DevBuf tgid, tloc, tcnt, order, tkey, tkey_out, tidx, tword, tmin, wide, vcnt, vmin, vword, vgid, vloc;
@@ -587,6 +649,9 @@ void build_scatter_tiles(Builder& B, bs_gs* gs) {
     hipLaunchKernelGGL(k_tile_sort, dim3(static_cast<unsigned int>(nt)), dim3(kBlock), 0, B.st, gs->map, gs->n_local,
                        tkey.as<uint32_t>(), tidx.as<int32_t>(), tgid.as<int32_t>(), tloc.as<uint16_t>(),
                        tcnt.as<int32_t>(), tword.as<uint32_t>(), tmin.as<int32_t>(), wide.as<int>());
+    if (eo)
+      hipLaunchKernelGGL(k_tile_elem_keys, dim3(blocks_for(nt)), dim3(kBlock), 0, B.st, nt, gs->n_local, eo->P,
+                         eo->rank, eo->group, tkey.as<uint32_t>());
     B.launched();
     uint32_t* k0 = tkey.as<uint32_t>();
     uint32_t* k1 = tkey_out.as<uint32_t>();
@@ -633,8 +698,10 @@ struct LatticeOrder {
 };
 
 // Rows with copies in a permuted order and the CSR in that order: by default
-// the visiting order of the scatter tiles, or (lat) lattice tiles.
-void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const LatticeOrder* lat = nullptr) {
+// the visiting order of the scatter tiles, or (lat) lattice tiles, or (eo)
+// the first visited element holding a copy.
+void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const LatticeOrder* lat = nullptr,
+                        const ElementOrder* eo = nullptr) {
   gs->has_perm = false;
   // a window (chunk + max_degree - 1 entries) must fit the stage, whose offsets take 11 bits
   if (gs->max_degree > kStage / 2) return;
@@ -652,7 +719,13 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
   B.need(pcols, gs->n_unmasked * 4, "columns");
   if (!B.ok()) return;
   if (ng > 0) hipLaunchKernelGGL(k_iota, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rows0.as<int32_t>(), ng);
-  if (lat) {
+  if (eo) {
+    if (ng > 0)
+      hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
+    if (nl > 0)
+      hipLaunchKernelGGL(k_elem_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, eo->P, eo->rank,
+                         eo->group, rkey.as<uint32_t>());
+  } else if (lat) {
     const int64_t ntx = (lat->mx + lat->tile - 1) / lat->tile, nty = (lat->my + lat->tile - 1) / lat->tile;
     const int64_t nbx = (lat->tile + lat->bx - 1) / lat->bx, nby = (lat->tile + lat->by - 1) / lat->by,
                   nbz = (lat->tile + lat->bz - 1) / lat->bz;
@@ -666,7 +739,7 @@ void build_gather_order(Builder& B, bs_gs* gs, int64_t n_zero_rows, const Lattic
       hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(ng)), dim3(kBlock), 0, B.st, rkey.as<int32_t>(), ng, -1);
     if (nl > 0)
       hipLaunchKernelGGL(k_row_keys, dim3(blocks_for(nl)), dim3(kBlock), 0, B.st, gs->map, nl, rank.as<int32_t>(),
-                         rkey.as<uint32_t>());
+                         kRowGroupTiles, rkey.as<uint32_t>());
   }
   B.launched();
   if (ng > 0) {
@@ -853,6 +926,105 @@ extern "C" bs_status bs_gs_order_rows(bs_gs* gs, int64_t mx, int64_t my, int64_t
       (void)hipFree(q);
   } else {
     gs->has_perm = true;  // the previous order is still in place
+  }
+  (void)hipSetDevice(prev);
+  return B.s;
+}
+
+extern "C" bs_status bs_gs_order_elements(bs_gs* gs, int64_t nodes_per_element, const int32_t* d_elem_rank,
+                                          int64_t elements_per_group, void* stream) {
+  const char* op = "bs_gs_order_elements";
+  if (!gs) return fail(BS_ERR_INVALID_ARG, "%s: plan is NULL", op);
+  const int64_t P = nodes_per_element;
+  if (P < 1 || gs->n_local % P != 0)
+    return fail(BS_ERR_INVALID_ARG, "%s: n_local must be a multiple of nodes_per_element >= 1", op);
+  if (elements_per_group < 1 || elements_per_group > 2147483647LL)
+    return fail(BS_ERR_INVALID_ARG, "%s: elements_per_group must lie in [1, 2^31)", op);
+  if (d_elem_rank && !aligned_to(d_elem_rank, 4))
+    return fail(BS_ERR_INVALID_ARG, "%s: d_elem_rank is not 4-byte aligned", op);
+  int N = 0;
+  if (!d_elem_rank) {
+    while (static_cast<int64_t>(N + 1) * (N + 1) * (N + 1) < P) ++N;
+    if (static_cast<int64_t>(N + 1) * (N + 1) * (N + 1) != P || N < 1)
+      return fail(BS_ERR_INVALID_ARG, "%s: nodes_per_element must be (N+1)^3 with N >= 1 to derive an order", op);
+  }
+  if (!gs->has_perm) return fail(BS_ERR_UNSUPPORTED, "%s: the plan has no permuted order (a degree exceeds 1024)", op);
+  const int64_t n_elem = gs->n_local / P;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(gs->device);
+  Builder B{op, static_cast<hipStream_t>(stream)};
+  DevBuf rank_buf;
+  const int32_t* rank = d_elem_rank;
+  if (!d_elem_rank) {
+    // corners to the host, the bisection order, ranks back to the device
+    DevBuf cbuf;
+    B.need(cbuf, static_cast<size_t>(n_elem) * 8 * 4, "element corners");
+    B.need(rank_buf, static_cast<size_t>(n_elem) * 4, "element ranks");
+    std::vector<int32_t> corners, hrank;
+    std::string err;
+    if (B.ok() && n_elem > 0) {
+      hipLaunchKernelGGL(k_elem_corners, dim3(blocks_for(n_elem * 8)), dim3(kBlock), 0, B.st, gs->map, n_elem, N,
+                         cbuf.as<int32_t>());
+      B.launched();
+      try {
+        corners.resize(static_cast<size_t>(n_elem) * 8);
+      } catch (const std::bad_alloc&) {
+        B.s = fail(BS_ERR_ALLOC, "%s: cannot allocate %lld host corner ids", op, static_cast<long long>(n_elem * 8));
+      }
+      B.hip(hipMemcpyAsync(corners.data(), cbuf.p, corners.size() * 4, hipMemcpyDeviceToHost, B.st));
+      B.hip(hipStreamSynchronize(B.st));
+      if (B.ok() && !element_order_bisection(corners.data(), n_elem, kOrderLeaf, hrank, err))
+        B.s = fail(BS_ERR_ALLOC, "%s: %s", op, err.c_str());
+      B.hip(hipMemcpyAsync(rank_buf.p, hrank.data(), hrank.size() * 4, hipMemcpyHostToDevice, B.st));
+      B.hip(hipStreamSynchronize(B.st));
+    }
+    rank = rank_buf.as<int32_t>();
+  }
+  if (!B.ok()) {
+    (void)hipSetDevice(prev);
+    return B.s;
+  }
+  int32_t* old_rows = gs->perm_rows;
+  uint32_t* old_words = gs->perm_words;
+  int32_t* old_segs = gs->perm_segs;
+  int32_t* old_segoff = gs->perm_segoff;
+  int32_t* old_runoff = gs->perm_runoff;
+  int32_t* old_runs = gs->perm_runs;
+  int32_t* old_bstart = gs->perm_bstart;
+  int32_t* old_bnz0 = gs->perm_bnz0;
+  const int64_t zero_rows = gs->n_global - gs->n_nzrows;
+  const ElementOrder eo{rank, P, elements_per_group};
+  build_gather_order(B, gs, zero_rows, nullptr, &eo);
+  if (B.ok()) {
+    for (void* q : {static_cast<void*>(old_rows), static_cast<void*>(old_words), static_cast<void*>(old_segs),
+                    static_cast<void*>(old_segoff), static_cast<void*>(old_runoff), static_cast<void*>(old_runs),
+                    static_cast<void*>(old_bstart), static_cast<void*>(old_bnz0)})
+      (void)hipFree(q);
+  } else {
+    gs->has_perm = true;  // the previous order is still in place
+    (void)hipSetDevice(prev);
+    return B.s;
+  }
+  // the scatter's tiles in the same element order
+  bs_gs old = *gs;
+  gs->tile_order = gs->tile_gid = gs->tile_min = gs->tile_count = nullptr;
+  gs->tile_loc = nullptr;
+  gs->tile_word = nullptr;
+  build_scatter_tiles(B, gs, &eo);
+  if (B.ok()) {
+    for (void* q : {static_cast<void*>(old.tile_order), static_cast<void*>(old.tile_gid),
+                    static_cast<void*>(old.tile_loc), static_cast<void*>(old.tile_word),
+                    static_cast<void*>(old.tile_min), static_cast<void*>(old.tile_count)})
+      (void)hipFree(q);
+  } else {
+    gs->tile_order = old.tile_order;
+    gs->tile_gid = old.tile_gid;
+    gs->tile_loc = old.tile_loc;
+    gs->tile_word = old.tile_word;
+    gs->tile_min = old.tile_min;
+    gs->tile_count = old.tile_count;
+    gs->tile_packed = old.tile_packed;
   }
   (void)hipSetDevice(prev);
   return B.s;

@@ -30,18 +30,110 @@ namespace stencil {
 using dev::DW;
 using dev::Storage;
 
-// Scalars of a CG solve, kept on the device.
+// Scalars of a CG solve, kept on the device.  The kernels of an iteration
+// compute the scalars they need from the previous kernel's partial sums
+// (each workgroup adds them itself, in one fixed order, so all get the same
+// bits); the values an iteration writes go to the slot of its parity, so
+// that no kernel reads a field that another workgroup of the same kernel
+// writes (done aside: it only ever changes from 0, every workgroup takes the
+// same decision, and it is read and written atomically).
 struct CgState {
-  double rr;       // r.r of the current residual
-  double pAp;      // p.Ap of the current direction
+  double rr_slot[2];  // r.r at the start of the iterations of parity 0 and 1
+  double rr;          // the latest r.r (for the host)
+  double pAp;         // p.Ap of the latest direction
   double alpha;
-  double beta;     // applied to p by the next operator application
-  double stop_rr;  // iterate while rr > stop_rr
-  int32_t done;    // 0 running, 1 converged or out of iterations, 2 breakdown
-  int32_t iters;
+  double beta;
+  double stop_rr;     // iterate while rr > stop_rr
+  int32_t done;       // 0 running, 1 converged or out of iterations, 2 breakdown
+  int32_t iters;      // completed updates, written by the update kernel only
   int32_t max_iters;
-  int32_t pad;
+  int32_t fresh;      // 1 until the first update of a run (its direction is p = r)
 };
+
+// Where a kernel finds the partial sums of the previous one: G compensated
+// pairs, and the parity slot it reads or writes.
+struct CgLink {
+  const double* partials;
+  int32_t G;
+  int32_t slot;
+};
+
+// The sum of G compensated pairs added in index order per thread and then
+// across the workgroup (the same order in every workgroup), and the done
+// flag as thread 0 read it, both given to every thread.
+struct Bcast {
+  double v;
+  int32_t done;
+};
+
+__device__ __forceinline__ Bcast block_sum_bcast(const double* __restrict__ partials, int G, const int32_t* done) {
+  __shared__ double s_v;
+  __shared__ int32_t s_done;
+  DW<double> r{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  r = dev::block_reduce<kBlock>(r);
+  if (threadIdx.x == 0) {
+    s_v = r.s + r.c;
+    s_done = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return Bcast{s_v, s_done};
+}
+
+__device__ __forceinline__ void set_done(CgState* st, int32_t v) {
+  __hip_atomic_store(&st->done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Algorithm 1 step 10 and the stopping test, at the head of the kernel that
+// forms the next direction: r'.r' from the update's partial sums, beta =
+// r'.r' / r.r (0 for the first direction of a run).  Returns false when the
+// solve is over; every thread of a workgroup returns the same.
+__device__ __forceinline__ bool cg_beta(CgState* st, CgLink in, double* beta) {
+  const Bcast b = block_sum_bcast(in.partials, in.G, &st->done);
+  if (b.done) return false;
+  if (st->fresh) {
+    *beta = 0.0;
+    return true;
+  }
+  const double rr_new = b.v, rr_old = st->rr_slot[in.slot ^ 1];
+  int32_t done = 0;
+  if (!__builtin_isfinite(rr_new))
+    done = 2;  // overflow or NaN: further iterations cannot recover
+  else if (rr_new <= st->stop_rr || st->iters >= st->max_iters)
+    done = 1;
+  const double bt = rr_new / rr_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr_slot[in.slot] = rr_new;
+    st->rr = rr_new;
+    st->beta = bt;
+    if (done) set_done(st, done);
+  }
+  *beta = bt;
+  return done == 0;
+}
+
+// Algorithm 1 step 7 at the head of the update kernel: p.Ap from the
+// operator's partial sums, alpha = r.r / p.Ap.  Returns false when the solve
+// is over or p.Ap is not positive (breakdown).
+__device__ __forceinline__ bool cg_alpha(CgState* st, CgLink in, double* alpha) {
+  const Bcast b = block_sum_bcast(in.partials, in.G, &st->done);
+  if (b.done) return false;
+  const double pAp = b.v;
+  const bool ok = pAp > 0.0;  // A is positive definite on p unless p vanished
+  const double a = st->rr_slot[in.slot] / pAp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pAp = pAp;
+    if (ok) {
+      st->alpha = a;
+      st->iters += 1;
+      st->fresh = 0;
+    } else {
+      set_done(st, 2);
+    }
+  }
+  *alpha = a;
+  return ok;
+}
 
 // Values the operator is applied to: the stored p, or (DIR) the new
 // direction r + beta p rounded to storage exactly as an AXPY rounds it.
@@ -263,13 +355,18 @@ __global__ __launch_bounds__(kBlock) void k_plane7(Plan7 pl, typename Storage<T>
                                                    const typename Storage<T>::E* __restrict__ r,
                                                    typename Storage<T>::E* __restrict__ p_new,
                                                    typename Storage<T>::E* __restrict__ y, double* partials,
-                                                   const CgState* st) {
+                                                   CgState* st, CgLink link) {
   using St = Storage<T>;
   using C = typename St::C;
   using E = typename St::E;
   extern __shared__ __align__(16) unsigned char plane_lds[];
-  if (st && st->done) return;
-  const Source<T, DIR> src{p, r, DIR ? static_cast<C>(st->beta) : C(0)};
+  double beta = 0.0;
+  if constexpr (DIR) {
+    if (!cg_beta(st, link, &beta)) return;
+  } else {
+    if (st && st->done) return;
+  }
+  const Source<T, DIR> src{p, r, static_cast<C>(beta)};
   const int32_t m = pl.m;
   const int64_t plane = static_cast<int64_t>(m) * m;
   const uint32_t b = dev::xcd_block(blockIdx.x, gridDim.x);
@@ -324,12 +421,17 @@ __global__ __launch_bounds__(kBlock) void k_march7(March gm, typename Storage<T>
                                                    const typename Storage<T>::E* __restrict__ r,
                                                    typename Storage<T>::E* __restrict__ p_new,
                                                    typename Storage<T>::E* __restrict__ y, double* partials,
-                                                   const CgState* st) {
+                                                   CgState* st, CgLink link) {
   using St = Storage<T>;
   using C = typename St::C;
   using E = typename St::E;
-  if (st && st->done) return;
-  const Source<T, DIR> src{p, r, DIR ? static_cast<C>(st->beta) : C(0)};
+  double beta = 0.0;
+  if constexpr (DIR) {
+    if (!cg_beta(st, link, &beta)) return;
+  } else {
+    if (st && st->done) return;
+  }
+  const Source<T, DIR> src{p, r, static_cast<C>(beta)};
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t w = static_cast<int64_t>(dev::xcd_block(blockIdx.x, gridDim.x)) * 4 + wave;
   const int32_t m = gm.m;
@@ -456,24 +558,24 @@ struct Op7 {
   }
 
   void enqueue(hipStream_t st, double shift, const E* p, const E* r, E* p_new, E* y, double* partials,
-               const CgState* cs) const {
+               CgState* cs, CgLink link = CgLink{nullptr, 0, 0}) const {
     const C c = static_cast<C>(6.0 + shift);
     switch (kind) {
       case 0:
         hipLaunchKernelGGL((k_plane7<T, DOT, DIR, S, 2, D>), dim3(blocks), dim3(kBlock), lds, st, plan, c, p, r, p_new,
-                           y, partials, cs);
+                           y, partials, cs, link);
         break;
       case 1:
         hipLaunchKernelGGL((k_plane7<T, DOT, DIR, S, 4, D>), dim3(blocks), dim3(kBlock), lds, st, plan, c, p, r, p_new,
-                           y, partials, cs);
+                           y, partials, cs, link);
         break;
       case 2:
         hipLaunchKernelGGL((k_plane7<T, DOT, DIR, S, 12, D>), dim3(blocks), dim3(kBlock), lds, st, plan, c, p, r,
-                           p_new, y, partials, cs);
+                           p_new, y, partials, cs, link);
         break;
       default:
         hipLaunchKernelGGL((k_march7<T, DOT, DIR>), dim3(blocks), dim3(kBlock), 0, st, march, c, p, r, p_new, y,
-                           partials, cs);
+                           partials, cs, link);
         break;
     }
   }

@@ -156,10 +156,16 @@ def test_full_size_fp64_and_mixed(ctx):
     r64 = bs.bs_cg_solve(ctx, m, SHIFT, db, x64, tol=1e-10)
     x32 = torch.zeros_like(x64)
     r32 = bs.bs_cg_ir_solve(ctx, bs.BS_F32, m, SHIFT, db, x32, tol=1e-10, inner_tol=1e-4)
-    a, c = to_host(x64), to_host(x32)
-    assert true_relres(a, b, m) <= 1e-10 and true_relres(c, b, m) <= 1e-10
+    x16 = torch.zeros_like(x64)
+    r16 = bs.bs_cg_ir_solve(ctx, bs.BS_BF16, m, SHIFT, db, x16, tol=1e-10, inner_tol=0.1, max_outer=60)
+    assert r16["status"] == "BS_OK"
+    a, c, d = to_host(x64), to_host(x32), to_host(x16)
+    # true residuals recomputed by the oracle's operator from the library's x
+    assert true_relres(a, b, m) <= 1e-10 and true_relres(c, b, m) <= 1e-10 and true_relres(d, b, m) <= 1e-10
     kappa = cg.eigenvalue(m, SHIFT, m, m, m) / cg.eigenvalue(m, SHIFT, 1, 1, 1)
     assert np.linalg.norm(a - c) <= kappa * 2e-10 * np.linalg.norm(a)
+    assert np.linalg.norm(a - d) <= kappa * 2e-10 * np.linalg.norm(a)
+    assert r16["outer_iterations"] >= 2 and r32["outer_iterations"] >= 2
     # Chebyshev bound on the A-norm error, turned into one on the residual
     # (a factor sqrt(kappa) between the two): a ceiling, not an estimate
     ceiling = math.sqrt(kappa) / 2 * math.log(2 * math.sqrt(kappa) / 1e-10)

@@ -369,3 +369,86 @@ def test_gather_lattice_order_masked_and_errors(ctx):
     bs.bs_gather(ctx, plan, xL, xG)
     rs, ci = mesh.csr_inverse(ids, NG)
     assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
+
+
+@pytest.mark.parametrize("remap", [0, 8])
+@pytest.mark.parametrize("K,N,seed,group", [(1, 1, None, 1), (3, 2, 2, 1), (4, 7, 3, 1), (6, 5, 5, 7), (8, 3, None, 64),
+                                            (5, 4, 7, 1000), (3, 15, 4, 2)])
+def test_gather_element_order_derived(ctx, K, N, seed, group, remap):
+    # the order derived from the map's connectivity changes which rows a
+    # workgroup adds, not how a row is summed
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ids = device_map(K, N, seed)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    bs.bs_gs_order_elements(plan, (N + 1) ** 3, None, group)
+    with_variant(ctx, 0 + remap)
+    xL = dev_uniform(NL, 11)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
+
+
+@pytest.mark.parametrize("ranks", ["reversed", "random", "constant"])
+def test_gather_element_order_given_and_masked(ctx, ranks):
+    K, N = 5, 4
+    E, NL, NG = mesh.sizes(K, N)
+    _, ids = device_map(K, N, 9)
+    ids = ids.copy()
+    ids[::7] = -1  # masked copies, masked corners; some rows lose every copy
+    ids[ids == 17] = -1
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ids.astype(np.int32)).cuda(), NG)
+    r = {"reversed": np.arange(E)[::-1], "random": bsgen.permutation(3, E),
+         "constant": np.zeros(E, dtype=np.int64)}[ranks]
+    bs.bs_gs_order_elements(plan, (N + 1) ** 3, torch.from_numpy(np.ascontiguousarray(r).astype(np.int32)).cuda(), 3)
+    rs, ci = mesh.csr_inverse(ids, NG)
+    for variant in (0, 8):
+        with_variant(ctx, variant)
+        xL = dev_uniform(NL, 11)
+        xG = torch.full((NG,), 7.0, dtype=torch.float64, device="cuda")
+        bs.bs_gather(ctx, plan, xL, xG)
+        assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
+    # the derived order copes with masked corners too
+    bs.bs_gs_order_elements(plan, (N + 1) ** 3)
+    with_variant(ctx, 0)
+    xL = dev_uniform(NL, 12)
+    xG = torch.empty(NG, dtype=torch.float64, device="cuda")
+    bs.bs_gather(ctx, plan, xL, xG)
+    assert np.array_equal(bits(to_host(xG)), bits(ops.gather(rs, ci, to_host(xL))))
+
+
+def test_gather_element_order_errors(ctx):
+    K, N = 3, 2
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, _ = device_map(K, N, 1)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_elements(plan, 0)
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_elements(plan, 26)  # not a divisor of n_local
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_elements(plan, 9)  # divides n_local but is not (N+1)^3: no order can be derived
+    with pytest.raises(ValueError):
+        bs.bs_gs_order_elements(plan, 27, torch.zeros(E + 1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(bs.BSError):
+        bs.bs_gs_order_elements(plan, 27, None, 0)
+
+
+@pytest.mark.parametrize("K,N,seed,given,group", [(4, 7, 3, False, 1), (5, 4, 7, True, 5), (3, 15, 4, False, 2),
+                                                  (6, 2, 2, True, 1), (6, 2, 2, False, 16)])
+def test_scatter_tiles_in_element_order(ctx, K, N, seed, given, group):
+    # the scatter visits its tiles in the element order too; same bits
+    E, NL, NG = mesh.sizes(K, N)
+    d_map, ids = device_map(K, N, seed)
+    plan = bs.bs_gs_create(ctx, d_map, NG)
+    r = torch.from_numpy(bsgen.permutation(seed + 1, E).astype(np.int32)).cuda() if given else None
+    bs.bs_gs_order_elements(plan, (N + 1) ** 3, r, group)
+    xG_h = host_uniform(NG, 12)
+    xL_h = host_uniform(NL, 11)
+    ref = ops.scatter(ids, xG_h, xL_h)
+    for variant in (0, 1, 2, 8):
+        for tpw in (1, 2, 4):
+            bs.bs_ctx_set_tune(ctx, "scatter", tpw, 1 << 30, variant)
+            xL = torch.from_numpy(xL_h.copy()).cuda()
+            bs.bs_gs_scatter(ctx, plan, torch.from_numpy(xG_h).cuda(), xL)
+            assert np.array_equal(bits(to_host(xL)), bits(ref)), (variant, tpw)
