@@ -930,11 +930,13 @@ def main():
 
     cg_gbs = per_op["cg_update"]["GB_s"]
     traffic = read_traffic(byt["cg_update"])
-    cu, cg_cap, corder = bs.bs_ctx_tune_for(ctx, "cg_update", n)
+    cu, cg_cap, cvar = bs.bs_ctx_tune_for(ctx, "cg_update", n)
     cu = 8 if cu >= 8 else 4 if cu >= 4 else 2 if cu >= 2 else 1
-    cg_grid = max(1, min(cg_cap, 1 << 21, -(-(n // 2) // (256 * cu))))
-    roofline = {"bound": "hbm", "kernel": f"k_cg_update<double, 2, {cu}, true>", "workgroups": cg_grid,
-                "workgroup_order": corder, "achieved": cg_gbs,
+    cnb = {1: 128, 2: 512}.get((cvar >> 2) & 3, 256)
+    corder = cvar & 3 if (cvar & 3) in (1, 2) else 0
+    cg_grid = max(1, min(cg_cap, 1 << 21, -(-(n // 2) // (cnb * cu))))
+    roofline = {"bound": "hbm", "kernel": f"k_cg_update<double, 2, {cu}, true, {cnb}>", "workgroups": cg_grid,
+                "workgroup_order": corder, "workgroup_size": cnb, "achieved": cg_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cg_gbs / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": byt["cg_update"],
                 "avg_launch_ms": round(per_ms["cg_update"], 4),

@@ -91,14 +91,16 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * sets).  op: 0 copy, 1 axpy, 2 norm, 3 dot, 4 cg_update, 5 gather,
  * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
- * the number of 256-thread workgroups (kernels grid-stride beyond it;
- * reductions are further capped at 2097152).  variant, for copy, axpy,
- * norm, dot and cg_update, is the workgroup order: 0 as the hardware
+ * the number of workgroups (kernels grid-stride beyond it; reductions are
+ * further capped at 2097152).  variant, for copy, axpy, norm, dot and
+ * cg_update, is the workgroup order in its two low bits: 0 as the hardware
  * dispatches them (round-robin over the 8 XCDs, so the XCDs interleave 4 KB
  * slices of each operand), 1 the 256 workgroups one XCD receives in each
- * group of 2048 take consecutive block numbers (1 MB runs per XCD), 2 each
- * XCD takes one contiguous range of blocks over the whole grid; other
- * values act as 0.  For gather and scatter, variant is a kernel choice,
+ * group of 2048 take consecutive block numbers (1 MB runs per XCD with
+ * 256-thread workgroups), 2 each XCD takes one contiguous range of blocks
+ * over the whole grid, 3 acts as 0; plus the workgroup size: + 4 for 128
+ * threads, + 8 for 512 threads, otherwise 256 (operands not 16-byte aligned
+ * with one another always run 256-thread workgroups).  For gather and scatter, variant is a kernel choice,
  * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
  * 256 blocks per XCD in every group of 2048, instead of one contiguous range
  * of blocks per XCD.  Gather: 0 = rows in the plan's permuted order (by default

@@ -9,13 +9,16 @@ operation, dtype and length bucket, and writes the fastest as a tune table
 bs_ctx_create picks it up; BS_TUNE_FILE overrides it.
 
 Candidates:
-  copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass}
+  copy, axpy        unroll {1, 2, 4, 8} x grid cap {1024, 4096, 16384, 65536, one pass},
+                      same orders and workgroup sizes as below
   norm, dot,        unroll {1, 2, 4, 8} x grid cap {256, 1024, 4096, 16384, 65536,
   cg_update           one pass (up to 2^21 workgroups, the reductions' partial
                       buffer)}, and cap 1
                       up to 2^20 elements (one workgroup finishes the sum in the
                       same launch); from 2^20 elements on, each shape also with
-                      the two XCD-grouped workgroup orders (variants 1 and 2)
+                      the two XCD-grouped workgroup orders (variants 1 and 2);
+                      every shape with 256-, 128- and 512-thread workgroups
+                      (variant + 0, + 4, + 8)
   gather, scatter   kernel variant {0, 1, 2}, each in the three workgroup orders
                     (one range per XCD, +4 dispatch order, +8 runs of 256 blocks
                     per XCD), on permuted and oriented N = 7 meshes, with
@@ -107,9 +110,11 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
                 # below 2^20 elements a launch has fewer than 2048 workgroups (or one),
                 # where the orders differ little
                 orders = (0, 1, 2) if n >= (1 << 20) else (0,)
+                # workgroup size: + 0 for 256 threads, + 4 for 128, + 8 for 512
+                variants = [o + b for b in (0, 4, 8) for o in orders]
                 for u in (1, 2, 4, 8):
                     for g in caps:
-                        for v in orders:
+                        for v in variants:
                             bs.bs_ctx_set_tune(ctx, op, u, g, v)
                             times[(u, g, v)] = _time(torch, calls[op], reps)
                             log.write(json.dumps({"op": op, "dtype": dname, "n": n, "unroll": u, "grid_cap": g,

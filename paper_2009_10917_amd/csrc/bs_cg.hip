@@ -146,26 +146,86 @@ __device__ __forceinline__ typename Storage<T>::E round_once(double v) {
   }
 }
 
-// out = r * s rounded once, to nearest with ties to even, to the storage type
+// Start of a refinement step: s = 1 / sqrt(*rr) (the binary64 residual's
+// norm, read on the device), rl = r s rounded once to the storage type (to
+// nearest, ties to even), p = rl, d = 0, and the partial sums of rl.rl over
+// the stored values (binary32 arithmetic, compensated, as the norm of BS3).
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_scale_to(const double* __restrict__ r, double s, int64_t n,
-                                                     typename Storage<T>::E* __restrict__ out) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) out[i] = round_once<T>(r[i] * s);
+__global__ __launch_bounds__(kBlock) void k_ir_prepare(const double* __restrict__ r, const double* __restrict__ rr,
+                                                       int64_t n, typename Storage<T>::E* __restrict__ rl,
+                                                       typename Storage<T>::E* __restrict__ p,
+                                                       typename Storage<T>::E* __restrict__ d, double* partials) {
+  using S = Storage<T>;
+  using C = typename S::C;
+  using E = typename S::E;
+  const double s = 1.0 / sqrt(*rr);
+  DW<C> acc{C(0), C(0)};
+  const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += step) {
+    const E e = round_once<T>(r[i] * s);
+    rl[i] = e;
+    p[i] = e;
+    d[i] = E{};
+    const C v = S::load(e);
+    dev::dw_acc(acc, v * v);
+  }
+  store_partial(DW<double>{static_cast<double>(acc.s), static_cast<double>(acc.c)}, partials);
 }
 
-// x = x + s * d  (binary64 x, narrow d)
+// x = x + sqrt(*rr) d  (binary64 x, narrow d; the refinement's correction)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_add_scaled(double* __restrict__ x, double s,
+__global__ __launch_bounds__(kBlock) void k_add_scaled(double* __restrict__ x, const double* __restrict__ rr,
                                                        const typename Storage<T>::E* __restrict__ d, int64_t n) {
+  const double s = sqrt(*rr);
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) x[i] = x[i] + s * static_cast<double>(Storage<T>::load(d[i]));
 }
 
-template <class E>
-__global__ __launch_bounds__(kBlock) void k_zero(E* __restrict__ p, int64_t n) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) p[i] = E{};
+// Tail of the binary64 residual: r = b - r (r holding A x on entry), rounded
+// as BS2 rounds fl(1 b + (-1) r), and the compensated partial sums of r.r.
+template <int V>
+struct ResidualOp : ops::Base<double, V> {
+  using B = ops::Base<double, V>;
+  using Vec = typename B::Vec;
+  struct Regs {
+    Vec b, r;
+  };
+  const double* b;
+  double* r;
+  int32_t head;
+  DW<double> acc;
+  __device__ double one(double be, double re) {
+    const double v = be - re;
+    dev::dw_acc(acc, v * v);
+    return v;
+  }
+  __device__ void load(Regs& g, int64_t j) const {
+    g.b = B::ld(b + head, j);
+    g.r = B::ld(r + head, j);
+  }
+  __device__ void apply(Regs& g, int64_t j) {
+#pragma unroll
+    for (int k = 0; k < V; ++k) ops::vset(g.r, k, one(ops::vget<Vec, double>(g.b, k), ops::vget<Vec, double>(g.r, k)));
+    B::st(r + head, j, g.r);
+  }
+  __device__ void scalar(int64_t e) { r[e] = one(b[e], r[e]); }
+};
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_residual_tail(const double* __restrict__ b, double* __restrict__ r, Span sp,
+                                                          double* partials) {
+  ResidualOp<V> op{{}, b, r, sp.head, DW<double>{0.0, 0.0}};
+  stream_loop<4>(op, sp);
+  store_partial(DW<double>{op.acc.s, op.acc.c}, partials);
+}
+
+// *out = the G compensated pairs added in order (one workgroup).
+__global__ __launch_bounds__(kFinishBlock) void k_sum_pairs(const double* __restrict__ partials, int G,
+                                                             double* __restrict__ out) {
+  DW<double> a{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kFinishBlock) a = dev::dw_add(a, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  a = dev::block_reduce<kFinishBlock>(a);
+  if (threadIdx.x == 0) *out = a.s + a.c;
 }
 
 // ---------------------------------------------------------------- host-side CG engine
@@ -308,13 +368,27 @@ bs_status check_solver_args(const char* op, bs_ctx* ctx, int64_t m, const double
   return BS_OK;
 }
 
-// r = b - A x (binary64); returns r.r in *rr_host
-bs_status residual(bs_ctx* ctx, int64_t m, double shift, const double* b, const double* x, double* r, double* rr_dev,
-                   double* rr_host, hipStream_t st) {
+// r = b - A x (binary64) with r.r left in *rr_dev; nothing is read back.
+constexpr int kTailBlocks = 2048;  // workgroups of the residual tail and the step preparation
+bs_status residual_dev(bs_ctx* ctx, int64_t m, double shift, const double* b, const double* x, double* r,
+                       double* rr_dev, hipStream_t st) {
   const int64_t n = m * m * m;
   bs_status s = launch_stencil<double>(m, shift, x, r, st);
-  if (!s) s = bs_axpy(ctx, BS_F64, n, 1.0, b, -1.0, r, st);
-  if (!s) s = bs_norm(ctx, BS_F64, n, r, nullptr, rr_dev, st);
+  if (s) return s;
+  Span sp = make_span<double>(n, {b, r});
+  const int g = grid_for(sp, 4, kTailBlocks);
+  if (sp.vwidth == 1)
+    hipLaunchKernelGGL(k_residual_tail<1>, dim3(g), dim3(kBlock), 0, st, b, r, sp, ctx->partials);
+  else
+    hipLaunchKernelGGL(k_residual_tail<2>, dim3(g), dim3(kBlock), 0, st, b, r, sp, ctx->partials);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, g, rr_dev);
+  return check_launch("residual");
+}
+
+// The same, returning r.r on the host.
+bs_status residual(bs_ctx* ctx, int64_t m, double shift, const double* b, const double* x, double* r, double* rr_dev,
+                   double* rr_host, hipStream_t st) {
+  bs_status s = residual_dev(ctx, m, shift, b, x, r, rr_dev, st);
   if (!s) s = check_hip(hipMemcpyAsync(rr_host, rr_dev, sizeof(double), hipMemcpyDeviceToHost, st), "residual");
   if (!s) s = check_hip(hipStreamSynchronize(st), "residual");
   return s;
@@ -364,8 +438,19 @@ bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double
   int64_t outer = 0, inner = 0;
   double rr = 0.0;
   bool stagnated = false;
+  // scal[2] = r.r of the binary64 residual, scal[0] = rl.rl of its rounded
+  // direction; one read-back per refinement step
+  if ((s = residual_dev(ctx, m, shift, b, x, r64, scal + 2, st))) return s;
+  const unsigned int gp = blocks_for(n) < static_cast<unsigned int>(kTailBlocks) ? blocks_for(n) : kTailBlocks;
   while (true) {
-    if ((s = residual(ctx, m, shift, b, x, r64, scal + 2, &rr, st))) return s;
+    hipLaunchKernelGGL((k_ir_prepare<T>), dim3(gp), dim3(kBlock), 0, st, r64, scal + 2, n, rl, p, d, ctx->partials);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, static_cast<int>(gp), scal);
+    if ((s = check_launch(op))) return s;
+    double h[3] = {0.0, 0.0, 0.0};
+    if ((s = check_hip(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, st), op))) return s;
+    if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+    rr = h[2];
+    const double rr0 = h[0];
     if (rr <= stop || outer >= max_outer) break;
     // outer residual must halve within three refinement steps
     if (outer >= 3 && std::sqrt(rr) > 0.5 * std::sqrt(hist[(outer - 3) % 4])) {
@@ -373,22 +458,15 @@ bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double
       break;
     }
     hist[outer % 4] = rr;
-    const double nr = std::sqrt(rr);
-    hipLaunchKernelGGL((k_scale_to<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, r64, 1.0 / nr, n, rl);
-    hipLaunchKernelGGL((k_zero<E>), dim3(blocks_for(n)), dim3(kBlock), 0, st, d, n);
-    if ((s = check_launch(op))) return s;
-    if ((s = bs_copy(ctx, dtype_of<T>(), n, rl, p, st))) return s;
-    if ((s = bs_norm(ctx, dtype_of<T>(), n, rl, nullptr, scal, st))) return s;
-    double rr0 = 0.0;
-    if ((s = check_hip(hipMemcpyAsync(&rr0, scal, 8, hipMemcpyDeviceToHost, st), op))) return s;
-    if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
     // the last step need not go below what the outer target asks for
     const double theta = std::max(inner_tol, 0.5 * std::sqrt(stop / rr));
     CgState fin{};
     if ((s = eng.run(theta * theta * rr0, static_cast<int32_t>(max_inner), &fin))) return s;
     inner += fin.iters;
-    hipLaunchKernelGGL((k_add_scaled<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, x, nr, static_cast<const E*>(d), n);
+    hipLaunchKernelGGL((k_add_scaled<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, x, scal + 2,
+                       static_cast<const E*>(d), n);
     if ((s = check_launch(op))) return s;
+    if ((s = residual_dev(ctx, m, shift, b, x, r64, scal + 2, st))) return s;
     ++outer;
   }
   if ((s = check_hip(hipStreamSynchronize(st), op))) return s;

@@ -58,9 +58,9 @@ struct CgLink {
   int32_t slot;
 };
 
-// The sum of G compensated pairs added in index order per thread and then
-// across the workgroup (the same order in every workgroup), and the done
-// flag as thread 0 read it, both given to every thread.
+// The done flag as thread 0 read it and, while it is 0, the sum of G
+// compensated pairs added in index order per thread and then across the
+// workgroup (the same order in every workgroup), both given to every thread.
 struct Bcast {
   double v;
   int32_t done;
@@ -69,15 +69,17 @@ struct Bcast {
 __device__ __forceinline__ Bcast block_sum_bcast(const double* __restrict__ partials, int G, const int32_t* done) {
   __shared__ double s_v;
   __shared__ int32_t s_done;
+  // once the solve is over (the rest of a captured batch) the pairs are not read
+  if (threadIdx.x == 0) s_done = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int32_t d = s_done;
+  if (d) return Bcast{0.0, d};
   DW<double> r{0.0, 0.0};
   for (int i = threadIdx.x; i < G; i += kBlock) r = dev::dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
   r = dev::block_reduce<kBlock>(r);
-  if (threadIdx.x == 0) {
-    s_v = r.s + r.c;
-    s_done = __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) s_v = r.s + r.c;
   __syncthreads();
-  return Bcast{s_v, s_done};
+  return Bcast{s_v, 0};
 }
 
 __device__ __forceinline__ void set_done(CgState* st, int32_t v) {

@@ -30,55 +30,55 @@ namespace {
 
 using namespace ops;
 
-template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_copy(const typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, int NB>
+__global__ __launch_bounds__(NB) void k_copy(const typename Storage<T>::E* __restrict__ x,
                                                  typename Storage<T>::E* __restrict__ y, Span sp) {
   CopyOp<T, V> op{{}, x, y, sp.head};
-  stream_loop<U>(op, sp);
+  stream_loop<U, NB>(op, sp);
 }
 
 // ---------------------------------------------------------------- BS2 AXPY
 
 
-template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_axpy(typename Storage<T>::C alpha, const typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, int NB>
+__global__ __launch_bounds__(NB) void k_axpy(typename Storage<T>::C alpha, const typename Storage<T>::E* __restrict__ x,
                                                  typename Storage<T>::C beta, typename Storage<T>::E* __restrict__ y,
                                                  Span sp) {
   AxpyOp<T, V> op{{}, alpha, beta, x, y, sp.head};
-  stream_loop<U>(op, sp);
+  stream_loop<U, NB>(op, sp);
 }
 
 // ---------------------------------------------------------------- BS3 norm
 
 
-template <class T, int V, int U, bool W>
-__global__ __launch_bounds__(kBlock) void k_norm(const typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, bool W, int NB>
+__global__ __launch_bounds__(NB) void k_norm(const typename Storage<T>::E* __restrict__ x,
                                                  const typename Storage<T>::E* __restrict__ w, Span sp,
                                                  double* partials, double* out) {
   using C = typename Storage<T>::C;
   NormOp<T, V, W> op{{}, x, w, sp.head, DW<C>{C(0), C(0)}};
-  stream_loop<U>(op, sp);
-  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  stream_loop<U, NB>(op, sp);
+  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- BS4 inner product
 
 
-template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_dot(const typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, int NB>
+__global__ __launch_bounds__(NB) void k_dot(const typename Storage<T>::E* __restrict__ x,
                                                 const typename Storage<T>::E* __restrict__ y, Span sp,
                                                 double* partials, double* out) {
   using C = typename Storage<T>::C;
   DotOp<T, V> op{{}, x, y, sp.head, DW<C>{C(0), C(0)}};
-  stream_loop<U>(op, sp);
-  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  stream_loop<U, NB>(op, sp);
+  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- BS5 fused CG update
 
 
-template <class T, int V, int U, bool W>
-__global__ __launch_bounds__(kBlock) void k_cg_update(typename Storage<T>::C alpha, typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, bool W, int NB>
+__global__ __launch_bounds__(NB) void k_cg_update(typename Storage<T>::C alpha, typename Storage<T>::E* __restrict__ x,
                                                       const typename Storage<T>::E* __restrict__ p,
                                                       typename Storage<T>::E* __restrict__ r,
                                                       const typename Storage<T>::E* __restrict__ Ap,
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(typename Storage<T>::C alp
                                                       double* partials, double* out) {
   using C = typename Storage<T>::C;
   CgOp<T, V, W> op{{}, alpha, x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
-  stream_loop<U>(op, sp);
-  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  stream_loop<U, NB>(op, sp);
+  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- device scalars
@@ -108,16 +108,16 @@ __device__ __forceinline__ double dev_scalar(const DevScalar& s) {
   return s.h * q;
 }
 
-template <class T, int V, int U>
-__global__ __launch_bounds__(kBlock) void k_axpy_dev(DevScalar a, const typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, int NB>
+__global__ __launch_bounds__(NB) void k_axpy_dev(DevScalar a, const typename Storage<T>::E* __restrict__ x,
                                                      DevScalar b, typename Storage<T>::E* __restrict__ y, Span sp) {
   using C = typename Storage<T>::C;
   AxpyOp<T, V> op{{}, static_cast<C>(dev_scalar(a)), static_cast<C>(dev_scalar(b)), x, y, sp.head};
-  stream_loop<U>(op, sp);
+  stream_loop<U, NB>(op, sp);
 }
 
-template <class T, int V, int U, bool W>
-__global__ __launch_bounds__(kBlock) void k_cg_update_dev(DevScalar a, typename Storage<T>::E* __restrict__ x,
+template <class T, int V, int U, bool W, int NB>
+__global__ __launch_bounds__(NB) void k_cg_update_dev(DevScalar a, typename Storage<T>::E* __restrict__ x,
                                                           const typename Storage<T>::E* __restrict__ p,
                                                           typename Storage<T>::E* __restrict__ r,
                                                           const typename Storage<T>::E* __restrict__ Ap,
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_dev(DevScalar a, typename 
                                                           double* partials, double* out) {
   using C = typename Storage<T>::C;
   CgOp<T, V, W> op{{}, static_cast<C>(dev_scalar(a)), x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
-  stream_loop<U>(op, sp);
-  dev::block_store_pair<kBlock>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  stream_loop<U, NB>(op, sp);
+  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
 
 // ---------------------------------------------------------------- host side
@@ -182,43 +182,62 @@ bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char*
 
 // Tune variant of a streaming operation -> Span::order (1 and 2 select the
 // XCD-grouped workgroup orders; anything else keeps the dispatch order).
-inline int stream_order(int variant) { return (variant == 1 || variant == 2) ? variant : 0; }
+inline int stream_order(int variant) {
+  const int o = variant & 3;
+  return (o == 1 || o == 2) ? o : 0;
+}
 
 inline int norm_unroll(int u) { return (u >= 8) ? 8 : (u >= 4) ? 4 : (u >= 2) ? 2 : 1; }
 
-// Launch `K<T, V, U>` for the runtime unroll and packet width.
-#define BS_DISPATCH(KERNEL, T, sp, u, grid, stream, ...)                                                  \
+// Threads per workgroup of a streaming kernel, from its tune variant: + 4
+// selects 128, + 8 selects 512, otherwise 256 (the two low bits keep the
+// workgroup order).  Unaligned operands (one element per packet) always run
+// 256-thread workgroups.
+inline int stream_block(const Span& sp, int variant) {
+  if (sp.vwidth == 1) return kBlock;
+  const int s = (variant >> 2) & 3;
+  return s == 1 ? 128 : s == 2 ? 512 : kBlock;
+}
+
+// Launch `K<T, V, U, NB>` for the runtime unroll, packet width and block size.
+#define BS_DISPATCH_U(KERNEL_ARGS, VN, u, NB, grid, stream, ...)                                          \
   do {                                                                                                     \
-    constexpr int VN = Storage<T>::V;                                                                      \
-    if ((sp).vwidth == 1) {                                                                                \
-      hipLaunchKernelGGL((KERNEL<T, 1, 4>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);             \
-    } else if ((u) == 8) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 8>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);            \
+    if ((u) == 8) {                                                                                        \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 8, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
     } else if ((u) == 4) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 4>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);            \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 4, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
     } else if ((u) == 2) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 2>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);            \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 2, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
     } else {                                                                                               \
-      hipLaunchKernelGGL((KERNEL<T, VN, 1>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);            \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 1, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
     }                                                                                                      \
   } while (0)
 
-// The same with an extra bool template argument (weighted or not).
-#define BS_DISPATCH_B(KERNEL, T, B, sp, u, grid, stream, ...)                                             \
+#define BS_DISPATCH_NB(KERNEL_ARGS, T, sp, u, nb, grid, stream, ...)                                       \
   do {                                                                                                     \
     constexpr int VN = Storage<T>::V;                                                                      \
     if ((sp).vwidth == 1) {                                                                                \
-      hipLaunchKernelGGL((KERNEL<T, 1, 4, B>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);          \
-    } else if ((u) == 8) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 8, B>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);         \
-    } else if ((u) == 4) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 4, B>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);         \
-    } else if ((u) == 2) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL<T, VN, 2, B>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);         \
+      hipLaunchKernelGGL((KERNEL_ARGS(1, 4, kBlock)), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);   \
+    } else if ((nb) == 128) {                                                                              \
+      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 128, grid, stream, __VA_ARGS__);                                   \
+    } else if ((nb) == 512) {                                                                              \
+      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 512, grid, stream, __VA_ARGS__);                                   \
     } else {                                                                                               \
-      hipLaunchKernelGGL((KERNEL<T, VN, 1, B>), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);         \
+      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 256, grid, stream, __VA_ARGS__);                                   \
     }                                                                                                      \
   } while (0)
+
+
+#define K_COPY(V, U, NB) k_copy<T, V, U, NB>
+#define K_AXPY(V, U, NB) k_axpy<T, V, U, NB>
+#define K_DOT(V, U, NB) k_dot<T, V, U, NB>
+#define K_AXPY_DEV(V, U, NB) k_axpy_dev<T, V, U, NB>
+#define K_NORM_W(V, U, NB) k_norm<T, V, U, true, NB>
+#define K_NORM(V, U, NB) k_norm<T, V, U, false, NB>
+#define K_UPD_W(V, U, NB) k_cg_update<T, V, U, true, NB>
+#define K_UPD(V, U, NB) k_cg_update<T, V, U, false, NB>
+#define K_UPD_DEV_W(V, U, NB) k_cg_update_dev<T, V, U, true, NB>
+#define K_UPD_DEV(V, U, NB) k_cg_update_dev<T, V, U, false, NB>
 
 template <class T> constexpr int dtype_index() { return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2; }
 
@@ -228,8 +247,9 @@ bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t s
   const Tune& tn = tune_for(ctx, OP_COPY, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
-  BS_DISPATCH(k_copy, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
+  BS_DISPATCH_NB(K_COPY, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
   return check_launch("bs_copy");
 }
 
@@ -240,8 +260,9 @@ bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double b
   const Tune& tn = tune_for(ctx, OP_AXPY, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
-  BS_DISPATCH(k_axpy, T, sp, u, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
+  BS_DISPATCH_NB(K_AXPY, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
               static_cast<typename Storage<T>::E*>(y), sp);
   return check_launch("bs_axpy");
 }
@@ -253,12 +274,13 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (w)
-    BS_DISPATCH_B(k_norm, T, true, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
+    BS_DISPATCH_NB(K_NORM_W, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
                   ctx->partials, out);
   else
-    BS_DISPATCH_B(k_norm, T, false, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
+    BS_DISPATCH_NB(K_NORM, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
                   ctx->partials, out);
   return finish(ctx, g, out, st, "bs_norm");
 }
@@ -270,8 +292,9 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
-  BS_DISPATCH(k_dot, T, sp, u, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
+  BS_DISPATCH_NB(K_DOT, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
   return finish(ctx, g, out, st, "bs_dot");
 }
 
@@ -286,16 +309,17 @@ bs_status launch_cg_update(int64_t n, double alpha, void* x, const void* p, void
   Span sp = make_span<T>(n, {x, p, r, Ap, w});
   sp.order = stream_order(variant);
   const int u = norm_unroll(unroll);
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
+  const int nb = stream_block(sp, variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (g > cap)
     return fail(BS_ERR_INVALID_ARG, "%s: %d workgroups need more reduction pairs than the %d the buffer holds", op, g,
                 cap);
   if (w)
-    BS_DISPATCH_B(k_cg_update, T, true, sp, u, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+    BS_DISPATCH_NB(K_UPD_W, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w),
                   sp, partials, out);
   else
-    BS_DISPATCH_B(k_cg_update, T, false, sp, u, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+    BS_DISPATCH_NB(K_UPD, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p),
                   sp, partials, out);
   return finish_on(partials, sums, g, out, st, op);
@@ -352,8 +376,9 @@ bs_status run_axpy_dev(bs_ctx* ctx, int64_t n, DevScalar a, const void* x, DevSc
   const Tune& tn = tune_for(ctx, OP_AXPY, dtype_index<T>(), n);
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap);
-  BS_DISPATCH(k_axpy_dev, T, sp, u, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
+  BS_DISPATCH_NB(K_AXPY_DEV, T, sp, u, nb, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
   return check_launch("bs_axpy_dev");
 }
 
@@ -366,12 +391,13 @@ bs_status run_cg_update_dev(bs_ctx* ctx, int64_t n, DevScalar a, void* x, const 
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
-  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap);
+  const int nb = stream_block(sp, tn.variant);
+  const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (w)
-    BS_DISPATCH_B(k_cg_update_dev, T, true, sp, u, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+    BS_DISPATCH_NB(K_UPD_DEV_W, T, sp, u, nb, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
                   static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w), sp, ctx->partials, out);
   else
-    BS_DISPATCH_B(k_cg_update_dev, T, false, sp, u, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+    BS_DISPATCH_NB(K_UPD_DEV, T, sp, u, nb, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
                   static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p), sp, ctx->partials, out);
   return finish(ctx, g, out, st, "bs_cg_update_dev");
 }

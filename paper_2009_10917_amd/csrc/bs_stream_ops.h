@@ -46,31 +46,31 @@ __device__ __forceinline__ int64_t scalar_index(const Span& sp) {
 }
 
 // The streaming loop shared by BS1-BS5.  Thread t of workgroup b (the
-// logical block number) owns packets i, i + 256, ..., i + (U-1)*256 with
-// i = b*256*U + t and strides by the whole grid.  Each trip first issues
+// logical block number) of NB threads owns packets i, i + NB, ...,
+// i + (U-1)*NB with i = b*NB*U + t and strides by the whole grid.  Each trip first issues
 // all of its loads (op.load), then computes and stores (op.apply), so U
 // packets per operand are in flight.
 // Trips that are entirely in range run without bounds checks; only the last
 // (ragged) trip of a thread checks each packet.
-template <int U, class Op>
+template <int U, int NB = kBlock, class Op>
 __device__ __forceinline__ void stream_loop(Op& op, const Span& sp) {
-  const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock * U;
-  int64_t i = logical_block(sp) * kBlock * U + threadIdx.x;
-  for (; i + static_cast<int64_t>(U - 1) * kBlock < sp.nvec; i += step) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * NB * U;
+  int64_t i = logical_block(sp) * NB * U + threadIdx.x;
+  for (; i + static_cast<int64_t>(U - 1) * NB < sp.nvec; i += step) {
     typename Op::Regs r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) op.load(r[u], i + u * kBlock);
+    for (int u = 0; u < U; ++u) op.load(r[u], i + u * NB);
 #pragma unroll
-    for (int u = 0; u < U; ++u) op.apply(r[u], i + u * kBlock);
+    for (int u = 0; u < U; ++u) op.apply(r[u], i + u * NB);
   }
   if (i < sp.nvec) {
     typename Op::Regs r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i + u * kBlock < sp.nvec) op.load(r[u], i + u * kBlock);
+      if (i + u * NB < sp.nvec) op.load(r[u], i + u * NB);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i + u * kBlock < sp.nvec) op.apply(r[u], i + u * kBlock);
+      if (i + u * NB < sp.nvec) op.apply(r[u], i + u * NB);
   }
   if (blockIdx.x == 0) {
     const int64_t e = scalar_index(sp);
@@ -271,8 +271,8 @@ Span make_span(int64_t n, std::initializer_list<const void*> ptrs) {
   return sp;
 }
 
-inline int grid_for(const Span& sp, int unroll, int cap) {
-  const int64_t per = static_cast<int64_t>(kBlock) * unroll;
+inline int grid_for(const Span& sp, int unroll, int cap, int block = kBlock) {
+  const int64_t per = static_cast<int64_t>(block) * unroll;
   int64_t g = (sp.nvec + per - 1) / per;
   if (g < 1) g = 1;
   if (g > cap) g = cap;

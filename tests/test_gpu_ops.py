@@ -206,11 +206,12 @@ def order_case():
                "x": bits(h["x"])}
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 4, 5, 6, 8, 9, 10])
 @pytest.mark.parametrize("unroll,cap", [(1, 1 << 30), (4, 65536), (2, 3000), (8, 7)])
 def test_workgroup_orders_do_not_change_results(order_case, order, unroll, cap):
-    # variant 1 and 2 of the streaming operations renumber workgroups per XCD; every
-    # element is still handled once, so vectors stay bit-exact and sums within tolerance
+    # variant 1 and 2 of the streaming operations renumber workgroups per XCD, + 4 and + 8
+    # run 128- and 512-thread workgroups; every element is still handled once, so vectors
+    # stay bit-exact and sums within tolerance
     n, want = order_case
     ctx = bs.bs_ctx_create(0)
     try:
@@ -295,3 +296,37 @@ def test_error_paths(ctx):
     assert float(to_host(o)[0]) == 0.0
     with pytest.raises(bs.BSError):
         bs.bs_copy(ctx, x, x)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("n", [1, 77, 4097, 1_000_003])
+@pytest.mark.parametrize("unroll,cap", [(1, 1), (4, 1 << 30), (2, 300)])
+def test_workgroup_sizes_agree(dtype, n, unroll, cap):
+    # 128- and 512-thread workgroups (variant + 4, + 8) against 256: vectors bit-identical,
+    # reductions within the compensated sums' tolerance
+    res = {}
+    for v in (0, 4, 8):
+        ctx = bs.bs_ctx_create(0)
+        try:
+            for op in ("copy", "axpy", "norm", "dot", "cg_update"):
+                bs.bs_ctx_set_tune(ctx, op, unroll, cap, v)
+            x, y, p, Ap, w = (dev_uniform(n, s, lo=0.0 if s == 5 else -1.0, dtype=dtype) for s in (1, 2, 3, 4, 5))
+            z = torch.empty_like(x)
+            bs.bs_copy(ctx, x, z)
+            o = torch.zeros(3, dtype=torch.float64, device="cuda")
+            bs.bs_norm(ctx, x, w, o[0:1])
+            bs.bs_dot(ctx, x, y, o[1:2])
+            bs.bs_cg_update(ctx, 0.37, z, p, y, Ap, w, o[2:3])
+            bs.bs_axpy(ctx, 0.37, x, 0.61, p)
+            res[v] = [bits(to_host(t)) for t in (z, y, p)] + list(to_host(o))
+        finally:
+            torch.cuda.synchronize()
+            ctx.close()
+    for v in (4, 8):
+        for a, b in zip(res[0][:3], res[v][:3]):
+            assert np.array_equal(a, b), v
+        for a, b in zip(res[0][3:], res[v][3:]):
+            if dtype == torch.float64:
+                assert rel_err(b, a) <= 1e-14, (v, a, b)
+            else:  # compensated binary32 sums of n terms of magnitude <= 1: within 2u * n each
+                assert abs(b - a) <= 4 * 2.0 ** -24 * n, (v, a, b)
