@@ -57,18 +57,24 @@ def source_digest():
 
 def committed_kernel_average(kernel):
     """Average duration (us) and command of `kernel` in the committed
-    rocprofv3 kernel statistics of the benchmark step, or (None, None)."""
+    rocprofv3 kernel statistics of the benchmark step (its first table,
+    whose header names the columns), or (None, None)."""
     path = os.path.join(ROOT, "profiles", "bench_step_kernel_stats_K128.md")
     if not os.path.exists(path):
         return None, None
-    cmd = None
+    cmd, cols = None, None
     for line in open(path):
         if line.strip().startswith("cd /tmp") and cmd is None:
             cmd = line.strip()
+        if not line.strip().startswith("|"):
+            continue
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 3 and cells[0] == kernel:
+        if cols is None and "kernel" in cells and "average (us)" in cells:
+            cols = (cells.index("kernel"), cells.index("average (us)"))
+            continue
+        if cols and len(cells) > max(cols) and cells[cols[0]] == kernel:
             try:
-                return float(cells[2]), cmd
+                return float(cells[cols[1]]), cmd
             except ValueError:
                 return None, cmd
     return None, cmd

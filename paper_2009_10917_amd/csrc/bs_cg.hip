@@ -2,20 +2,27 @@
 // the 7-point finite-difference operator, and mixed-precision iterative
 // refinement around it.  The operator kernels live in bs_stencil.h.
 //
-// One CG iteration runs on the device without returning to the host:
+// One CG iteration runs on the device without returning to the host.
+// Binary64 (five launches):
 //   Ap = A p with the partial sums of p.Ap               (operator + BS4)
 //   alpha = r.r / p.Ap                                   (1 workgroup)
 //   x += alpha p, r -= alpha Ap, partial sums of r.r     (BS5)
 //   beta = r'.r' / r.r, convergence test                 (1 workgroup)
 //   p = r + beta p                                       (BS2)
-// For binary32 and bfloat16 storage the direction update is folded into the
-// next operator application: that kernel reads r and the old p, forms the new
-// p with the same rounded operations the AXPY uses, writes it to a second
-// buffer (p alternates between two buffers) and applies the operator to it;
-// the first iteration runs with beta = 0 on p = r.  In binary64 the four
-// vectors of the fused kernel outgrow the 256 MB last-level cache on the
-// benchmark grid, and its halo re-reads then cost more than the separate
-// AXPY, so binary64 keeps the five-launch form.
+// Binary32 and bfloat16 storage (two launches): the direction update is
+// folded into the next operator application -- that kernel forms beta and
+// the convergence test at its head from the update's partial sums, reads r
+// and the old p, forms the new p with the same rounded operations the AXPY
+// uses, writes it to a second buffer (p alternates between two buffers) and
+// applies the operator to it -- and the update kernel forms alpha at its head
+// from the operator's partial sums; the first iteration runs with beta = 0
+// on p = r.  Every workgroup of such a kernel adds all the pairs itself, in
+// one fixed order, so the update's grid stays small (kUpdateBlocks).  In
+// binary64 the four vectors of the fused kernel outgrow the 256 MB
+// last-level cache on the benchmark grid and its halo re-reads cost more than
+// the separate AXPY, and the streaming kernels run fastest on full grids,
+// whose pairs are too many to add at every workgroup's head: binary64 keeps
+// the one-workgroup scalar kernels.
 //
 // The scalars live in a device-side state; once it says done, the remaining
 // kernels of a batch return at once.  Batches of iterations are captured into
@@ -49,10 +56,10 @@ using stencil::Op7;
 using stencil::store_partial;
 
 constexpr int kBatch = 16;  // iterations per captured graph (even)
-// Workgroups of the update and direction kernels (grid-stride): every
-// workgroup of the next kernel adds their partial sums, so they stay few.
+// Workgroups of the update kernel when the next kernel forms beta at its
+// head (grid-stride): every workgroup of that kernel adds their partial
+// sums, so they stay few.
 constexpr int kUpdateBlocks = 1024;
-constexpr int kDirectionBlocks = 2048;
 
 // Storage types whose CG folds the direction update into the operator.
 template <class T>
@@ -94,9 +101,52 @@ __global__ void k_cg_init(CgState* st, const double* rr, double stop_rr, int32_t
   }
 }
 
-// x += alpha p, r -= alpha Ap and the partial sums of r.r, with alpha =
-// r.r / p.Ap formed at the head from the operator's partial sums.
-template <class T, int V, int U>
+// Algorithm 1 step 7 as a kernel of its own (one workgroup), for the
+// binary64 engine: p.Ap from the operator's partial sums, alpha = r.r / p.Ap.
+__global__ __launch_bounds__(kFinishBlock) void k_after_pAp(const double* __restrict__ partials, int G, CgState* st,
+                                                             int slot) {
+  if (st->done) return;
+  DW<double> a{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kFinishBlock) a = dev::dw_add(a, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  a = dev::block_reduce<kFinishBlock>(a);
+  if (threadIdx.x == 0) {
+    const double pAp = a.s + a.c;
+    st->pAp = pAp;
+    if (pAp > 0.0) {
+      st->alpha = st->rr_slot[slot] / pAp;
+      st->iters += 1;
+    } else {
+      st->done = 2;  // A is not positive definite on p (or p vanished)
+    }
+  }
+}
+
+// Algorithm 1 step 10 and the stopping test as a kernel of its own (one
+// workgroup), for the binary64 engine: r'.r' from the update's partial
+// sums, beta = r'.r' / r.r into the slot of the next iteration.
+__global__ __launch_bounds__(kFinishBlock) void k_after_update(const double* __restrict__ partials, int G,
+                                                                CgState* st, int slot) {
+  if (st->done) return;
+  DW<double> a{0.0, 0.0};
+  for (int i = threadIdx.x; i < G; i += kFinishBlock) a = dev::dw_add(a, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  a = dev::block_reduce<kFinishBlock>(a);
+  if (threadIdx.x == 0) {
+    const double rr_new = a.s + a.c;
+    st->beta = rr_new / st->rr_slot[slot ^ 1];
+    st->rr_slot[slot] = rr_new;
+    st->rr = rr_new;
+    st->fresh = 0;
+    if (!__builtin_isfinite(rr_new))
+      st->done = 2;  // overflow or NaN: further iterations cannot recover
+    else if (rr_new <= st->stop_rr || st->iters >= st->max_iters)
+      st->done = 1;
+  }
+}
+
+// x += alpha p, r -= alpha Ap and the partial sums of r.r.  With HEAD, alpha
+// = r.r / p.Ap is formed at the head from the operator's partial sums;
+// otherwise it is read from the state (k_after_pAp).
+template <class T, int V, int U, bool HEAD>
 __global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums, typename Storage<T>::E* __restrict__ x,
                                                     const typename Storage<T>::E* __restrict__ p,
                                                     typename Storage<T>::E* __restrict__ r,
@@ -104,21 +154,32 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums,
                                                     double* partials) {
   using C = typename Storage<T>::C;
   double alpha = 0.0;
-  if (!cg_alpha(st, op_sums, &alpha)) return;
+  if constexpr (HEAD) {
+    if (!cg_alpha(st, op_sums, &alpha)) return;
+  } else {
+    if (st->done) return;
+    alpha = st->alpha;
+  }
   CgOp<T, V, false> op{{}, static_cast<C>(alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
   store_partial(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials);
 }
 
-// p = r + beta p, with beta = r'.r' / r.r formed at the head from the
-// update's partial sums (and the stopping test).
-template <class T, int V, int U>
+// p = r + beta p.  With HEAD, beta = r'.r' / r.r and the stopping test are
+// formed at the head from the update's partial sums; otherwise beta is read
+// from the state (k_after_update).
+template <class T, int V, int U, bool HEAD>
 __global__ __launch_bounds__(kBlock) void k_direction(CgState* st, CgLink upd_sums,
                                                       const typename Storage<T>::E* __restrict__ r,
                                                       typename Storage<T>::E* __restrict__ p, Span sp) {
   using C = typename Storage<T>::C;
   double beta = 0.0;
-  if (!cg_beta(st, upd_sums, &beta)) return;
+  if constexpr (HEAD) {
+    if (!cg_beta(st, upd_sums, &beta)) return;
+  } else {
+    if (st->done) return;
+    beta = st->beta;
+  }
   AxpyOp<T, V> op{{}, C(1), static_cast<C>(beta), r, p, sp.head};
   stream_loop<U>(op, sp);
 }
@@ -270,24 +331,38 @@ struct CgEngine {
   double* op_partials() const { return ctx->partials; }
   double* upd_partials() const { return ctx->partials + 2 * static_cast<size_t>(kMaxReduceBlocks); }
 
+  // Binary32 and bfloat16 (direction folded into the operator): two
+  // launches, the scalars formed at the heads of the kernels that use them.
+  // Binary64: the operator, alpha (one workgroup), the update, beta (one
+  // workgroup) and the direction, each streaming kernel on its full grid.
   void enqueue_iteration(int parity) {
     E* p_old = (kFuse && parity) ? p2 : p;
     E* p_cur = kFuse ? (parity ? p : p2) : p;
     const CgLink from_update{upd_partials(), g_upd, parity};  // the direction of this iteration
     const CgLink from_op{op_partials(), static_cast<int32_t>(op.blocks), parity};
     op.enqueue(st, shift, p_old, r, p_cur, Ap, op_partials(), state, from_update);
-    if (sp.vwidth == 1)
-      hipLaunchKernelGGL((k_cg_step<T, 1, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r, Ap, sp,
-                         upd_partials());
-    else
-      hipLaunchKernelGGL((k_cg_step<T, S::V, 4>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r, Ap,
-                         sp, upd_partials());
-    if constexpr (!kFuse) {
-      const CgLink next{upd_partials(), g_upd, parity ^ 1};  // the direction of the next iteration
+    if constexpr (kFuse) {
       if (sp.vwidth == 1)
-        hipLaunchKernelGGL((k_direction<T, 1, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, next, r, p, sp);
+        hipLaunchKernelGGL((k_cg_step<T, 1, 4, true>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r,
+                           Ap, sp, upd_partials());
       else
-        hipLaunchKernelGGL((k_direction<T, S::V, 1>), dim3(g_dir), dim3(kBlock), 0, st, state, next, r, p, sp);
+        hipLaunchKernelGGL((k_cg_step<T, S::V, 4, true>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur,
+                           r, Ap, sp, upd_partials());
+    } else {
+      hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, op_partials(), static_cast<int>(op.blocks),
+                         state, parity);
+      if (sp.vwidth == 1)
+        hipLaunchKernelGGL((k_cg_step<T, 1, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r,
+                           Ap, sp, upd_partials());
+      else
+        hipLaunchKernelGGL((k_cg_step<T, S::V, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur,
+                           r, Ap, sp, upd_partials());
+      hipLaunchKernelGGL(k_after_update, dim3(1), dim3(kFinishBlock), 0, st, upd_partials(), g_upd, state, parity ^ 1);
+      const CgLink none{nullptr, 0, parity ^ 1};
+      if (sp.vwidth == 1)
+        hipLaunchKernelGGL((k_direction<T, 1, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
+      else
+        hipLaunchKernelGGL((k_direction<T, S::V, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
     }
   }
 
@@ -295,8 +370,10 @@ struct CgEngine {
     sp = make_span<T>(n, {x, r, p, p2, Ap});
     if (!op.prepare(m, ctx->device))
       return fail(BS_ERR_INVALID_ARG, "cg: grid side %lld is too large", static_cast<long long>(m));
-    g_upd = grid_for(sp, 4, kUpdateBlocks);
-    g_dir = grid_for(sp, 1, kDirectionBlocks);
+    // with the scalars formed at the kernels' heads every workgroup reads all
+    // the previous kernel's pairs, so those grids stay small
+    g_upd = grid_for(sp, 4, kFuse ? kUpdateBlocks : kMaxReduceBlocks);
+    g_dir = grid_for(sp, 1, 1 << 30);
     // capture kBatch iterations into one graph
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager fallback
