@@ -89,7 +89,10 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
 
 /* Launch-shape knobs of one operation on this context (what the autotuner
  * sets).  op: 0 copy, 1 axpy, 2 norm, 3 dot, 4 cg_update, 5 gather,
- * 6 scatter.  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
+ * 6 scatter, 7 batch (the persistent form of bs_batch_step: unroll is the
+ * number of work items a workgroup claims per ticket, grid_cap caps the
+ * workgroups below the resident count; variant unused; keyed by the
+ * batch's number of work items).  unroll in {1, 2, 4, 8} is the number of 16-byte packets (or,
  * for scatter, entries) each thread handles per loop trip; grid_cap bounds
  * the number of workgroups (kernels grid-stride beyond it; reductions are
  * further capped at 2097152).  variant, for copy, axpy, norm, dot and

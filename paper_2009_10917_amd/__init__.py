@@ -23,7 +23,7 @@ STATUS_NAMES = {
     0: "BS_OK", 1: "BS_ERR_INVALID_ARG", 2: "BS_ERR_UNSUPPORTED", 3: "BS_ERR_ALLOC",
     4: "BS_ERR_HIP", 5: "BS_ERR_NO_CONVERGENCE",
 }
-OP_IDS = {"copy": 0, "axpy": 1, "norm": 2, "dot": 3, "cg_update": 4, "gather": 5, "scatter": 6}
+OP_IDS = {"copy": 0, "axpy": 1, "norm": 2, "dot": 3, "cg_update": 4, "gather": 5, "scatter": 6, "batch": 7}
 
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64

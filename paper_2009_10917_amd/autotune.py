@@ -1,6 +1,6 @@
 """Autotuner for the launch shapes of the streaming operations.
 
-    python -m paper_2009_10917_amd.autotune --out tune_gfx950.txt [--quick]
+    python -m paper_2009_10917_amd.autotune --out tune_gfx950.txt [--quick] [--only PART ...]
 
 Measures, on the current GPU, every candidate launch shape of each
 operation, dtype and length bucket, and writes the fastest as a tune table
@@ -19,6 +19,9 @@ Candidates:
                       the two XCD-grouped workgroup orders (variants 1 and 2);
                       every shape with 256-, 128- and 512-thread workgroups
                       (variant + 0, + 4, + 8)
+  batch             items per claim {1, 2, 4, 8} x workgroup cap {128, 256, 512,
+                      resident} of the persistent batched step, on the 1024
+                      box-mesh instances (binary64, binary32)
   gather, scatter   kernel variant {0, 1, 2}, each in the three workgroup orders
                     (one range per XCD, +4 dispatch order, +8 runs of 256 blocks
                     per XCD), on permuted and oriented N = 7 meshes, with
@@ -53,7 +56,8 @@ DTYPES = (("f64", 0), ("f32", 1), ("bf16", 2))
 BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 24, 1 << 26), (1 << 27, 1 << 28))
 MESH_K = ((0, 4), (1 << 20, 16), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
 DEFAULTS = {"copy": (1, 1 << 30, 0), "axpy": (1, 1 << 30, 0), "norm": (8, 4096, 0), "dot": (8, 4096, 0),
-            "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (2, 1 << 30, 1)}
+            "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (2, 1 << 30, 1),
+            "batch": (8, 1 << 30, 0)}
 MARGIN = 0.98
 
 
@@ -183,10 +187,55 @@ def write_table(path, entries, device, seconds, quick):
             f.write(f"{op} {dname} {n_min} {u} {g} {v}\n")
 
 
+def tune_batch(torch, np, bs, bsgen, ctx, quick, log, n_inst=1024):
+    """Items per claim and the workgroup cap of the persistent batched step,
+    on the box-mesh instances of the batched configuration (binary64 and
+    binary32; bfloat16 takes binary32's choice)."""
+    E, N = bsgen.batch_instances(10917, 128 if quick else n_inst)
+    maps, nl, ng = [], [], []
+    for e, d in zip(E, N):
+        m, g = bs.bs_mesh_box_map_host(int(e), int(d))
+        maps.append(m)
+        nl.append(m.size)
+        ng.append(g)
+    d_map = torch.from_numpy(np.concatenate(maps)).cuda()
+    b = bs.bs_batch_create(ctx, nl, ng, d_map)
+    del maps, d_map
+    entries = []
+    streams = {"x": 1, "y": 2, "p": 3, "r": 4, "Ap": 5, "xL": 11, "pL": 12, "wL": 6}
+    for dname, did, dt in (("f64", 0, torch.float64), ("f32", 1, torch.float32)):
+        v = {}
+        for k, sid in streams.items():
+            t = torch.empty(b.n_global if k in bs.BATCH_GLOBAL else b.n_local, dtype=dt, device="cuda")
+            bsgen.device_uniform(t, 10917, sid, lo=0.0 if k == "wL" else -1.0)
+            v[k] = t
+        out = torch.zeros(8 * b.n_inst, dtype=torch.float64, device="cuda")
+        times = {}
+        for claim in (1, 2, 4, 8):
+            for cap in (128, 256, 512, 1 << 30):
+                bs.bs_ctx_set_tune(ctx, "batch", claim, cap, 0)
+                times[(claim, cap, 0)] = _time(torch, lambda: bs.bs_batch_step(ctx, b, v, 0.37, 0.61, out, 2), 5)
+                log.write(json.dumps({"op": "batch", "dtype": dname, "claim": claim, "grid_cap": cap,
+                                      "ms": round(times[(claim, cap, 0)], 5)}) + "\n")
+        choice = _pick(times, DEFAULTS["batch"])
+        bs.bs_ctx_set_tune(ctx, "batch", *DEFAULTS["batch"])
+        print(f"# batch     {dname:4s} {b.n_inst} instances: {choice} "
+              f"{times[choice]:.4f} ms (default {times[DEFAULTS['batch']]:.4f})", flush=True)
+        entries.append(("batch", dname, 0, *choice))
+        if dname == "f32":
+            entries.append(("batch", "bf16", 0, *choice))
+        del v, out
+    b.close()
+    torch.cuda.empty_cache()
+    return entries
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default="tune_gfx950.txt")
     ap.add_argument("--quick", action="store_true", help="skip the largest sizes")
+    ap.add_argument("--only", choices=("streaming", "gs", "batch"), action="append",
+                    help="search these parts only (repeatable; default: all)")
     args = ap.parse_args(argv)
     os.environ["BS_TUNE_FILE"] = "none"  # measure against the built-in defaults
     import numpy as np
@@ -201,8 +250,14 @@ def main(argv=None):
     ctx = bs.bs_ctx_create(0)
     t0 = time.time()
     with open(args.out + ".jsonl", "w") as log:
-        entries = tune_streaming(torch, bs, bsgen, ctx, args.quick, log)
-        entries += tune_gather_scatter(torch, np, bs, bsgen, ctx, args.quick, log)
+        parts = args.only or ("streaming", "gs", "batch")
+        entries = []
+        if "streaming" in parts:
+            entries += tune_streaming(torch, bs, bsgen, ctx, args.quick, log)
+        if "gs" in parts:
+            entries += tune_gather_scatter(torch, np, bs, bsgen, ctx, args.quick, log)
+        if "batch" in parts:
+            entries += tune_batch(torch, np, bs, bsgen, ctx, args.quick, log)
     props = torch.cuda.get_device_properties(0)
     device = f"{getattr(props, 'gcnArchName', '?').split(':')[0]} ({props.multi_processor_count} CUs)"
     write_table(args.out, entries, device, time.time() - t0, args.quick)

@@ -63,7 +63,7 @@ constexpr int kPer = 8;                    // elements per thread in a chunk
 constexpr int kChunk = kBlock * kPer;      // elements per chunk
 constexpr int kIntervals = 11;
 constexpr int kItemChunks = 8;             // chunks per item
-constexpr int kClaim = 8;                  // items per ticket of the persistent form
+constexpr int kClaimMax = 8;               // items per ticket of the persistent form, at most (tune op "batch")
 constexpr int kSlots = 8;                  // output doubles per instance
 enum Slot { S_NORM = 0, S_DOT, S_RR, S_PAP, S_ALPHA, S_RR2, S_BETA };
 
@@ -112,6 +112,7 @@ struct Sched {
   const unsigned int* need; // [kIntervals][n_inst] items in all
   int64_t n_items;
   int32_t n_inst;
+  int32_t claim;            // items per ticket (1 .. kClaimMax)
   uint64_t wait_ticks;      // wall-clock limit of one wait
 };
 
@@ -470,7 +471,7 @@ __device__ bool wait_ready(const Sched& sc, int k, int32_t i, unsigned int local
   return true;
 }
 
-// Each claim of kClaim consecutive items runs in list order; its completions
+// Each claim of sc.claim consecutive items runs in list order; its completions
 // are published together after one release fence (an item may depend on an
 // earlier item of the same claim, whose writes this workgroup already sees).
 template <class T>
@@ -482,12 +483,12 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args<T> a, Sched sc) {
       const bool stop = __hip_atomic_load(sc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
       s_claim = stop ? sc.n_items
                      : static_cast<int64_t>(__hip_atomic_fetch_add(sc.ticket, 1u, __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_AGENT)) * kClaim;
+                                                                   __HIP_MEMORY_SCOPE_AGENT)) * sc.claim;
     }
     __syncthreads();
     const int64_t first = s_claim;
     if (first >= sc.n_items) break;
-    const int64_t last = first + kClaim < sc.n_items ? first + kClaim : sc.n_items;
+    const int64_t last = first + sc.claim < sc.n_items ? first + sc.claim : sc.n_items;
     bool stop = false;
     for (int64_t t = first; t < last; ++t) {
       const Item it = a.items[t];
@@ -662,7 +663,8 @@ int resident_blocks(int device) {
 }
 
 template <class T>
-bs_status run_step(bs_batch* b, int mode, const bs_batch_vectors* v, double alpha, double beta, double* d_out,
+bs_status run_step(bs_ctx* ctx, bs_batch* b, int mode, const bs_batch_vectors* v, double alpha, double beta,
+                   double* d_out,
                    hipStream_t st) {
   using E = typename Storage<T>::E;
   using C = typename Storage<T>::C;
@@ -722,8 +724,12 @@ bs_status run_step(bs_batch* b, int mode, const bs_batch_vectors* v, double alph
   sc.n_inst = n;
   sc.wait_ticks = b->wait_ticks;
   const int dt = static_cast<int>(DtypeOf<T>::v);
-  const int64_t claims = (b->n_items + kClaim - 1) / kClaim;
-  const unsigned int grid = static_cast<unsigned int>(std::max<int64_t>(1, std::min<int64_t>(b->resident[dt], claims)));
+  // items per claim and a cap on the workgroups from the tune entry of op "batch"
+  const Tune& tn = tune_for(ctx, OP_BATCH, dt, b->n_items);
+  sc.claim = tn.unroll < 1 ? 1 : (tn.unroll > kClaimMax ? kClaimMax : tn.unroll);
+  const int64_t claims = (b->n_items + sc.claim - 1) / sc.claim;
+  const unsigned int grid = static_cast<unsigned int>(
+      std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(b->resident[dt], claims), tn.grid_cap)));
   hipLaunchKernelGGL(k_persistent<T>, dim3(grid), dim3(kBlock), 0, st, a, sc);
   return check_launch("bs_batch_step");
 }
@@ -797,7 +803,7 @@ extern "C" bs_status bs_batch_create(bs_ctx* ctx, int32_t n_inst, const int64_t*
   std::vector<unsigned int> need;
   make_items(b, items, b->first_item, need);
   b->n_items = static_cast<int64_t>(items.size());
-  if (b->n_items >= (int64_t(kClaim) << 31)) {
+  if (b->n_items >= (int64_t(1) << 31)) {
     delete b;
     return fail(BS_ERR_INVALID_ARG, "%s: too many work items", op);
   }
@@ -927,9 +933,9 @@ extern "C" bs_status bs_batch_step(bs_ctx* ctx, bs_batch* b, bs_dtype dtype, int
   if (!aligned_to(d_out, 8)) return fail(BS_ERR_INVALID_ARG, "%s: misaligned output", op);
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {
-    case BS_F64: return run_step<double>(b, mode, v, alpha, beta, d_out, st);
-    case BS_F32: return run_step<float>(b, mode, v, alpha, beta, d_out, st);
-    case BS_BF16: return run_step<dev::bf16>(b, mode, v, alpha, beta, d_out, st);
+    case BS_F64: return run_step<double>(ctx, b, mode, v, alpha, beta, d_out, st);
+    case BS_F32: return run_step<float>(ctx, b, mode, v, alpha, beta, d_out, st);
+    case BS_BF16: return run_step<dev::bf16>(ctx, b, mode, v, alpha, beta, d_out, st);
   }
   return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype", op);
 }

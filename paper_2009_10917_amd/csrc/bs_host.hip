@@ -76,7 +76,7 @@ extern "C" const char* bs_version(void) { return "bs-mi355x 0.1 (gfx950)"; }
 
 namespace {
 
-const char* const kOpNames[OP_COUNT] = {"copy", "axpy", "norm", "dot", "cg_update", "gather", "scatter"};
+const char* const kOpNames[OP_COUNT] = {"copy", "axpy", "norm", "dot", "cg_update", "gather", "scatter", "batch"};
 const char* const kDtypeNames[3] = {"f64", "f32", "bf16"};
 
 void set_one(TuneList& L, Tune t) {
@@ -99,6 +99,8 @@ void set_defaults(bs_ctx* c) {
     // tiles per workgroup
     set_one(c->tune[OP_GATHER][d], Tune{1, 1 << 30, 1});
     set_one(c->tune[OP_SCATTER][d], Tune{2, 1 << 30, 1});
+    // persistent batch: 8 items per claim, every resident workgroup
+    set_one(c->tune[OP_BATCH][d], Tune{8, 1 << 30, 0});
   }
 }
 

@@ -47,7 +47,7 @@ struct Tune {
   int variant;
 };
 
-enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCATTER, OP_COUNT };
+enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCATTER, OP_BATCH, OP_COUNT };
 
 // Tune entries of one operation and dtype, by length: entry k applies to
 // lengths n >= n_min[k] up to the next entry's n_min (n_min[0] == 0,

@@ -97,6 +97,27 @@ def test_persistent_form_repeats(ctx, small):
     assert bs.bs_batch_barrier_timeouts(b) == 0
 
 
+@pytest.mark.parametrize("claim,cap", [(1, 1 << 30), (2, 7), (4, 64), (8, 1)])
+def test_persistent_claim_sizes(ctx, small, claim, cap):
+    # the tune entry of op "batch" sets the items per claim and caps the workgroups;
+    # the schedule finishes with any of them and gives the per-phase bits
+    b = small[0]
+    v0 = inputs(b)
+    ref, out_ref = run(ctx, b, v0, bs.BS_BATCH_PER_PHASE)
+    own = bs.bs_ctx_create(torch.cuda.current_device())
+    try:
+        bs.bs_ctx_set_tune(own, "batch", claim, cap, 0)
+        for _ in range(2):
+            v, out = run(own, b, v0, bs.BS_BATCH_PERSISTENT)
+            assert torch.equal(out.view(torch.int64), out_ref.view(torch.int64))
+            for k in v:
+                assert torch.equal(bits(v[k]), bits(ref[k])), k
+    finally:
+        torch.cuda.synchronize()
+        own.close()
+    assert bs.bs_batch_barrier_timeouts(b) == 0
+
+
 def test_binary64_matches_oracle(ctx, small):
     b, maps, ng = small
     v0 = inputs(b)
