@@ -577,7 +577,8 @@ def elem_ops(ctx, bs, bsgen, torch, np, seed, reps=10, K=64, N=7):
     the sum-factorised local Helmholtz operator with the scatter fused in
     (x_L never written), the full y_G = Z^T A_L Z x_G (local operator + BS6
     gather), and the lumped mass in one pass over the CSR of Z^T, against
-    the unfused scatter + gather it replaces."""
+    the unfused scatter + gather it replaces; and CG on the assembled
+    operator (time per iteration, GDOF/s)."""
     E, P = K ** 3, (N + 1) ** 3
     NL, NG = E * P, (K * N + 1) ** 3
     perm = torch.from_numpy(bsgen.permutation(seed, E).astype(np.int32)).cuda()
@@ -616,6 +617,28 @@ def elem_ops(ctx, bs, bsgen, torch, np, seed, reps=10, K=64, N=7):
                         "mfma_issued_TFLOP_s": round(ELEM_MFMA_FLOPS_N7 * E / t / 1e12, 2)})
         res[name] = rec
         print(f"# elem {name}: {rec}", file=sys.stderr, flush=True)
+    # CG on the assembled operator: the time of an iteration from the
+    # difference of two solves run to a fixed iteration count (set-up,
+    # graph capture and the true residuals cancel)
+    b = xG
+    x = torch.zeros_like(xG)
+    secs = {}
+    for it in (16, 112):
+        x.zero_()
+        torch.cuda.synchronize()
+        r = bs.bs_helmholtz_cg_solve(ctx, el, plan, geo, lam, b, x, tol=1e-30, max_iter=it, check=False)
+        if r["iterations"] != it:
+            raise RuntimeError(f"helmholtz cg stopped after {r['iterations']} of {it} iterations ({r['status']})")
+        secs[it] = r["seconds"]
+    per_it = (secs[112] - secs[16]) / 96
+    it_bytes = byts["helmholtz_apply"] + 48 * NG + 24 * NG  # operator + gather, BS5 update, BS2 direction
+    rec = {"ms_per_iteration": round(per_it * 1e3, 4), "GDOF_s": round(NG / per_it / 1e9, 3),
+           "alg_bytes_per_iteration": it_bytes, "GB_s": round(it_bytes / per_it / 1e9, 1),
+           "TFLOP_s_local": round(ELEM_FLOPS_N7 * E / per_it / 1e12, 2),
+           "solve_seconds_16_112": [round(secs[16], 4), round(secs[112], 4)],
+           "note": "binary64, lambda 0.01, b uniform; GDOF/s = global unknowns x iterations / time"}
+    res["helmholtz_cg"] = rec
+    print(f"# elem helmholtz_cg: {rec}", file=sys.stderr, flush=True)
     el.close()
     plan.close()
     return res

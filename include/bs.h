@@ -457,6 +457,27 @@ bs_status bs_cg_ir_solve(bs_ctx* ctx, bs_dtype inner, int64_t m, double shift, c
                          double tol, double inner_tol, int64_t max_inner, int64_t max_outer, bs_cg_result* res,
                          void* stream);
 
+/* Solve (S + lambda M) x = b by CG (Algorithm 1) in binary64, where
+ * S + lambda M = Z^T A_L Z is the assembled Helmholtz operator of
+ * bs_helmholtz_apply (Section 2, eqs. global_system, assembled_stiff,
+ * assembled_mass): gs is the plan of the scatter map (masked copies are
+ * Dirichlet nodes, left out of Z), el the degree (N <= 7), d_geo the
+ * per-element factors as for bs_helmholtz_local.  d_b, d_x: binary64
+ * [n_global] device vectors; x is the starting guess and is overwritten; x
+ * must not overlap b.  The operator must be positive definite on the
+ * unmasked nodes (lambda > 0, or a stiffness with enough masked nodes).
+ * Stopping, restarts and the result record as for bs_cg_solve.  Each
+ * iteration: the local operator on p (the scatter fused into its load) with
+ * the partial sums of p.Ap formed there (the sum over elements of
+ * u_e . A^e u_e, equal to p . Z^T A_L Z p), the gather (Listing 4), alpha,
+ * the update (BS5), beta and the direction (BS2), the scalars on the
+ * device; batches of iterations run as one captured HIP graph.  Allocates
+ * its workspace (3 global vectors and one local vector), synchronises
+ * `stream`; BS_ERR_NO_CONVERGENCE if tol is not met within max_iter. */
+bs_status bs_helmholtz_cg_solve(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* d_geo, double lambda,
+                                const double* d_b, double* d_x, double tol, int64_t max_iter, bs_cg_result* res,
+                                void* stream);
+
 /* ---------------------------------------------------------------- batched instances
  *
  * Many independent instances of uneven size run as one batch (the launch

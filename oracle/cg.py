@@ -72,17 +72,19 @@ def sine_mode(m, a, b, c):
     return np.einsum("k,j,i->kji", s(c), s(b), s(a)).ravel()
 
 
-def cg(b, m, shift, x0=None, tol=1e-10, max_iter=10000):
-    """Algorithm 1 in binary64.  Returns (x, iterations, true relative residual)."""
+def cg_operator(apply, b, x0=None, tol=1e-10, max_iter=10000):
+    """Algorithm 1 in binary64 for the symmetric positive definite operator
+    `apply` (a function of a vector).  Returns (x, iterations, true relative
+    residual)."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     nb = math.sqrt(float(np.dot(b, b)))
-    r = b - stencil7(x, m, shift)
+    r = b - apply(x)
     p = r.copy()
     rr = float(np.dot(r, r))
     j = 0
     while j < max_iter and math.sqrt(rr) > tol * nb:
-        Ap = stencil7(p, m, shift)
+        Ap = apply(p)
         alpha = rr / float(np.dot(p, Ap))
         x = x + alpha * p
         r = r - alpha * Ap
@@ -90,8 +92,14 @@ def cg(b, m, shift, x0=None, tol=1e-10, max_iter=10000):
         p = r + (rr_new / rr) * p
         rr = rr_new
         j += 1
-    res = b - stencil7(x, m, shift)
+    res = b - apply(x)
     return x, j, math.sqrt(float(np.dot(res, res))) / nb
+
+
+def cg(b, m, shift, x0=None, tol=1e-10, max_iter=10000):
+    """Algorithm 1 in binary64 on the shifted 7-point operator.  Returns (x,
+    iterations, true relative residual)."""
+    return cg_operator(lambda v: stencil7(v, m, shift), b, x0, tol, max_iter)
 
 
 # significand bits (with the hidden bit), smallest normal exponent, largest finite value

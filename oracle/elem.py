@@ -27,7 +27,12 @@ Readings (the paper gives the forms, not the quadrature or the geometry):
   permutation matrix, so G = (h/2) I and |J| = (h/2)^3;
 * the Helmholtz block is A^e = S^e + lambda M^e, and the global operator
   y_G = Z^T A_L Z x_G: scatter, apply every block, gather (eq.
-  assembled_stiff, assembled_mass);
+  assembled_stiff, assembled_mass); a negative scatter id masks its local
+  copy (the scatter's convention, Listing 5): Z has no entry in that row,
+  so the copy reads 0 and its result is dropped (a Dirichlet node);
+* helmholtz_cg solves Z^T A_L Z x = b with Algorithm 1 in binary64 (the
+  conjugate gradients of the cg module, this operator in place of the
+  finite-difference one);
 * the lumped mass puts the GLL rule on the nodes themselves: the block is
   diagonal, d_l = |J_e| w_i w_j w_k (GLL weights, rounded as
   fl(fl(fl(w_i w_j) w_k) |J_e|)), and y_G[g] adds d_l x_G[g] over the local
@@ -42,7 +47,7 @@ import numpy as np
 from numpy.polynomial import legendre as L
 
 __all__ = ["gll", "gauss", "lagrange_basis", "element_1d", "element_blocks", "geometry_cube",
-           "apply_local", "apply_assembled", "lumped_weights", "apply_lumped", "node_coordinates"]
+           "apply_local", "apply_assembled", "helmholtz_cg", "lumped_weights", "apply_lumped", "node_coordinates"]
 
 
 def _legendre_exact(n, x):
@@ -183,13 +188,24 @@ def apply_local(N, geo, lam, xL):
 
 def apply_assembled(N, geo, lam, scatter_ids, xG):
     """y_G = Z^T A_L Z x_G (eqs. assembled_stiff, assembled_mass): scatter,
-    apply the blocks, and add the local results of each global node."""
+    apply the blocks, and add the local results of each global node; masked
+    copies (negative ids) read 0 and add nothing."""
     ids = np.asarray(scatter_ids, dtype=np.int64)
     xG = np.asarray(xG, dtype=np.float64)
-    yL = apply_local(N, geo, lam, xG[ids])
+    live = ids >= 0
+    xL = np.zeros(ids.size)
+    xL[live] = xG[ids[live]]
+    yL = apply_local(N, geo, lam, xL)
     yG = np.zeros_like(xG)
-    np.add.at(yG, ids, yL)
+    np.add.at(yG, ids[live], yL[live])
     return yG
+
+
+def helmholtz_cg(N, geo, lam, scatter_ids, b, x0=None, tol=1e-10, max_iter=10000):
+    """Algorithm 1 on the assembled operator.  Returns (x, iterations, true
+    relative residual)."""
+    from oracle.cg import cg_operator
+    return cg_operator(lambda v: apply_assembled(N, geo, lam, scatter_ids, v), b, x0, tol, max_iter)
 
 
 def lumped_weights(N, geo):

@@ -69,6 +69,7 @@ PROTOTYPES = {
     "bs_mass_lumped": (_st, [_p, _p, _p, _p, _p, _p, _p]),
     "bs_cg_solve": (_st, [_p, _i64, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_cg_ir_solve": (_st, [_p, _i32, _i64, _d, _p, _p, _d, _d, _i64, _i64, _p, _p]),
+    "bs_helmholtz_cg_solve": (_st, [_p, _p, _p, _p, _d, _p, _p, _d, _i64, _p, _p]),
     "bs_mesh_box_map_host": (_st, [_i64, _i32, _p, _p]),
     "bs_gs_order_rows": (_st, [_p, _i64, _i64, _i64, _i32, _i32, _i32, _i32, _p]),
     "bs_gs_order_elements": (_st, [_p, _i64, _p, _i64, _p]),
@@ -532,6 +533,22 @@ def bs_cg_solve(ctx, m, shift, b, x, tol=1e-10, max_iter=100000, stream=None, ch
                          ctypes.byref(res), _stream(stream))
     if check:
         _check(st, "bs_cg_solve")
+    out = res.as_dict()
+    out["status"] = STATUS_NAMES.get(st, st)
+    return out
+
+
+def bs_helmholtz_cg_solve(ctx, el, plan, geo, lam, b, x, tol=1e-10, max_iter=100000, stream=None, check=True):
+    """Binary64 CG on the assembled Helmholtz operator Z^T A_L Z of the plan's
+    map; x is the starting guess, overwritten.  Returns the result record."""
+    _f64(geo, 7 * (plan.n_local // el.P), "bs_helmholtz_cg_solve geo")
+    _f64(b, plan.n_global, "bs_helmholtz_cg_solve b")
+    _f64(x, plan.n_global, "bs_helmholtz_cg_solve x")
+    res = CgResult()
+    st = lib.bs_helmholtz_cg_solve(ctx.handle, el.handle, plan.handle, *_ptrs(ctx, geo), float(lam),
+                                   *_ptrs(ctx, b, x), float(tol), int(max_iter), ctypes.byref(res), _stream(stream))
+    if check:
+        _check(st, "bs_helmholtz_cg_solve")
     out = res.as_dict()
     out["status"] = STATUS_NAMES.get(st, st)
     return out

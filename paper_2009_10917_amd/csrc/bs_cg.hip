@@ -1,6 +1,7 @@
 // Conjugate gradients (Algorithm 1) built from the streaming operations, on
-// the 7-point finite-difference operator, and mixed-precision iterative
-// refinement around it.  The operator kernels live in bs_stencil.h.
+// the 7-point finite-difference operator (kernels in bs_stencil.h) and on
+// the assembled Helmholtz operator of the spectral elements (bs_elem.hip),
+// and mixed-precision iterative refinement around the former.
 //
 // One CG iteration runs on the device without returning to the host.
 // Binary64 (five launches):
@@ -411,6 +412,98 @@ struct CgEngine {
   }
 };
 
+// CG on y_G = Z^T A_L Z x_G, the assembled Helmholtz operator (Section 2,
+// eqs. global_system, assembled_stiff, assembled_mass), binary64, six
+// launches per iteration: the local operator applied to p (scatter fused
+// into its load) with the partial sums of p.Ap formed there as the sum over
+// elements of u_e . A^e u_e, the gather of the local results, alpha (one
+// workgroup), the update with the partial sums of r.r (BS5), beta (one
+// workgroup) and the direction (BS2).  The scalars stay on the device, and
+// batches of iterations run as one captured graph.
+struct HelmEngine {
+  bs_ctx* ctx;
+  hipStream_t st;
+  const bs_elem* el;
+  const bs_gs* gs;
+  const double* geo;
+  double lambda;
+  int64_t n;
+  double *x, *r, *p, *Ap, *yL;
+  CgState* state;
+  Span sp;
+  int g_op = 1, g_upd = 1, g_dir = 1;
+  hipGraphExec_t exec = nullptr;
+
+  ~HelmEngine() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+
+  double* op_partials() const { return ctx->partials; }
+  double* upd_partials() const { return ctx->partials + 2 * static_cast<size_t>(kMaxReduceBlocks); }
+
+  bs_status enqueue_iteration(int parity) {
+    bs_status s = helm_apply_dot(ctx, el, gs, geo, lambda, p, yL, Ap, op_partials(), &state->done, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_after_pAp, dim3(1), dim3(kFinishBlock), 0, st, op_partials(), g_op, state, parity);
+    const CgLink none{nullptr, 0, parity};
+    if (sp.vwidth == 1)
+      hipLaunchKernelGGL((k_cg_step<double, 1, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, none, x, p, r, Ap,
+                         sp, upd_partials());
+    else
+      hipLaunchKernelGGL((k_cg_step<double, 2, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, none, x, p, r, Ap,
+                         sp, upd_partials());
+    hipLaunchKernelGGL(k_after_update, dim3(1), dim3(kFinishBlock), 0, st, upd_partials(), g_upd, state, parity ^ 1);
+    if (sp.vwidth == 1)
+      hipLaunchKernelGGL((k_direction<double, 1, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
+    else
+      hipLaunchKernelGGL((k_direction<double, 2, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
+    return check_launch("bs_helmholtz_cg_solve");
+  }
+
+  bs_status prepare() {
+    sp = make_span<double>(n, {x, r, p, Ap});
+    g_op = helm_dot_blocks(gs->n_local / ((el->N + 1) * (el->N + 1) * (el->N + 1)));
+    g_upd = grid_for(sp, 4, kMaxReduceBlocks);
+    g_dir = grid_for(sp, 1, 1 << 30);
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager
+    bs_status s = BS_OK;
+    for (int i = 0; i < kBatch && !s; ++i) s = enqueue_iteration(i & 1);
+    const hipError_t e1 = hipStreamEndCapture(st, &graph);
+    if (s) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e1 != hipSuccess || !graph) {
+      (void)hipGetLastError();
+      return BS_OK;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      exec = nullptr;
+      (void)hipGetLastError();
+    }
+    return BS_OK;
+  }
+
+  bs_status run(const double* rr_dev, double stop_rr, int32_t max_iters, CgState* out) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, st, state, rr_dev, stop_rr, max_iters);
+    bs_status s = check_launch("bs_helmholtz_cg_solve");
+    while (!s) {
+      if (exec) {
+        s = check_hip(hipGraphLaunch(exec, st), "bs_helmholtz_cg_solve graph launch");
+      } else {
+        for (int i = 0; i < kBatch && !s; ++i) s = enqueue_iteration(i & 1);
+      }
+      if (!s) s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
+      if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
+      if (!s && out->done) break;
+    }
+    return s;
+  }
+};
+
 // Solver workspace: one allocation, carved into aligned pieces.
 struct Workspace {
   DevMem mem;
@@ -658,4 +751,84 @@ extern "C" bs_status bs_cg_ir_solve(bs_ctx* ctx, bs_dtype inner, int64_t m, doub
     case BS_BF16: return ir_solve<dev::bf16>(ctx, m, shift, d_b, d_x, tol, inner_tol, max_inner, max_outer, res, st);
   }
   return fail(BS_ERR_INVALID_ARG, "%s: unknown dtype", op);
+}
+
+extern "C" bs_status bs_helmholtz_cg_solve(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* d_geo,
+                                           double lambda, const double* d_b, double* d_x, double tol, int64_t max_iter,
+                                           bs_cg_result* res, void* stream) {
+  const char* op = "bs_helmholtz_cg_solve";
+  bs_status s;
+  if ((s = check_ctx(ctx, op))) return s;
+  if (!el || !gs) return fail(BS_ERR_INVALID_ARG, "%s: element object or plan is NULL", op);
+  if (el->device != ctx->device || gs->device != ctx->device)
+    return fail(BS_ERR_INVALID_ARG, "%s: element object or plan on another device", op);
+  if (el->N > 7) return fail(BS_ERR_UNSUPPORTED, "%s: the local operator is built for degrees N <= 7", op);
+  const int64_t P = static_cast<int64_t>(el->N + 1) * (el->N + 1) * (el->N + 1);
+  if (gs->n_local % P != 0) return fail(BS_ERR_INVALID_ARG, "%s: plan length is not a whole number of elements", op);
+  const int64_t n = gs->n_global, n_elem = gs->n_local / P;
+  if ((s = check_vec(op, "geo", d_geo, 7 * n_elem, BS_F64)) || (s = check_vec(op, "b", d_b, n, BS_F64)) ||
+      (s = check_vec(op, "x", d_x, n, BS_F64)))
+    return s;
+  if (n > 0 && (!d_b || !d_x)) return fail(BS_ERR_INVALID_ARG, "%s: b or x is NULL", op);
+  if (!(tol > 0.0)) return fail(BS_ERR_INVALID_ARG, "%s: tolerance must be positive", op);
+  if (max_iter < 0) return fail(BS_ERR_INVALID_ARG, "%s: max_iter must be >= 0", op);
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(d_x), ba = reinterpret_cast<uintptr_t>(d_b);
+  if (n > 0 && xa < ba + static_cast<uintptr_t>(n) * 8 && ba < xa + static_cast<uintptr_t>(n) * 8)
+    return fail(BS_ERR_INVALID_ARG, "%s: x overlaps b", op);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (n == 0) {
+    if (res) *res = bs_cg_result{0, 0, 0, 0.0, 0.0};
+    return BS_OK;
+  }
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  if ((s = check_hip(hipStreamSynchronize(caller), op))) return s;
+  OwnStream own;
+  if ((s = check_hip(hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking), op))) return s;
+  hipStream_t st = own.s;
+  Workspace ws;
+  const size_t bytes = 3 * padded(n * 8) + padded(gs->n_local * 8) + padded(sizeof(CgState)) + 1024;
+  if (!ws.alloc(bytes)) return fail(BS_ERR_ALLOC, "%s: cannot allocate %zu bytes of workspace", op, bytes);
+  double* r = ws.take<double>(n);
+  double* p = ws.take<double>(n);
+  double* Ap = ws.take<double>(n);
+  double* yL = ws.take<double>(gs->n_local);
+  CgState* state = ws.take<CgState>(1);
+  double* scal = ws.take<double>(8);
+  HelmEngine eng{ctx, st, el, gs, d_geo, lambda, n, d_x, r, p, Ap, yL, state};
+  if ((s = eng.prepare())) return s;
+  double bb = 0.0;
+  if ((s = bs_norm(ctx, BS_F64, n, d_b, nullptr, scal + 1, st))) return s;
+  if ((s = check_hip(hipMemcpyAsync(&bb, scal + 1, 8, hipMemcpyDeviceToHost, st), op))) return s;
+  if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+  const double stop = tol * tol * bb;
+  int64_t iters = 0, restarts = 0;
+  double rr = 0.0;
+  bool breakdown = false;
+  while (true) {
+    // (re)start from the true residual r = b - A x, in binary64
+    if ((s = bs_helmholtz_apply(ctx, el, gs, d_geo, lambda, d_x, yL, r, st)) ||
+        (s = bs_axpy(ctx, BS_F64, n, 1.0, d_b, -1.0, r, st)) || (s = bs_norm(ctx, BS_F64, n, r, nullptr, scal, st)))
+      return s;
+    if ((s = check_hip(hipMemcpyAsync(&rr, scal, 8, hipMemcpyDeviceToHost, st), op))) return s;
+    if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+    if (rr <= stop || iters >= max_iter || breakdown) break;
+    if ((s = bs_copy(ctx, BS_F64, n, r, p, st))) return s;
+    CgState fin{};
+    const int64_t left = max_iter - iters;
+    if ((s = eng.run(scal, stop, static_cast<int32_t>(left < INT32_MAX ? left : INT32_MAX), &fin))) return s;
+    iters += fin.iters;
+    breakdown = fin.done == 2;
+    ++restarts;
+  }
+  if (res) {
+    res->iterations = iters;
+    res->outer_iterations = 0;
+    res->restarts = restarts > 0 ? restarts - 1 : 0;
+    res->rel_residual = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (rr > stop)
+    return fail(BS_ERR_NO_CONVERGENCE, "%s: relative residual %.3e after %lld iterations", op,
+                bb > 0.0 ? std::sqrt(rr / bb) : 0.0, static_cast<long long>(iters));
+  return BS_OK;
 }

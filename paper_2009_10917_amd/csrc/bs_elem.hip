@@ -45,14 +45,6 @@
 #include "bs_device.h"
 #include "bs_internal.h"
 
-struct bs_elem {
-  int device;
-  int N;
-  double gll_x[16], gll_w[16];  // GLL nodes and weights (N+1 used)
-  double gauss_x[16], gauss_w[16];
-  double* tables;  // device: the MFMA operand matrices (N <= 7), see kTab*
-};
-
 namespace bs {
 namespace {
 
@@ -262,39 +254,27 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave per element; four elements per workgroup.  map/xG give the
-// element's values (the fused scatter), yL receives A^e u.
+// One wave per element, four elements per workgroup, the workgroups
+// striding over the elements.  map/xG give the element's values (the fused
+// scatter), yL receives A^e u.  With DOT (the CG form) the workgroup also
+// leaves in partials[blockIdx.x] the compensated sum of u . A^e u over its
+// elements, which adds up to p . Z^T A_L Z p since masked copies read u = 0;
+// it returns at once when *done is set.
+template <bool DOT>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
     const double* __restrict__ tab, Rule8 rule, const int32_t* __restrict__ map, int64_t n_global,
     const double* __restrict__ geo, double lambda, const double* __restrict__ xG, double* __restrict__ yL,
-    int64_t n_elem, int P1) {
+    int64_t n_elem, int P1, const int32_t* __restrict__ done, double* __restrict__ partials) {
   __shared__ double lds[kWavesPerBlock][4][kTenPad];
+  if constexpr (DOT) {
+    if (*done) return;  // set only between launches: every workgroup leaves here or none
+  }
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
-  const bool live = e < n_elem;
   double* b0 = lds[wave][0];
   double* b1 = lds[wave][1];
   double* b2 = lds[wave][2];
   double* b3 = lds[wave][3];
   const int64_t P = static_cast<int64_t>(P1) * P1 * P1;
-
-  // element values through the map (masked or out-of-range ids read 0)
-  if (live) {
-    int32_t id[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int f = l + 64 * m, i = f & 7, j = (f >> 3) & 7, k = f >> 6;
-      id[m] = (i < P1 && j < P1 && k < P1) ? map[e * P + i + P1 * (j + P1 * k)] : -1;
-    }
-    double u[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) u[m] = (id[m] >= 0 && id[m] < n_global) ? xG[id[m]] : 0.0;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int f = l + 64 * m;
-      b0[tad(f & 7, (f >> 3) & 7, f >> 6)] = u[m];
-    }
-  }
   double aB[2], aBD[2], aDh[2], aDhT[2], aBtDt[4], aBt[2];
   operand(tab, kTabB, aB);
   operand(tab, kTabBD, aBD);
@@ -302,85 +282,134 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
   operand(tab, kTabDhT, aDhT);
   operand(tab, kTabBtDt, aBtDt);
   operand(tab, kTabBt, aBt);
-  Geo g{};
-  if (live) {
-    const double* q = geo + 7 * e;
-    g = Geo{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
-  }
-  wave_sync();
-  dvec4 acc[4];
-  // U = (B, B, B) u and G1 = (B, B, D) u: along k, along j, then [B; D] along i
-  zero(acc);
-  contract<2, 2>(b0, aB, acc);
-  store_rows<2>(b1, acc, 0);
-  wave_sync();
-  zero(acc);
-  contract<1, 2>(b1, aB, acc);
-  store_rows<1>(b0, acc, 0);
-  wave_sync();
-  zero(acc);
-  contract<0, 2>(b0, aBD, acc);
-  store_rows<0>(b1, acc, 0);  // U
-  store_rows<0>(b2, acc, 8);  // G1
-  wave_sync();
-  // G2 = Dh along j of U, G3 = Dh along k of U
-  zero(acc);
-  contract<1, 2>(b1, aDh, acc);
-  store_rows<1>(b0, acc, 0);
-  zero(acc);
-  contract<2, 2>(b1, aDh, acc);
-  store_rows<2>(b3, acc, 0);
-  wave_sync();
-  // quadrature-point values: V0 (b1), V1 (b2), V2 (b0), V3 (b3), in place
+  dev::DW<double> dot{0.0, 0.0};
+
+  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock; e0 < n_elem;
+       e0 += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+    const int64_t e = e0 + wave;
+    const bool live = e < n_elem;
+    // element values through the map (masked or out-of-range ids read 0)
+    double u[8];
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int f = l + 64 * m, a = f & 7, b = (f >> 3) & 7, c = f >> 6;
-    const int ad = tad(a, b, c);
-    const double W = (rule.w[a] * rule.w[b]) * rule.w[c];
-    const double U = b1[ad], d1 = b2[ad], d2 = b0[ad], d3 = b3[ad];
-    b1[ad] = ((lambda * g.detj) * W) * U;
-    b2[ad] = W * ((g.g11 * d1 + g.g12 * d2) + g.g13 * d3);
-    b0[ad] = W * ((g.g12 * d1 + g.g22 * d2) + g.g23 * d3);
-    b3[ad] = W * ((g.g13 * d1 + g.g23 * d2) + g.g33 * d3);
-  }
-  wave_sync();
-  // W1 = V0 + Dh_k^T V3, then W2 = W1 + Dh_j^T V2 (accumulated in place in b1)
-  load_rows<2>(b1, acc);
-  contract<2, 2>(b3, aDhT, acc);
-  wave_sync();
-  store_rows<2>(b1, acc, 0);
-  wave_sync();
-  load_rows<1>(b1, acc);
-  contract<1, 2>(b0, aDhT, acc);
-  wave_sync();
-  store_rows<1>(b1, acc, 0);
-  wave_sync();
-  // Y3 = B^T W2 + D^T V1 along i (K = 16: W2 then V1)
-  zero(acc);
-  {
-    double lo[2] = {aBtDt[0], aBtDt[1]}, hi[2] = {aBtDt[2], aBtDt[3]};
-    contract<0, 2>(b1, lo, acc);
-    contract<0, 2>(b2, hi, acc);
-  }
-  store_rows<0>(b0, acc, 0);
-  wave_sync();
-  zero(acc);
-  contract<1, 2>(b0, aBt, acc);
-  store_rows<1>(b3, acc, 0);
-  wave_sync();
-  zero(acc);
-  contract<2, 2>(b3, aBt, acc);
-  // y along k: register v < 2 of lane l holds node k = l/16 + 4v at
-  // (i, j) = (col % 8, col / 8); registers 2 and 3 hold the padding rows
-  if (live) {
+    for (int m = 0; m < 8; ++m) u[m] = 0.0;
+    if (live) {
+      int32_t id[8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int col = 16 * t + (l & 15), i = col & 7, j = col >> 3;
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int k = (l >> 4) + 4 * v;
-        if (i < P1 && j < P1 && k < P1) dev::st_nt(yL + e * P + i + P1 * (j + P1 * k), acc[t][v]);
+      for (int m = 0; m < 8; ++m) {
+        const int f = l + 64 * m, i = f & 7, j = (f >> 3) & 7, k = f >> 6;
+        id[m] = (i < P1 && j < P1 && k < P1) ? map[e * P + i + P1 * (j + P1 * k)] : -1;
       }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) u[m] = (id[m] >= 0 && id[m] < n_global) ? xG[id[m]] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int f = l + 64 * m;
+      b0[tad(f & 7, (f >> 3) & 7, f >> 6)] = u[m];
+    }
+    Geo g{};
+    if (live) {
+      const double* q = geo + 7 * e;
+      g = Geo{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+    }
+    wave_sync();
+    dvec4 acc[4];
+    // U = (B, B, B) u and G1 = (B, B, D) u: along k, along j, then [B; D] along i
+    zero(acc);
+    contract<2, 2>(b0, aB, acc);
+    store_rows<2>(b1, acc, 0);
+    wave_sync();
+    zero(acc);
+    contract<1, 2>(b1, aB, acc);
+    store_rows<1>(b0, acc, 0);
+    wave_sync();
+    zero(acc);
+    contract<0, 2>(b0, aBD, acc);
+    store_rows<0>(b1, acc, 0);  // U
+    store_rows<0>(b2, acc, 8);  // G1
+    wave_sync();
+    // G2 = Dh along j of U, G3 = Dh along k of U
+    zero(acc);
+    contract<1, 2>(b1, aDh, acc);
+    store_rows<1>(b0, acc, 0);
+    zero(acc);
+    contract<2, 2>(b1, aDh, acc);
+    store_rows<2>(b3, acc, 0);
+    wave_sync();
+    // quadrature-point values: V0 (b1), V1 (b2), V2 (b0), V3 (b3), in place
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int f = l + 64 * m, a = f & 7, b = (f >> 3) & 7, c = f >> 6;
+      const int ad = tad(a, b, c);
+      const double W = (rule.w[a] * rule.w[b]) * rule.w[c];
+      const double U = b1[ad], d1 = b2[ad], d2 = b0[ad], d3 = b3[ad];
+      b1[ad] = ((lambda * g.detj) * W) * U;
+      b2[ad] = W * ((g.g11 * d1 + g.g12 * d2) + g.g13 * d3);
+      b0[ad] = W * ((g.g12 * d1 + g.g22 * d2) + g.g23 * d3);
+      b3[ad] = W * ((g.g13 * d1 + g.g23 * d2) + g.g33 * d3);
+    }
+    wave_sync();
+    // W1 = V0 + Dh_k^T V3, then W2 = W1 + Dh_j^T V2 (accumulated in place in b1)
+    load_rows<2>(b1, acc);
+    contract<2, 2>(b3, aDhT, acc);
+    wave_sync();
+    store_rows<2>(b1, acc, 0);
+    wave_sync();
+    load_rows<1>(b1, acc);
+    contract<1, 2>(b0, aDhT, acc);
+    wave_sync();
+    store_rows<1>(b1, acc, 0);
+    wave_sync();
+    // Y3 = B^T W2 + D^T V1 along i (K = 16: W2 then V1)
+    zero(acc);
+    {
+      double lo[2] = {aBtDt[0], aBtDt[1]}, hi[2] = {aBtDt[2], aBtDt[3]};
+      contract<0, 2>(b1, lo, acc);
+      contract<0, 2>(b2, hi, acc);
+    }
+    store_rows<0>(b0, acc, 0);
+    wave_sync();
+    zero(acc);
+    contract<1, 2>(b0, aBt, acc);
+    store_rows<1>(b3, acc, 0);
+    wave_sync();
+    zero(acc);
+    contract<2, 2>(b3, aBt, acc);
+    if constexpr (DOT) {
+      // y back through LDS into the load's layout, beside the lane's u
+      store_rows<2>(b1, acc, 0);
+      wave_sync();
+      if (live) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int f = l + 64 * m, i = f & 7, j = (f >> 3) & 7, k = f >> 6;
+          if (i < P1 && j < P1 && k < P1) {
+            const double y = b1[tad(i, j, k)];
+            dev::st_nt(yL + e * P + i + P1 * (j + P1 * k), y);
+            dev::dw_acc_prod(dot, u[m], y);
+          }
+        }
+      }
+    } else if (live) {
+      // y along k: register v < 2 of lane l holds node k = l/16 + 4v at
+      // (i, j) = (col % 8, col / 8); registers 2 and 3 hold the padding rows
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 16 * t + (l & 15), i = col & 7, j = col >> 3;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int k = (l >> 4) + 4 * v;
+          if (i < P1 && j < P1 && k < P1) dev::st_nt(yL + e * P + i + P1 * (j + P1 * k), acc[t][v]);
+        }
+      }
+    }
+    wave_sync();  // this element's LDS reads before the next element's writes
+  }
+  if constexpr (DOT) {
+    dot = dev::block_reduce<kWavesPerBlock * 64>(dot);
+    if (threadIdx.x == 0) {
+      partials[2 * blockIdx.x] = dot.s;
+      partials[2 * blockIdx.x + 1] = dot.c;
     }
   }
 }
@@ -458,12 +487,36 @@ bs_status launch_local(bs_ctx* ctx, const bs_elem* el, int64_t n_elem, const int
   if (n_elem == 0) return BS_OK;
   Rule8 rule{};
   for (int a = 0; a <= el->N; ++a) rule.w[a] = el->gauss_w[a];
-  hipLaunchKernelGGL(k_helm_local, dim3(ceil_div(n_elem, kWavesPerBlock)), dim3(kWavesPerBlock * 64), 0, st,
-                     el->tables, rule, map, n_global, geo, lambda, xG, yL, n_elem, el->N + 1);
+  hipLaunchKernelGGL(k_helm_local<false>, dim3(ceil_div(n_elem, kWavesPerBlock)), dim3(kWavesPerBlock * 64), 0, st,
+                     el->tables, rule, map, n_global, geo, lambda, xG, yL, n_elem, el->N + 1, nullptr, nullptr);
   return check_launch("bs_helmholtz_local");
 }
 
 }  // namespace
+
+// Workgroups of the CG form of the local operator: few enough that one
+// workgroup adds their partial sums quickly, enough to keep every CU busy
+// (two workgroups fit a CU's LDS).
+constexpr int kHelmDotBlocks = 1024;
+
+int helm_dot_blocks(int64_t n_elem) {
+  const int64_t g = (n_elem + kWavesPerBlock - 1) / kWavesPerBlock;
+  return static_cast<int>(g < 1 ? 1 : (g < kHelmDotBlocks ? g : kHelmDotBlocks));
+}
+
+bs_status helm_apply_dot(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* geo, double lambda,
+                         const double* p, double* yL, double* Ap, double* partials, const int32_t* done,
+                         hipStream_t st) {
+  const int64_t P = static_cast<int64_t>(el->N + 1) * (el->N + 1) * (el->N + 1);
+  const int64_t n_elem = gs->n_local / P;
+  Rule8 rule{};
+  for (int a = 0; a <= el->N; ++a) rule.w[a] = el->gauss_w[a];
+  hipLaunchKernelGGL(k_helm_local<true>, dim3(helm_dot_blocks(n_elem)), dim3(kWavesPerBlock * 64), 0, st, el->tables,
+                     rule, gs->map, gs->n_global, geo, lambda, p, yL, n_elem, el->N + 1, done, partials);
+  if (bs_status s = check_launch("helmholtz cg")) return s;
+  return bs_gather(ctx, gs, BS_F64, yL, Ap, st);
+}
+
 }  // namespace bs
 
 using namespace bs;

@@ -161,6 +161,14 @@ struct bs_gs {
   int64_t n_pblocks;
 };
 
+struct bs_elem {
+  int device;
+  int N;
+  double gll_x[16], gll_w[16];  // GLL nodes and weights (N+1 used)
+  double gauss_x[16], gauss_w[16];
+  double* tables;  // device: the MFMA operand matrices of the local operator (N <= 7)
+};
+
 namespace bs {
 constexpr int kStage = 2048;  // values staged in LDS per gather workgroup
 constexpr int kRunCap = 256;  // row-id runs a gather workgroup takes from LDS (more: it reads the row ids)
@@ -181,4 +189,14 @@ constexpr int kGroupOrder = 8;
 inline int gs_order(int variant) { return (variant & kNoXcdRemap) ? 0 : (variant & kGroupOrder) ? 1 : 2; }
 
 void free_plan(bs_gs* gs);
+
+// The Helmholtz operator in the form CG uses (bs_elem.hip): yL = A_L Z p,
+// Ap = Z^T yL, and in partials the compensated pairs of p . Ap, one per
+// workgroup of the local operator (helm_dot_blocks of them, at most 1024);
+// the local operator returns at once when *done is set.  The caller checks
+// the arguments.  Asynchronous on st.
+int helm_dot_blocks(int64_t n_elem);
+bs_status helm_apply_dot(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* geo, double lambda,
+                         const double* p, double* yL, double* Ap, double* partials, const int32_t* done,
+                         hipStream_t st);
 }  // namespace bs

@@ -81,6 +81,7 @@ def test_host_checks_reject_bad_arguments_before_any_launch():
     assert L.bs_stencil7(None, 0, 3, 0.01, 16, 32, None) == INVALID
     assert L.bs_cg_solve(None, 3, 0.01, 16, 32, 1e-10, 10, None, None) == INVALID
     assert L.bs_cg_ir_solve(None, 1, 3, 0.01, 16, 32, 1e-10, 1e-4, 10, 10, None, None) == INVALID
+    assert L.bs_helmholtz_cg_solve(None, 16, 32, 48, 0.01, 64, 80, 1e-10, 10, None, None) == INVALID
     assert L.bs_ctx_create(0, None) == INVALID
     # destroying NULL handles is a no-op
     assert L.bs_ctx_destroy(None) == 0 and L.bs_gs_destroy(None) == 0

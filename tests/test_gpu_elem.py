@@ -171,3 +171,121 @@ def test_element_argument_checks(ctx):
     el.close()
     with pytest.raises(bs.BSError):
         bs.bs_elem_create(ctx, 16)
+
+
+def _interior_problem(K, N, seed):
+    """-Lap u = f on the unit cube, u = x(1-x) y(1-y) z(1-z) vanishing on the
+    boundary: every copy of a boundary node masked, b the consistent mass of
+    f against the interior test functions (all computed by the oracle)."""
+    ids = _mesh(K, N, seed)
+    X, Y, Z = elem.node_coordinates(K, N)
+    on_bnd = np.zeros(X.size, dtype=bool)
+    for c in (X, Y, Z):
+        on_bnd |= (np.abs(c) < 1e-14) | (np.abs(c - 1.0) < 1e-14)
+    masked = np.where(on_bnd[ids], -1, ids)
+    geo = elem.geometry_cube(K)
+    geo_mass = geo.copy()
+    geo_mass[:, :6] = 0.0
+    q = lambda t: t * (1.0 - t)  # noqa: E731
+    u = q(X) * q(Y) * q(Z)
+    f = 2.0 * (q(Y) * q(Z) + q(X) * q(Z) + q(X) * q(Y))
+    b = np.where(on_bnd, 0.0, elem.apply_assembled(N, geo_mass, 1.0, ids, f))
+    return masked, geo, u, b, on_bnd
+
+
+def _solve(ctx, N, ids, geo, lam, b, tol, max_iter=100000, x0=None, check=True):
+    NG = b.size
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ids.astype(np.int32)).cuda(), NG)
+    el = bs.bs_elem_create(ctx, N)
+    x = torch.zeros(NG, dtype=F64, device="cuda") if x0 is None else torch.from_numpy(x0.copy()).cuda()
+    try:
+        res = bs.bs_helmholtz_cg_solve(ctx, el, plan, torch.from_numpy(geo.ravel()).cuda(), lam,
+                                       torch.from_numpy(b).cuda(), x, tol, max_iter, check=check)
+        return to_host(x), res
+    finally:
+        el.close()
+        plan.close()
+
+
+@pytest.mark.parametrize("K,N,seed", [(2, 3, 3), (3, 5, 4), (2, 7, None)])
+def test_helmholtz_cg_recovers_a_polynomial_solution(ctx, K, N, seed):
+    # u lies in the discrete space (degree 2 per axis, N >= 2): the Galerkin
+    # solution is its interpolant, so the solve must return u at the nodes
+    masked, geo, u, b, on_bnd = _interior_problem(K, N, seed)
+    tol = 1e-12
+    x, res = _solve(ctx, N, masked, geo, 0.0, b, tol)
+    assert res["status"] == "BS_OK"
+    r = b - elem.apply_assembled(N, geo, 0.0, masked, x)
+    assert np.linalg.norm(r) <= tol * np.linalg.norm(b) * (1 + 1e-6)
+    assert np.all(x[on_bnd] == 0.0)
+    assert np.max(np.abs(x - u)) <= 1e-10
+    # the oracle's Algorithm 1 on the same system takes about as many steps
+    _, it_ref, _ = elem.helmholtz_cg(N, geo, 0.0, masked, b, tol=tol)
+    assert abs(res["iterations"] - it_ref) <= max(3, it_ref // 10), (res["iterations"], it_ref)
+
+
+@pytest.mark.parametrize("K,N,seed,lam", [(3, 4, 7, 0.5), (2, 7, 8, 10.0), (4, 2, 9, 0.01)])
+def test_helmholtz_cg_matches_the_oracle(ctx, K, N, seed, lam):
+    ids = _mesh(K, N, seed)
+    E, NL, NG = mesh.sizes(K, N)
+    geo = elem.geometry_cube(K)
+    b = bsgen.uniform(21, 12, NG)
+    tol = 1e-11
+    x, res = _solve(ctx, N, ids, geo, lam, b, tol)
+    assert res["status"] == "BS_OK" and res["iterations"] > 0
+    r = b - elem.apply_assembled(N, geo, lam, ids, x)
+    assert np.linalg.norm(r) <= tol * np.linalg.norm(b) * (1 + 1e-6)
+    assert abs(res["rel_residual"] - np.linalg.norm(r) / np.linalg.norm(b)) <= 1e-3 * tol
+    x_ref, it_ref, _ = elem.helmholtz_cg(N, geo, lam, ids, b, tol=tol)
+    assert abs(res["iterations"] - it_ref) <= max(3, it_ref // 10), (res["iterations"], it_ref)
+    assert np.linalg.norm(x - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+
+
+def test_helmholtz_cg_limits_and_start(ctx):
+    K, N, lam = 2, 4, 0.3
+    ids = _mesh(K, N, 10)
+    E, NL, NG = mesh.sizes(K, N)
+    geo = elem.geometry_cube(K)
+    b = bsgen.uniform(22, 12, NG)
+    # three iterations, then the limit: the record says so and x moved
+    x, res = _solve(ctx, N, ids, geo, lam, b, 1e-12, max_iter=3, check=False)
+    assert res["status"] == "BS_ERR_NO_CONVERGENCE" and res["iterations"] == 3
+    x3, _, _ = elem.helmholtz_cg(N, geo, lam, ids, b, tol=1e-30, max_iter=3)
+    assert np.linalg.norm(x - x3) <= 1e-10 * np.linalg.norm(x3)
+    # starting from a converged x takes no iteration
+    x_ref, _, _ = elem.helmholtz_cg(N, geo, lam, ids, b, tol=1e-12)
+    x2, res2 = _solve(ctx, N, ids, geo, lam, b, 1e-9, x0=x_ref)
+    assert res2["status"] == "BS_OK" and res2["iterations"] == 0
+    assert np.array_equal(x2, x_ref)
+    # b = 0 from x = 0: done at once, x stays 0
+    x0, res0 = _solve(ctx, N, ids, geo, lam, np.zeros(NG), 1e-9)
+    assert res0["iterations"] == 0 and not np.any(x0)
+
+
+def test_helmholtz_cg_argument_checks(ctx):
+    K, N = 2, 3
+    ids = _mesh(K, N, 1)
+    E, NL, NG = mesh.sizes(K, N)
+    plan = bs.bs_gs_create(ctx, torch.from_numpy(ids.astype(np.int32)).cuda(), NG)
+    el = bs.bs_elem_create(ctx, N)
+    geo = torch.from_numpy(elem.geometry_cube(K).ravel()).cuda()
+    b = torch.ones(NG, dtype=F64, device="cuda")
+    x = torch.zeros(NG, dtype=F64, device="cuda")
+    try:
+        for bad in ({"tol": 0.0}, {"max_iter": -1}):
+            args = {"tol": 1e-10, "max_iter": 10, **bad}
+            with pytest.raises(bs.BSError) as e:
+                bs.bs_helmholtz_cg_solve(ctx, el, plan, geo, 1.0, b, x, args["tol"], args["max_iter"])
+            assert e.value.status == 1
+        with pytest.raises(bs.BSError):  # x overlapping b
+            bs.bs_helmholtz_cg_solve(ctx, el, plan, geo, 1.0, b, b, 1e-10, 10)
+        with pytest.raises(ValueError):  # wrong length
+            bs.bs_helmholtz_cg_solve(ctx, el, plan, geo, 1.0, b[:-1], x[:-1], 1e-10, 10)
+        big = bs.bs_elem_create(ctx, 9)  # the local operator stops at N = 7
+        st = bs.lib.bs_helmholtz_cg_solve(ctx.handle, big.handle, plan.handle, geo.data_ptr(), 1.0, b.data_ptr(),
+                                          x.data_ptr(), 1e-10, 10, None, None)
+        assert st == 2
+        big.close()
+    finally:
+        el.close()
+        plan.close()

@@ -193,3 +193,72 @@ def test_lumped_mass(K, N, seed):
         ref[g] = acc
     assert np.array_equal(y, ref)
     assert np.array_equal(ops.gather(rs, ci, d * x[ids]), y)   # = gather(scatter(x) * d), bit for bit
+
+
+def test_masked_assembly_is_the_dense_product():
+    # Z as a 0/1 matrix (no entry in a masked copy's row), A_L block diagonal
+    K, N = 2, 2
+    ids = _mesh(K, N, 6).copy()
+    ids[::5] = -1
+    E, NL, NG = mesh.sizes(K, N)
+    P = (N + 1) ** 3
+    geo = elem.geometry_cube(K)
+    Zm = np.zeros((NL, NG))
+    live = np.flatnonzero(ids >= 0)
+    Zm[live, ids[live]] = 1.0
+    AL = np.zeros((NL, NL))
+    for e in range(E):
+        AL[e * P:(e + 1) * P, e * P:(e + 1) * P] = elem.element_blocks(N, geo[e], 0.4)
+    x = bsgen.uniform(7, 12, NG)
+    ref = Zm.T @ (AL @ (Zm @ x))
+    got = elem.apply_assembled(N, geo, 0.4, ids, x)
+    assert np.allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    # a global node whose copies are all masked has an empty row
+    dead = np.setdiff1d(np.arange(NG), ids[live])
+    assert dead.size > 0 and np.all(got[dead] == 0.0)
+
+
+def _interior_problem(K, N, seed):
+    """-Lap u = f on the unit cube, u = 0 on its boundary, with u =
+    x(1-x) y(1-y) z(1-z): every copy of a boundary node masked, b the
+    consistent mass of f against the interior test functions."""
+    ids = _mesh(K, N, seed)
+    X, Y, Z = elem.node_coordinates(K, N)
+    on_bnd = np.zeros(X.size, dtype=bool)
+    for c in (X, Y, Z):
+        on_bnd |= (np.abs(c) < 1e-14) | (np.abs(c - 1.0) < 1e-14)
+    masked = np.where(on_bnd[ids], -1, ids)
+    geo = elem.geometry_cube(K)
+    geo_mass = geo.copy()
+    geo_mass[:, :6] = 0.0  # no stiffness: the block is the consistent mass
+    q = lambda t: t * (1.0 - t)  # noqa: E731
+    u = q(X) * q(Y) * q(Z)
+    f = 2.0 * (q(Y) * q(Z) + q(X) * q(Z) + q(X) * q(Y))
+    b = np.where(on_bnd, 0.0, elem.apply_assembled(N, geo_mass, 1.0, ids, f))
+    return masked, geo, u, b, on_bnd
+
+
+@pytest.mark.parametrize("K,N,seed", [(2, 2, None), (2, 3, 3)])
+def test_helmholtz_cg_recovers_a_polynomial_solution(K, N, seed):
+    # u has degree 2 along each axis, so for N >= 2 it lies in the discrete
+    # space and the Galerkin solution is its interpolant (exact quadrature)
+    masked, geo, u, b, on_bnd = _interior_problem(K, N, seed)
+    x, it, res = elem.helmholtz_cg(N, geo, 0.0, masked, b, tol=1e-13)
+    assert res <= 1e-13
+    assert np.all(x[on_bnd] == 0.0)
+    assert np.max(np.abs(x - u)) <= 1e-12
+    assert it <= int((~on_bnd).sum())  # within the number of unknowns
+
+
+def test_helmholtz_cg_matches_a_dense_solve():
+    K, N, lam = 2, 3, 0.5
+    ids = _mesh(K, N, 2)
+    NG = (K * N + 1) ** 3
+    geo = elem.geometry_cube(K)
+    A = np.column_stack([elem.apply_assembled(N, geo, lam, ids, np.eye(NG)[:, j]) for j in range(NG)])
+    b = bsgen.uniform(9, 12, NG)
+    ref = np.linalg.solve(A, b)
+    x, it, res = elem.helmholtz_cg(N, geo, lam, ids, b, tol=1e-12)
+    assert res <= 1e-12
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(x - ref) <= 4 * kappa * 1e-12 * np.linalg.norm(ref)
