@@ -653,18 +653,26 @@ GATHER_VARIANT = 8
 
 
 def gather_sweep(args, np, torch, bs, bsgen):
-    """Gather on the K^3, N = 7 mesh in each row order: global order
-    (variant 1), the scatter tiles' visiting order (variant 0), and
-    lattice tiles of the given sizes ("tile", "tile:side" for cubic boxes or
-    "tile:bxXbyXbz", variant 0 after bs_gs_order_rows),
-    with and without the XCD renumbering.  --mesh chooses the element
-    layout: random (permuted and oriented, the benchmark's), orient
-    (lexicographic, oriented) or ident (lexicographic, unrotated).  One
-    JSON line per order; every output is checked against variant 1 bit for
-    bit."""
+    """Gather and scatter on the K^3, N = 7 mesh in each plan order.  The
+    gather: global row order (variant 1), the plan's default permuted order
+    (variant 0, and 8 with each XCD taking runs of 256 workgroups); the
+    scatter (the tune table's kernel, then the sorted-tile kernel with 2 or
+    4 tiles per workgroup in each of the three workgroup orders) in the
+    default tile order.  Then, for
+    each spec in turn, the plan is re-ordered and both are timed again:
+    "tile", "tile:side" or "tile:bxXbyXbz" sort the gather rows into lattice
+    tiles (bs_gs_order_rows; gather variants 0 and 4); "elem:G" orders rows
+    and tiles by elements in groups of G (bs_gs_order_elements with the
+    order derived from the map; gather variants 0 and 8).  --mesh chooses
+    the element layout: random (permuted and oriented, the benchmark's),
+    orient (lexicographic, oriented) or ident (lexicographic, unrotated).
+    One JSON line per (operation, order, variant); every output is checked
+    bit for bit against the first one.  Each timing is two warm-up calls and
+    --reps timed calls, in this order (for per-dispatch counters)."""
     K, N, seed = args.K, 7, args.seed
     E, M = K ** 3, K * N + 1
-    NL, NG = E * (N + 1) ** 3, M ** 3
+    P = (N + 1) ** 3
+    NL, NG = E * P, M ** 3
     ctx = bs.bs_ctx_create(0)
     perm = orient = None
     if args.mesh == "random":
@@ -680,29 +688,60 @@ def gather_sweep(args, np, torch, bs, bsgen):
     xL = torch.empty(NL, dtype=torch.float64, device="cuda")
     bsgen.device_uniform(xL, seed, 11)
     xG = torch.empty(NG, dtype=torch.float64, device="cuda")
-    alg = alg_bytes(0, NL, NG)["gather"]
+    bsgen.device_uniform(xG, seed, 12)
+    sL = torch.empty_like(xL)
+    alg = alg_bytes(0, NL, NG)
+    yG = torch.empty_like(xG)
+    # explicit launch shapes go to a context of their own; ctx keeps the tune table
+    fixed = bs.bs_ctx_create(0)
 
-    def run(variant):
-        bs.bs_ctx_set_tune(ctx, "gather", 1, 1 << 30, variant)
-        ms = _time_calls(lambda: bs.bs_gather(ctx, plan, xL, xG), args.reps, torch)[0] * 1e3
-        return ms
+    def run_gather(variant):
+        bs.bs_ctx_set_tune(fixed, "gather", 1, 1 << 30, variant)
+        return _time_calls(lambda: bs.bs_gather(fixed, plan, xL, yG), args.reps, torch)[0] * 1e3
 
-    def emit(order, variant, ms, same):
-        print(json.dumps({"gather_order": order, "variant": variant, "mesh": args.mesh, "K": K, "ms": round(ms, 4),
-                          "GB_s": round(alg / (ms * 1e-3) / 1e9, 1), "bit_equal_to_global_order": same}), flush=True)
+    def run_scatter(c=ctx):
+        return _time_calls(lambda: bs.bs_gs_scatter(c, plan, xG, sL), args.reps, torch)[0] * 1e3
 
-    ms = run(1)
-    ref = xG.clone()
-    emit("global", 1, ms, True)
-    ms = run(0)
-    emit("visiting", 0, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
+    def emit(op, order, variant, ms, same):
+        print(json.dumps({"op": op, "order": order, "variant": variant, "mesh": args.mesh, "K": K, "ms": round(ms, 4),
+                          "GB_s": round(alg[op] / (ms * 1e-3) / 1e9, 1), "bit_equal": same}), flush=True)
+
+    def same(a, b):
+        return torch.equal(a.view(torch.int64), b.view(torch.int64))
+
+    ms = run_gather(1)
+    ref = yG.clone()
+    emit("gather", "global", 1, ms, True)
+    for v in (0, 8):
+        ms = run_gather(v)
+        emit("gather", "plan default (groups of 9 visiting-order tiles)", v, ms, same(yG, ref))
+    ms = run_scatter()
+    sref = sL.clone()
+    emit("scatter", "plan default (tiles by smallest global id)", -1, ms, True)
+    for tpw in (2, 4):
+        for v in (0, 4, 8):  # workgroup orders: one range per XCD, dispatch order, runs of 256 per XCD
+            bs.bs_ctx_set_tune(fixed, "scatter", tpw, 1 << 30, v)
+            ms = run_scatter(fixed)
+            emit("scatter", f"plan default, {tpw} tiles per workgroup", v, ms, same(sL, sref))
     for spec in [t for t in args.gather_sweep.split(",") if t]:
-        tile, _, box = spec.partition(":")
-        box = tuple(int(v) for v in box.split("x")) if "x" in box else int(box or 0)
-        bs.bs_gs_order_rows(plan, M, M, M, int(tile), box)
-        for v in (0, 4):
-            ms = run(v)
-            emit(f"lattice tiles {spec}", v, ms, torch.equal(xG.view(torch.int64), ref.view(torch.int64)))
+        if spec.startswith("elem:"):
+            bs.bs_gs_order_elements(plan, P, None, int(spec[5:]))
+            variants = (0, 8)
+        else:
+            tile, _, box = spec.partition(":")
+            box = tuple(int(v) for v in box.split("x")) if "x" in box else int(box or 0)
+            bs.bs_gs_order_rows(plan, M, M, M, int(tile), box)
+            variants = (0, 4)
+        torch.cuda.synchronize()
+        for v in variants:
+            ms = run_gather(v)
+            emit("gather", spec, v, ms, same(yG, ref))
+        ms = run_scatter()
+        emit("scatter", spec, -1, ms, same(sL, sref))
+        bs.bs_ctx_set_tune(fixed, "scatter", 4, 1 << 30, 8)
+        ms = run_scatter(fixed)
+        emit("scatter", f"{spec}, 4 tiles per workgroup", 8, ms, same(sL, sref))
+    fixed.close()
     return 0
 
 
@@ -799,7 +838,9 @@ def main():
                     help="only the mixed-precision CG time-to-solution (225^3 shifted 7-point operator)")
     ap.add_argument("--no-cg", action="store_true", help="skip the mixed-precision CG section")
     ap.add_argument("--batch-only", action="store_true", help="only the batched step over 1024 box-mesh instances")
-    ap.add_argument("--gather-sweep", default="", help="comma-separated lattice tile sizes (tile, tile:side or tile:bxXbyXbz): time the gather's row orders")
+    ap.add_argument("--gather-sweep", default="",
+                    help="comma-separated plan orders after the default (tile, tile:side or tile:bxXbyXbz lattice "
+                         "tiles; elem:G element groups): time gather and scatter in each")
     ap.add_argument("--mesh", default="random", choices=("random", "orient", "ident"),
                     help="element layout for --gather-sweep")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched section")
