@@ -26,8 +26,10 @@
 // the one-workgroup scalar kernels.
 //
 // The scalars live in a device-side state; once it says done, the remaining
-// kernels of a batch return at once.  Batches of iterations are captured into
-// one HIP graph and replayed; the host reads the state once per batch.
+// kernels of a batch return at once.  Batches of 16, 8, 4 or 2 iterations
+// are captured into HIP graphs and replayed; the host reads the state after
+// each group of batches and sizes the next group from the rate at which r.r
+// has fallen (struct Batches).
 //
 // Iterative refinement (binary64 outer loop, inner CG in binary32 or
 // bfloat16 storage with binary32 arithmetic): r = b - A x and ||r|| in
@@ -56,7 +58,6 @@ using stencil::CgState;
 using stencil::Op7;
 using stencil::store_partial;
 
-constexpr int kBatch = 16;  // iterations per captured graph (even)
 // Workgroups of the update kernel when the next kernel forms beta at its
 // head (grid-stride): every workgroup of that kernel adds their partial
 // sums, so they stay few.
@@ -92,12 +93,33 @@ bs_status launch_stencil(int64_t m, double shift, const void* x, void* y, hipStr
 
 __global__ void k_cg_init(CgState* st, const double* rr, double stop_rr, int32_t max_iters) {
   if (threadIdx.x == 0) {
-    st->rr_slot[0] = st->rr_slot[1] = st->rr = *rr;
+    st->rr_slot[0] = st->rr_slot[1] = st->rr = st->rr0 = *rr;
     st->stop_rr = stop_rr;
     st->iters = 0;
     st->max_iters = max_iters;
     st->fresh = 1;
     st->done = (*rr <= stop_rr || max_iters <= 0) ? 1 : 0;
+    st->alpha = st->beta = st->pAp = 0.0;
+  }
+}
+
+// Start of the inner solve of a refinement step, on the device: scal[2] is
+// r.r of the binary64 residual, scal[0] rl.rl of its rounded direction.
+// The inner tolerance theta = max(inner_tol, 0.5 sqrt(stop / r.r)) (the last
+// step need not go below what the outer target asks for); the run is done
+// at once when the outer residual already meets stop.
+__global__ void k_ir_init(CgState* st, const double* scal, double stop, double inner_tol, int32_t max_inner) {
+  if (threadIdx.x == 0) {
+    const double rr = scal[2], rr0 = scal[0];
+    const double theta = fmax(inner_tol, 0.5 * sqrt(stop / rr));
+    const double stop_rr = theta * theta * rr0;
+    st->rr_slot[0] = st->rr_slot[1] = st->rr = st->rr0 = rr0;
+    st->outer_rr = rr;
+    st->stop_rr = stop_rr;
+    st->iters = 0;
+    st->max_iters = max_inner;
+    st->fresh = 1;
+    st->done = (rr <= stop || rr0 <= stop_rr || max_inner <= 0) ? 1 : 0;
     st->alpha = st->beta = st->pAp = 0.0;
   }
 }
@@ -299,6 +321,112 @@ struct DevMem {
   }
 };
 
+// Captured batches of CG iterations, 16, 8, 4 and 2 long (even, so that
+// the fused forms' direction is back in p after every batch).  A run starts
+// with a batch of 16; after each read-back of the state the host launches
+// at most 16 more, fewer when the mean rate at which r.r has fallen so far
+// says the run ends sooner, so that few iterations are launched after the
+// one that converges (each of those still costs a launch whose kernels
+// return at their head).  Larger steps from an early rate misjudge: r.r
+// need not fall steadily.
+struct Batches {
+  static constexpr int kCount = 4;
+  static constexpr int kSize[kCount] = {16, 8, 4, 2};
+  hipGraphExec_t exec[kCount] = {};
+
+  ~Batches() {
+    for (hipGraphExec_t e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+  }
+
+  // Capture each size; a size the runtime cannot capture runs eagerly.
+  template <class F>
+  bs_status capture(hipStream_t st, F&& enqueue) {
+    for (int w = 0; w < kCount; ++w) {
+      hipGraph_t graph = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      bs_status s = BS_OK;
+      for (int i = 0; i < kSize[w] && !s; ++i) s = enqueue(i & 1);
+      const hipError_t e1 = hipStreamEndCapture(st, &graph);
+      if (s) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e1 != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        continue;
+      }
+      const hipError_t e2 = hipGraphInstantiate(&exec[w], graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e2 != hipSuccess) {
+        exec[w] = nullptr;
+        (void)hipGetLastError();
+      }
+    }
+    return BS_OK;
+  }
+
+  template <class F>
+  bs_status launch(int w, hipStream_t st, F&& enqueue) {
+    if (exec[w]) return check_hip(hipGraphLaunch(exec[w], st), "cg graph launch");
+    bs_status s = BS_OK;
+    for (int i = 0; i < kSize[w] && !s; ++i) s = enqueue(i & 1);
+    return s ? s : check_launch("cg");
+  }
+
+  // Iterations to launch next: r.r fell from rr0 to rr over iters
+  // iterations; at that mean rate, with a margin, until stop_rr.  (r.r
+  // need not fall monotonically, and a read-back costs about as much as
+  // five idle iterations, so the margin is generous.)
+  static int64_t next_iterations(const CgState& c) {
+    int64_t k = kSize[0];
+    if (c.iters > 0 && c.rr > 0.0 && c.rr < c.rr0 && c.stop_rr > 0.0 && c.rr > c.stop_rr) {
+      const double need = std::log(c.stop_rr / c.rr) / (std::log(c.rr / c.rr0) / c.iters);
+      k = need < 4096.0 ? static_cast<int64_t>(std::ceil(need * 1.3)) + 4 : 4096;
+    }
+    return k;
+  }
+
+  // Launch at least k iterations (at most the state's limit): whole batches
+  // of 16, the rest rounded up to one smaller batch (each graph launch adds
+  // a gap of its own).
+  template <class F>
+  bs_status launch_at_least(int64_t k, const CgState* c, hipStream_t st, F&& enqueue) {
+    if (c) {
+      const int64_t left = static_cast<int64_t>(c->max_iters) - c->iters;
+      if (k > left) k = left;
+    }
+    if (k < 1) k = 1;
+    bs_status s = BS_OK;
+    for (; k >= kSize[0] && !s; k -= kSize[0]) s = launch(0, st, enqueue);
+    if (k > 0 && !s) {
+      int w = kCount - 1;
+      while (w > 0 && kSize[w] < k) --w;
+      s = launch(w, st, enqueue);
+    }
+    return s;
+  }
+
+  // Iterate until the state reports done, starting with at least `first`
+  // iterations (a caller that knows how many the last run took passes that);
+  // returns the final state in *out.
+  template <class F>
+  bs_status run(hipStream_t st, CgState* state, CgState* out, F&& enqueue, int64_t first = kSize[0]) {
+    bs_status s = launch_at_least(first, nullptr, st, enqueue);
+    while (!s) {
+      s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
+      if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
+      if (s || out->done) break;
+      const int64_t k = next_iterations(*out);
+      s = launch_at_least(k < kSize[0] ? k : kSize[0], out, st, enqueue);
+    }
+    return s;
+  }
+};
+
 // Runs CG iterations in dtype T on vectors owned by the caller.  With the
 // direction update folded into the operator, p alternates between p and p2:
 // iteration i reads the old direction from one and writes the new one to
@@ -321,11 +449,7 @@ struct CgEngine {
   Span sp;
   Op7<T, true, kFuse> op;
   int g_upd = 1, g_dir = 1;
-  hipGraphExec_t exec = nullptr;
-
-  ~CgEngine() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-  }
+  Batches batches;
 
   // The operator's partial sums (p.Ap) go to the first kMaxReduceBlocks
   // pairs of the context's buffer, the update's (r.r) to the next ones.
@@ -375,40 +499,32 @@ struct CgEngine {
     // the previous kernel's pairs, so those grids stay small
     g_upd = grid_for(sp, 4, kFuse ? kUpdateBlocks : kMaxReduceBlocks);
     g_dir = grid_for(sp, 1, 1 << 30);
-    // capture kBatch iterations into one graph
-    hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager fallback
-    for (int i = 0; i < kBatch; ++i) enqueue_iteration(i & 1);
-    const hipError_t e1 = hipStreamEndCapture(st, &graph);
-    if (e1 != hipSuccess || !graph) {
-      (void)hipGetLastError();
+    return batches.capture(st, [this](int parity) {
+      enqueue_iteration(parity);
       return BS_OK;
-    }
-    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e2 != hipSuccess) {
-      exec = nullptr;
-      (void)hipGetLastError();
-    }
-    return BS_OK;
+    });
   }
 
-  // Iterate until the state reports done; returns the final state.
-  bs_status run(double stop_rr, int32_t max_iters, CgState* out) {
+  // The same for a state some earlier kernel has initialised.
+  bs_status run_initialised(CgState* out) {
+    return batches.run(st, state, out, [this](int parity) {
+      enqueue_iteration(parity);
+      return BS_OK;
+    });
+  }
+
+  // Iterate until the state reports done, launching at least `first`
+  // iterations before the first read-back; returns the final state.
+  bs_status run(double stop_rr, int32_t max_iters, CgState* out, int64_t first = Batches::kSize[0]) {
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, st, state, rr_dev, stop_rr, max_iters);
-    bs_status s = check_launch("cg");
-    while (!s) {
-      if (exec) {
-        s = check_hip(hipGraphLaunch(exec, st), "cg graph launch");
-      } else {
-        for (int i = 0; i < kBatch; ++i) enqueue_iteration(i & 1);
-        s = check_launch("cg");
-      }
-      if (!s) s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
-      if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
-      if (!s && out->done) break;
-    }
-    return s;
+    if (bs_status s = check_launch("cg")) return s;
+    return batches.run(
+        st, state, out,
+        [this](int parity) {
+          enqueue_iteration(parity);
+          return BS_OK;
+        },
+        first);
   }
 };
 
@@ -432,11 +548,7 @@ struct HelmEngine {
   CgState* state;
   Span sp;
   int g_op = 1, g_upd = 1, g_dir = 1;
-  hipGraphExec_t exec = nullptr;
-
-  ~HelmEngine() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-  }
+  Batches batches;
 
   double* op_partials() const { return ctx->partials; }
   double* upd_partials() const { return ctx->partials + 2 * static_cast<size_t>(kMaxReduceBlocks); }
@@ -465,42 +577,13 @@ struct HelmEngine {
     g_op = helm_dot_blocks(gs->n_local / ((el->N + 1) * (el->N + 1) * (el->N + 1)));
     g_upd = grid_for(sp, 4, kMaxReduceBlocks);
     g_dir = grid_for(sp, 1, 1 << 30);
-    hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return BS_OK;  // eager
-    bs_status s = BS_OK;
-    for (int i = 0; i < kBatch && !s; ++i) s = enqueue_iteration(i & 1);
-    const hipError_t e1 = hipStreamEndCapture(st, &graph);
-    if (s) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return s;
-    }
-    if (e1 != hipSuccess || !graph) {
-      (void)hipGetLastError();
-      return BS_OK;
-    }
-    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e2 != hipSuccess) {
-      exec = nullptr;
-      (void)hipGetLastError();
-    }
-    return BS_OK;
+    return batches.capture(st, [this](int parity) { return enqueue_iteration(parity); });
   }
 
   bs_status run(const double* rr_dev, double stop_rr, int32_t max_iters, CgState* out) {
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, st, state, rr_dev, stop_rr, max_iters);
-    bs_status s = check_launch("bs_helmholtz_cg_solve");
-    while (!s) {
-      if (exec) {
-        s = check_hip(hipGraphLaunch(exec, st), "bs_helmholtz_cg_solve graph launch");
-      } else {
-        for (int i = 0; i < kBatch && !s; ++i) s = enqueue_iteration(i & 1);
-      }
-      if (!s) s = check_hip(hipMemcpyAsync(out, state, sizeof(CgState), hipMemcpyDeviceToHost, st), "cg");
-      if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
-      if (!s && out->done) break;
-    }
-    return s;
+    if (bs_status s = check_launch("bs_helmholtz_cg_solve")) return s;
+    return batches.run(st, state, out, [this](int parity) { return enqueue_iteration(parity); });
   }
 };
 
@@ -616,23 +699,29 @@ bs_status ir_solve(bs_ctx* ctx, int64_t m, double shift, const double* b, double
     hipLaunchKernelGGL((k_ir_prepare<T>), dim3(gp), dim3(kBlock), 0, st, r64, scal + 2, n, rl, p, d, ctx->partials);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(kFinishBlock), 0, st, ctx->partials, static_cast<int>(gp), scal);
     if ((s = check_launch(op))) return s;
-    double h[3] = {0.0, 0.0, 0.0};
-    if ((s = check_hip(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, st), op))) return s;
-    if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
-    rr = h[2];
-    const double rr0 = h[0];
-    if (rr <= stop || outer >= max_outer) break;
+    if (outer >= max_outer) {
+      if ((s = check_hip(hipMemcpyAsync(&rr, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st), op))) return s;
+      if ((s = check_hip(hipStreamSynchronize(st), op))) return s;
+      break;
+    }
+    // the inner tolerance and the outer test are taken on the device, so
+    // the inner iterations follow without a read-back; the host learns the
+    // outer residual from the state after the run (a run that starts done
+    // costs one batch of kernels that return at their head)
+    hipLaunchKernelGGL(k_ir_init, dim3(1), dim3(64), 0, st, state, scal, stop, inner_tol,
+                       static_cast<int32_t>(max_inner));
+    if ((s = check_launch(op))) return s;
+    CgState fin{};
+    if ((s = eng.run_initialised(&fin))) return s;
+    rr = fin.outer_rr;
+    inner += fin.iters;
+    if (rr <= stop) break;
     // outer residual must halve within three refinement steps
     if (outer >= 3 && std::sqrt(rr) > 0.5 * std::sqrt(hist[(outer - 3) % 4])) {
       stagnated = true;
       break;
     }
     hist[outer % 4] = rr;
-    // the last step need not go below what the outer target asks for
-    const double theta = std::max(inner_tol, 0.5 * std::sqrt(stop / rr));
-    CgState fin{};
-    if ((s = eng.run(theta * theta * rr0, static_cast<int32_t>(max_inner), &fin))) return s;
-    inner += fin.iters;
     hipLaunchKernelGGL((k_add_scaled<T>), dim3(blocks_for(n)), dim3(kBlock), 0, st, x, scal + 2,
                        static_cast<const E*>(d), n);
     if ((s = check_launch(op))) return s;

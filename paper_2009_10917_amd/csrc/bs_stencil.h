@@ -48,6 +48,8 @@ struct CgState {
   int32_t iters;      // completed updates, written by the update kernel only
   int32_t max_iters;
   int32_t fresh;      // 1 until the first update of a run (its direction is p = r)
+  double rr0;         // r.r at the start of the run (for the host's batch sizes)
+  double outer_rr;    // refinement: r.r of the binary64 residual the run started from
 };
 
 // Where a kernel finds the partial sums of the previous one: G compensated
