@@ -284,33 +284,50 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
   operand(tab, kTabBt, aBt);
   dev::DW<double> dot{0.0, 0.0};
 
-  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock; e0 < n_elem;
-       e0 += static_cast<int64_t>(gridDim.x) * kWavesPerBlock) {
+  // The loads of an element are issued an iteration ahead of its work (its
+  // map ids two ahead, since the x_G loads need them), so that their
+  // latency hides behind the contractions of the element before.
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+  auto load_ids = [&](int64_t e, int32_t (&id)[8]) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int f = l + 64 * m, i = f & 7, j = (f >> 3) & 7, k = f >> 6;
+      id[m] = (e < n_elem && i < P1 && j < P1 && k < P1) ? map[e * P + i + P1 * (j + P1 * k)] : -1;
+    }
+  };
+  // masked, padding and out-of-range ids read 0
+  auto load_vals = [&](const int32_t (&id)[8], double (&u)[8]) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) u[m] = (id[m] >= 0 && id[m] < n_global) ? xG[id[m]] : 0.0;
+  };
+  auto load_geo = [&](int64_t e) {
+    if (e >= n_elem) return Geo{};
+    const double* q = geo + 7 * e;
+    return Geo{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+  };
+  const int64_t e_first = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  int32_t id_next[8];
+  double u_cur[8];
+  Geo g_cur;
+  load_ids(e_first, id_next);
+  load_vals(id_next, u_cur);
+  g_cur = load_geo(e_first);
+  load_ids(e_first + stride, id_next);
+
+  for (int64_t e0 = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock; e0 < n_elem; e0 += stride) {
     const int64_t e = e0 + wave;
     const bool live = e < n_elem;
-    // element values through the map (masked or out-of-range ids read 0)
-    double u[8];
+    double u[8], u_next[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) u[m] = 0.0;
-    if (live) {
-      int32_t id[8];
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int f = l + 64 * m, i = f & 7, j = (f >> 3) & 7, k = f >> 6;
-        id[m] = (i < P1 && j < P1 && k < P1) ? map[e * P + i + P1 * (j + P1 * k)] : -1;
-      }
-#pragma unroll
-      for (int m = 0; m < 8; ++m) u[m] = (id[m] >= 0 && id[m] < n_global) ? xG[id[m]] : 0.0;
-    }
+    for (int m = 0; m < 8; ++m) u[m] = u_cur[m];
+    const Geo g = g_cur;
+    load_vals(id_next, u_next);
+    g_cur = load_geo(e + stride);
+    load_ids(e + 2 * stride, id_next);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int f = l + 64 * m;
       b0[tad(f & 7, (f >> 3) & 7, f >> 6)] = u[m];
-    }
-    Geo g{};
-    if (live) {
-      const double* q = geo + 7 * e;
-      g = Geo{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
     }
     wave_sync();
     dvec4 acc[4];
@@ -404,6 +421,8 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void k_helm_local(
       }
     }
     wave_sync();  // this element's LDS reads before the next element's writes
+#pragma unroll
+    for (int m = 0; m < 8; ++m) u_cur[m] = u_next[m];
   }
   if constexpr (DOT) {
     dot = dev::block_reduce<kWavesPerBlock * 64>(dot);
@@ -481,28 +500,38 @@ bs_status check_f64(const char* op, const char* name, const void* p, int64_t n) 
   return check_vec(op, name, p, n, BS_F64);
 }
 
+// Workgroups of the local operator: every resident one (two fit a CU's
+// LDS), each striding over the elements so that its loads run ahead of its
+// work, and no more than there are groups of four elements.
+template <bool DOT>
+int helm_blocks(int64_t n_elem) {
+  int device = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_helm_local<DOT>, kWavesPerBlock * 64, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    (void)hipGetLastError();
+    per_cu = 2;
+    cus = 256;
+  }
+  const int64_t resident = static_cast<int64_t>(per_cu < 1 ? 1 : per_cu) * (cus < 1 ? 1 : cus);
+  const int64_t g = (n_elem + kWavesPerBlock - 1) / kWavesPerBlock;
+  return static_cast<int>(g < 1 ? 1 : (g < resident ? g : resident));
+}
+
 bs_status launch_local(bs_ctx* ctx, const bs_elem* el, int64_t n_elem, const int32_t* map, int64_t n_global,
                        const double* geo, double lambda, const double* xG, double* yL, hipStream_t st) {
   (void)ctx;
   if (n_elem == 0) return BS_OK;
   Rule8 rule{};
   for (int a = 0; a <= el->N; ++a) rule.w[a] = el->gauss_w[a];
-  hipLaunchKernelGGL(k_helm_local<false>, dim3(ceil_div(n_elem, kWavesPerBlock)), dim3(kWavesPerBlock * 64), 0, st,
+  hipLaunchKernelGGL(k_helm_local<false>, dim3(helm_blocks<false>(n_elem)), dim3(kWavesPerBlock * 64), 0, st,
                      el->tables, rule, map, n_global, geo, lambda, xG, yL, n_elem, el->N + 1, nullptr, nullptr);
   return check_launch("bs_helmholtz_local");
 }
 
 }  // namespace
 
-// Workgroups of the CG form of the local operator: few enough that one
-// workgroup adds their partial sums quickly, enough to keep every CU busy
-// (two workgroups fit a CU's LDS).
-constexpr int kHelmDotBlocks = 1024;
-
-int helm_dot_blocks(int64_t n_elem) {
-  const int64_t g = (n_elem + kWavesPerBlock - 1) / kWavesPerBlock;
-  return static_cast<int>(g < 1 ? 1 : (g < kHelmDotBlocks ? g : kHelmDotBlocks));
-}
+int helm_dot_blocks(int64_t n_elem) { return helm_blocks<true>(n_elem); }
 
 bs_status helm_apply_dot(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* geo, double lambda,
                          const double* p, double* yL, double* Ap, double* partials, const int32_t* done,

@@ -192,9 +192,10 @@ void free_plan(bs_gs* gs);
 
 // The Helmholtz operator in the form CG uses (bs_elem.hip): yL = A_L Z p,
 // Ap = Z^T yL, and in partials the compensated pairs of p . Ap, one per
-// workgroup of the local operator (helm_dot_blocks of them, at most 1024);
+// workgroup of the local operator (helm_dot_blocks of them: the resident
+// workgroups, about 512);
 // the local operator returns at once when *done is set.  The caller checks
-// the arguments.  Asynchronous on st.
+// the arguments.  Asynchronous on st (on the current device).
 int helm_dot_blocks(int64_t n_elem);
 bs_status helm_apply_dot(bs_ctx* ctx, const bs_elem* el, const bs_gs* gs, const double* geo, double lambda,
                          const double* p, double* yL, double* Ap, double* partials, const int32_t* done,
