@@ -103,7 +103,10 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * 256-thread workgroups), 2 each XCD takes one contiguous range of blocks
  * over the whole grid, 3 acts as 0; plus the workgroup size: + 4 for 128
  * threads, + 8 for 512 threads, otherwise 256 (operands not 16-byte aligned
- * with one another always run 256-thread workgroups).  For gather and scatter, variant is a kernel choice,
+ * with one another always run 256-thread workgroups); plus 16 for ordinary
+ * cached loads and stores instead of nontemporal ones (faster when the
+ * operands stay in the 256 MB last-level cache from one call to the next,
+ * the small-size regime of Section 4's launch-latency model).  For gather and scatter, variant is a kernel choice,
  * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
  * 256 blocks per XCD in every group of 2048, instead of one contiguous range
  * of blocks per XCD.  Gather: 0 = rows in the plan's permuted order (by default

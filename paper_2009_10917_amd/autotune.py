@@ -18,7 +18,10 @@ Candidates:
                       same launch); from 2^20 elements on, each shape also with
                       the two XCD-grouped workgroup orders (variants 1 and 2);
                       every shape with 256-, 128- and 512-thread workgroups
-                      (variant + 0, + 4, + 8)
+                      (variant + 0, + 4, + 8); up to 2^24 elements each of
+                      those also with cached instead of nontemporal accesses
+                      (+ 16: vectors the next call finds in the 256 MB
+                      last-level cache)
   batch             items per claim {1, 2, 4, 8} x workgroup cap {128, 256, 512,
                       resident} of the persistent batched step, on the 1024
                       box-mesh instances (binary64, binary32)
@@ -53,7 +56,10 @@ STREAM_OPS = ("copy", "axpy", "norm", "dot", "cg_update")
 REDUCTIONS = ("norm", "dot", "cg_update")
 DTYPES = (("f64", 0), ("f32", 1), ("bf16", 2))
 # bucket lower bounds and the length timed in each bucket
-BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 24, 1 << 26), (1 << 27, 1 << 28))
+BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 23, 1 << 24), (1 << 25, 1 << 26),
+           (1 << 27, 1 << 28))
+# cached accesses (+16) are tried where an operation's vectors can stay in the 256 MB last-level cache
+CACHED_MAX_N = 1 << 24
 MESH_K = ((0, 4), (1 << 20, 16), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
 DEFAULTS = {"copy": (1, 1 << 30, 0), "axpy": (1, 1 << 30, 0), "norm": (8, 4096, 0), "dot": (8, 4096, 0),
             "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (2, 1 << 30, 1),
@@ -116,6 +122,8 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
                 orders = (0, 1, 2) if n >= (1 << 20) else (0,)
                 # workgroup size: + 0 for 256 threads, + 4 for 128, + 8 for 512
                 variants = [o + b for b in (0, 4, 8) for o in orders]
+                if n <= CACHED_MAX_N:
+                    variants += [v + 16 for v in variants]
                 for u in (1, 2, 4, 8):
                     for g in caps:
                         for v in variants:

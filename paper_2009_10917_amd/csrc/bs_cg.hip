@@ -63,6 +63,9 @@ using stencil::store_partial;
 // sums, so they stay few.
 constexpr int kUpdateBlocks = 1024;
 
+// Size of the last-level cache (MALL) of the device the solver is built for.
+constexpr double kLastLevelCache = 256.0 * 1024 * 1024;
+
 // Storage types whose CG folds the direction update into the operator.
 template <class T>
 constexpr bool kFuseDirection = !std::is_same<T, double>::value;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_after_update(const double* __r
 // x += alpha p, r -= alpha Ap and the partial sums of r.r.  With HEAD, alpha
 // = r.r / p.Ap is formed at the head from the operator's partial sums;
 // otherwise it is read from the state (k_after_pAp).
-template <class T, int V, int U, bool HEAD>
+template <class T, int V, int U, bool HEAD, bool NT = true>
 __global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums, typename Storage<T>::E* __restrict__ x,
                                                     const typename Storage<T>::E* __restrict__ p,
                                                     typename Storage<T>::E* __restrict__ r,
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums,
     if (st->done) return;
     alpha = st->alpha;
   }
-  CgOp<T, V, false> op{{}, static_cast<C>(alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
+  CgOp<T, V, false, NT> op{{}, static_cast<C>(alpha), x, p, r, Ap, nullptr, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U>(op, sp);
   store_partial(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials);
 }
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(CgState* st, CgLink op_sums,
 // p = r + beta p.  With HEAD, beta = r'.r' / r.r and the stopping test are
 // formed at the head from the update's partial sums; otherwise beta is read
 // from the state (k_after_update).
-template <class T, int V, int U, bool HEAD>
+template <class T, int V, int U, bool HEAD, bool NT = true>
 __global__ __launch_bounds__(kBlock) void k_direction(CgState* st, CgLink upd_sums,
                                                       const typename Storage<T>::E* __restrict__ r,
                                                       typename Storage<T>::E* __restrict__ p, Span sp) {
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_direction(CgState* st, CgLink upd_su
     if (st->done) return;
     beta = st->beta;
   }
-  AxpyOp<T, V> op{{}, C(1), static_cast<C>(beta), r, p, sp.head};
+  AxpyOp<T, V, NT> op{{}, C(1), static_cast<C>(beta), r, p, sp.head};
   stream_loop<U>(op, sp);
 }
 
@@ -448,6 +451,9 @@ struct CgEngine {
   double* rr_dev;  // scratch scalar
   Span sp;
   Op7<T, true, kFuse> op;
+  // the solve's vectors fit the 256 MB last-level cache: the streaming
+  // steps use cached accesses (they find the operator's output there)
+  bool cached = false;
   int g_upd = 1, g_dir = 1;
   Batches batches;
 
@@ -470,6 +476,9 @@ struct CgEngine {
       if (sp.vwidth == 1)
         hipLaunchKernelGGL((k_cg_step<T, 1, 4, true>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r,
                            Ap, sp, upd_partials());
+      else if (cached)
+        hipLaunchKernelGGL((k_cg_step<T, S::V, 4, true, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x,
+                           p_cur, r, Ap, sp, upd_partials());
       else
         hipLaunchKernelGGL((k_cg_step<T, S::V, 4, true>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur,
                            r, Ap, sp, upd_partials());
@@ -479,6 +488,9 @@ struct CgEngine {
       if (sp.vwidth == 1)
         hipLaunchKernelGGL((k_cg_step<T, 1, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur, r,
                            Ap, sp, upd_partials());
+      else if (cached)
+        hipLaunchKernelGGL((k_cg_step<T, S::V, 4, false, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x,
+                           p_cur, r, Ap, sp, upd_partials());
       else
         hipLaunchKernelGGL((k_cg_step<T, S::V, 4, false>), dim3(g_upd), dim3(kBlock), 0, st, state, from_op, x, p_cur,
                            r, Ap, sp, upd_partials());
@@ -486,6 +498,9 @@ struct CgEngine {
       const CgLink none{nullptr, 0, parity ^ 1};
       if (sp.vwidth == 1)
         hipLaunchKernelGGL((k_direction<T, 1, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
+      else if (cached)
+        hipLaunchKernelGGL((k_direction<T, S::V, 1, false, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r,
+                           p, sp);
       else
         hipLaunchKernelGGL((k_direction<T, S::V, 1, false>), dim3(g_dir), dim3(kBlock), 0, st, state, none, r, p, sp);
     }
@@ -493,6 +508,7 @@ struct CgEngine {
 
   bs_status prepare() {
     sp = make_span<T>(n, {x, r, p, p2, Ap});
+    cached = static_cast<double>(kFuse ? 5 : 4) * n * sizeof(E) <= kLastLevelCache;
     if (!op.prepare(m, ctx->device))
       return fail(BS_ERR_INVALID_ARG, "cg: grid side %lld is too large", static_cast<long long>(m));
     // with the scalars formed at the kernels' heads every workgroup reads all

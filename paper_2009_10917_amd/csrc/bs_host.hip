@@ -108,8 +108,8 @@ bs_status check_tune(const char* op, int unroll, int grid_cap, int variant) {
   if (!(unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8))
     return fail(BS_ERR_INVALID_ARG, "%s: unroll must be 1, 2, 4 or 8", op);
   if (grid_cap < 1) return fail(BS_ERR_INVALID_ARG, "%s: grid_cap must be positive", op);
-  if (variant < 0 || variant > 11 || (variant & kVariantMask) == 3 || ((variant & kNoXcdRemap) && (variant & kGroupOrder)))
-    return fail(BS_ERR_INVALID_ARG, "%s: variant must be 0, 1 or 2, optionally plus 4 or 8", op);
+  if (variant < 0 || variant > 27 || (variant & kVariantMask) == 3 || ((variant & kNoXcdRemap) && (variant & kGroupOrder)))
+    return fail(BS_ERR_INVALID_ARG, "%s: variant must be 0, 1 or 2, optionally plus 4 or 8, optionally plus 16", op);
   return BS_OK;
 }
 

@@ -30,33 +30,33 @@ namespace {
 
 using namespace ops;
 
-template <class T, int V, int U, int NB>
+template <class T, int V, int U, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_copy(const typename Storage<T>::E* __restrict__ x,
                                                  typename Storage<T>::E* __restrict__ y, Span sp) {
-  CopyOp<T, V> op{{}, x, y, sp.head};
+  CopyOp<T, V, NT> op{{}, x, y, sp.head};
   stream_loop<U, NB>(op, sp);
 }
 
 // ---------------------------------------------------------------- BS2 AXPY
 
 
-template <class T, int V, int U, int NB>
+template <class T, int V, int U, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_axpy(typename Storage<T>::C alpha, const typename Storage<T>::E* __restrict__ x,
                                                  typename Storage<T>::C beta, typename Storage<T>::E* __restrict__ y,
                                                  Span sp) {
-  AxpyOp<T, V> op{{}, alpha, beta, x, y, sp.head};
+  AxpyOp<T, V, NT> op{{}, alpha, beta, x, y, sp.head};
   stream_loop<U, NB>(op, sp);
 }
 
 // ---------------------------------------------------------------- BS3 norm
 
 
-template <class T, int V, int U, bool W, int NB>
+template <class T, int V, int U, bool W, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_norm(const typename Storage<T>::E* __restrict__ x,
                                                  const typename Storage<T>::E* __restrict__ w, Span sp,
                                                  double* partials, double* out) {
   using C = typename Storage<T>::C;
-  NormOp<T, V, W> op{{}, x, w, sp.head, DW<C>{C(0), C(0)}};
+  NormOp<T, V, W, NT> op{{}, x, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
   dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
@@ -64,12 +64,12 @@ __global__ __launch_bounds__(NB) void k_norm(const typename Storage<T>::E* __res
 // ---------------------------------------------------------------- BS4 inner product
 
 
-template <class T, int V, int U, int NB>
+template <class T, int V, int U, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_dot(const typename Storage<T>::E* __restrict__ x,
                                                 const typename Storage<T>::E* __restrict__ y, Span sp,
                                                 double* partials, double* out) {
   using C = typename Storage<T>::C;
-  DotOp<T, V> op{{}, x, y, sp.head, DW<C>{C(0), C(0)}};
+  DotOp<T, V, NT> op{{}, x, y, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
   dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(NB) void k_dot(const typename Storage<T>::E* __rest
 // ---------------------------------------------------------------- BS5 fused CG update
 
 
-template <class T, int V, int U, bool W, int NB>
+template <class T, int V, int U, bool W, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_cg_update(typename Storage<T>::C alpha, typename Storage<T>::E* __restrict__ x,
                                                       const typename Storage<T>::E* __restrict__ p,
                                                       typename Storage<T>::E* __restrict__ r,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NB) void k_cg_update(typename Storage<T>::C alpha, 
                                                       const typename Storage<T>::E* __restrict__ w, Span sp,
                                                       double* partials, double* out) {
   using C = typename Storage<T>::C;
-  CgOp<T, V, W> op{{}, alpha, x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
+  CgOp<T, V, W, NT> op{{}, alpha, x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
   dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
@@ -108,15 +108,15 @@ __device__ __forceinline__ double dev_scalar(const DevScalar& s) {
   return s.h * q;
 }
 
-template <class T, int V, int U, int NB>
+template <class T, int V, int U, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_axpy_dev(DevScalar a, const typename Storage<T>::E* __restrict__ x,
                                                      DevScalar b, typename Storage<T>::E* __restrict__ y, Span sp) {
   using C = typename Storage<T>::C;
-  AxpyOp<T, V> op{{}, static_cast<C>(dev_scalar(a)), static_cast<C>(dev_scalar(b)), x, y, sp.head};
+  AxpyOp<T, V, NT> op{{}, static_cast<C>(dev_scalar(a)), static_cast<C>(dev_scalar(b)), x, y, sp.head};
   stream_loop<U, NB>(op, sp);
 }
 
-template <class T, int V, int U, bool W, int NB>
+template <class T, int V, int U, bool W, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_cg_update_dev(DevScalar a, typename Storage<T>::E* __restrict__ x,
                                                           const typename Storage<T>::E* __restrict__ p,
                                                           typename Storage<T>::E* __restrict__ r,
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NB) void k_cg_update_dev(DevScalar a, typename Stor
                                                           const typename Storage<T>::E* __restrict__ w, Span sp,
                                                           double* partials, double* out) {
   using C = typename Storage<T>::C;
-  CgOp<T, V, W> op{{}, static_cast<C>(dev_scalar(a)), x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
+  CgOp<T, V, W, NT> op{{}, static_cast<C>(dev_scalar(a)), x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
   dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
 }
@@ -199,45 +199,60 @@ inline int stream_block(const Span& sp, int variant) {
   return s == 1 ? 128 : s == 2 ? 512 : kBlock;
 }
 
-// Launch `K<T, V, U, NB>` for the runtime unroll, packet width and block size.
-#define BS_DISPATCH_U(KERNEL_ARGS, VN, u, NB, grid, stream, ...)                                          \
+// Cache policy of a streaming launch: nontemporal accesses unless the tune
+// variant asks for cached ones (+16, the small-size regime).
+constexpr int kCached = 16;
+inline bool stream_nt(int variant) { return (variant & kCached) == 0; }
+
+// Launch `K<T, V, U, NB, NT>` for the runtime unroll, packet width, block
+// size and cache policy.
+#define BS_DISPATCH_U(KERNEL_ARGS, VN, u, NB, NT, grid, stream, ...)                                      \
   do {                                                                                                     \
     if ((u) == 8) {                                                                                        \
-      hipLaunchKernelGGL((KERNEL_ARGS(VN, 8, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 8, NB, NT)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);      \
     } else if ((u) == 4) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL_ARGS(VN, 4, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 4, NB, NT)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);      \
     } else if ((u) == 2) {                                                                                 \
-      hipLaunchKernelGGL((KERNEL_ARGS(VN, 2, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 2, NB, NT)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);      \
     } else {                                                                                               \
-      hipLaunchKernelGGL((KERNEL_ARGS(VN, 1, NB)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);          \
+      hipLaunchKernelGGL((KERNEL_ARGS(VN, 1, NB, NT)), dim3(grid), dim3(NB), 0, stream, __VA_ARGS__);      \
     }                                                                                                      \
   } while (0)
 
-#define BS_DISPATCH_NB(KERNEL_ARGS, T, sp, u, nb, grid, stream, ...)                                       \
+#define BS_DISPATCH_NT(KERNEL_ARGS, VN, u, NB, nt, grid, stream, ...)                                     \
+  do {                                                                                                     \
+    if (nt)                                                                                                \
+      BS_DISPATCH_U(KERNEL_ARGS, VN, u, NB, true, grid, stream, __VA_ARGS__);                              \
+    else                                                                                                   \
+      BS_DISPATCH_U(KERNEL_ARGS, VN, u, NB, false, grid, stream, __VA_ARGS__);                             \
+  } while (0)
+
+#define BS_DISPATCH_NB(KERNEL_ARGS, T, sp, u, nb, nt, grid, stream, ...)                                   \
   do {                                                                                                     \
     constexpr int VN = Storage<T>::V;                                                                      \
     if ((sp).vwidth == 1) {                                                                                \
-      hipLaunchKernelGGL((KERNEL_ARGS(1, 4, kBlock)), dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);   \
+      hipLaunchKernelGGL((KERNEL_ARGS(1, 4, kBlock, true)), dim3(grid), dim3(kBlock), 0, stream,            \
+                         __VA_ARGS__);                                                                     \
     } else if ((nb) == 128) {                                                                              \
-      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 128, grid, stream, __VA_ARGS__);                                   \
+      BS_DISPATCH_NT(KERNEL_ARGS, VN, u, 128, nt, grid, stream, __VA_ARGS__);                              \
     } else if ((nb) == 512) {                                                                              \
-      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 512, grid, stream, __VA_ARGS__);                                   \
+      BS_DISPATCH_NT(KERNEL_ARGS, VN, u, 512, nt, grid, stream, __VA_ARGS__);                              \
     } else {                                                                                               \
-      BS_DISPATCH_U(KERNEL_ARGS, VN, u, 256, grid, stream, __VA_ARGS__);                                   \
+      BS_DISPATCH_NT(KERNEL_ARGS, VN, u, 256, nt, grid, stream, __VA_ARGS__);                              \
     }                                                                                                      \
   } while (0)
 
 
-#define K_COPY(V, U, NB) k_copy<T, V, U, NB>
-#define K_AXPY(V, U, NB) k_axpy<T, V, U, NB>
-#define K_DOT(V, U, NB) k_dot<T, V, U, NB>
-#define K_AXPY_DEV(V, U, NB) k_axpy_dev<T, V, U, NB>
-#define K_NORM_W(V, U, NB) k_norm<T, V, U, true, NB>
-#define K_NORM(V, U, NB) k_norm<T, V, U, false, NB>
-#define K_UPD_W(V, U, NB) k_cg_update<T, V, U, true, NB>
-#define K_UPD(V, U, NB) k_cg_update<T, V, U, false, NB>
-#define K_UPD_DEV_W(V, U, NB) k_cg_update_dev<T, V, U, true, NB>
-#define K_UPD_DEV(V, U, NB) k_cg_update_dev<T, V, U, false, NB>
+#define K_COPY(V, U, NB, NT) k_copy<T, V, U, NB, NT>
+#define K_AXPY(V, U, NB, NT) k_axpy<T, V, U, NB, NT>
+#define K_DOT(V, U, NB, NT) k_dot<T, V, U, NB, NT>
+#define K_AXPY_DEV(V, U, NB, NT) k_axpy_dev<T, V, U, NB, NT>
+#define K_NORM_W(V, U, NB, NT) k_norm<T, V, U, true, NB, NT>
+#define K_NORM(V, U, NB, NT) k_norm<T, V, U, false, NB, NT>
+#define K_UPD_W(V, U, NB, NT) k_cg_update<T, V, U, true, NB, NT>
+#define K_UPD(V, U, NB, NT) k_cg_update<T, V, U, false, NB, NT>
+#define K_UPD_DEV_W(V, U, NB, NT) k_cg_update_dev<T, V, U, true, NB, NT>
+#define K_UPD_DEV(V, U, NB, NT) k_cg_update_dev<T, V, U, false, NB, NT>
 
 template <class T> constexpr int dtype_index() { return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2; }
 
@@ -248,8 +263,9 @@ bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t s
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
-  BS_DISPATCH_NB(K_COPY, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
+  BS_DISPATCH_NB(K_COPY, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
   return check_launch("bs_copy");
 }
 
@@ -261,8 +277,9 @@ bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double b
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
-  BS_DISPATCH_NB(K_AXPY, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
+  BS_DISPATCH_NB(K_AXPY, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
               static_cast<typename Storage<T>::E*>(y), sp);
   return check_launch("bs_axpy");
 }
@@ -275,12 +292,13 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (w)
-    BS_DISPATCH_NB(K_NORM_W, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
+    BS_DISPATCH_NB(K_NORM_W, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
                   ctx->partials, out);
   else
-    BS_DISPATCH_NB(K_NORM, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
+    BS_DISPATCH_NB(K_NORM, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
                   ctx->partials, out);
   return finish(ctx, g, out, st, "bs_norm");
 }
@@ -293,8 +311,9 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
-  BS_DISPATCH_NB(K_DOT, T, sp, u, nb, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
+  BS_DISPATCH_NB(K_DOT, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
   return finish(ctx, g, out, st, "bs_dot");
 }
 
@@ -310,16 +329,17 @@ bs_status launch_cg_update(int64_t n, double alpha, void* x, const void* p, void
   sp.order = stream_order(variant);
   const int u = norm_unroll(unroll);
   const int nb = stream_block(sp, variant);
+  const bool nt = stream_nt(variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (g > cap)
     return fail(BS_ERR_INVALID_ARG, "%s: %d workgroups need more reduction pairs than the %d the buffer holds", op, g,
                 cap);
   if (w)
-    BS_DISPATCH_NB(K_UPD_W, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+    BS_DISPATCH_NB(K_UPD_W, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w),
                   sp, partials, out);
   else
-    BS_DISPATCH_NB(K_UPD, T, sp, u, nb, g, st, static_cast<C>(alpha), static_cast<E*>(x),
+    BS_DISPATCH_NB(K_UPD, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p),
                   sp, partials, out);
   return finish_on(partials, sums, g, out, st, op);
@@ -377,8 +397,9 @@ bs_status run_axpy_dev(bs_ctx* ctx, int64_t n, DevScalar a, const void* x, DevSc
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
-  BS_DISPATCH_NB(K_AXPY_DEV, T, sp, u, nb, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
+  BS_DISPATCH_NB(K_AXPY_DEV, T, sp, u, nb, nt, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
   return check_launch("bs_axpy_dev");
 }
 
@@ -392,12 +413,13 @@ bs_status run_cg_update_dev(bs_ctx* ctx, int64_t n, DevScalar a, void* x, const 
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
+  const bool nt = stream_nt(tn.variant);
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (w)
-    BS_DISPATCH_NB(K_UPD_DEV_W, T, sp, u, nb, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+    BS_DISPATCH_NB(K_UPD_DEV_W, T, sp, u, nb, nt, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
                   static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w), sp, ctx->partials, out);
   else
-    BS_DISPATCH_NB(K_UPD_DEV, T, sp, u, nb, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
+    BS_DISPATCH_NB(K_UPD_DEV, T, sp, u, nb, nt, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
                   static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p), sp, ctx->partials, out);
   return finish(ctx, g, out, st, "bs_cg_update_dev");
 }

@@ -78,23 +78,32 @@ __device__ __forceinline__ void stream_loop(Op& op, const Span& sp) {
   }
 }
 
-template <class T, int V>
+// NT: every packet is touched once per call, so by default the accesses
+// are nontemporal; vectors that the next calls will touch again while they
+// still fit the 256 MB last-level cache (the small-size regime) run faster
+// with ordinary cached accesses (NT = false).
+template <class T, int V, bool NT = true>
 struct Base {
   using S = Storage<T>;
   using E = typename S::E;
   using C = typename S::C;
   using Vec = typename dev::VecOf<E, V>::type;
-  // packet j of the operand that starts at p (after the scalar head); every
-  // packet is touched once, so the accesses are nontemporal
-  __device__ static Vec ld(const E* p, int64_t j) { return dev::ld_nt(reinterpret_cast<const Vec*>(p) + j); }
-  __device__ static void st(E* p, int64_t j, const Vec& v) { dev::st_nt(reinterpret_cast<Vec*>(p) + j, v); }
+  // packet j of the operand that starts at p (after the scalar head)
+  __device__ static Vec ld(const E* p, int64_t j) {
+    if constexpr (NT) return dev::ld_nt(reinterpret_cast<const Vec*>(p) + j);
+    else return reinterpret_cast<const Vec*>(p)[j];
+  }
+  __device__ static void st(E* p, int64_t j, const Vec& v) {
+    if constexpr (NT) dev::st_nt(reinterpret_cast<Vec*>(p) + j, v);
+    else reinterpret_cast<Vec*>(p)[j] = v;
+  }
 };
 
 // ---------------------------------------------------------------- BS1 copy
 
-template <class T, int V>
-struct CopyOp : Base<T, V> {
-  using B = Base<T, V>;
+template <class T, int V, bool NT = true>
+struct CopyOp : Base<T, V, NT> {
+  using B = Base<T, V, NT>;
   using E = typename B::E;
   struct Regs {
     typename B::Vec a;
@@ -107,9 +116,9 @@ struct CopyOp : Base<T, V> {
   __device__ void scalar(int64_t e) const { y[e] = x[e]; }
 };
 
-template <class T, int V>
-struct AxpyOp : Base<T, V> {
-  using B = Base<T, V>;
+template <class T, int V, bool NT = true>
+struct AxpyOp : Base<T, V, NT> {
+  using B = Base<T, V, NT>;
   using S = typename B::S;
   using E = typename B::E;
   using C = typename B::C;
@@ -133,9 +142,9 @@ struct AxpyOp : Base<T, V> {
   __device__ void scalar(int64_t e) const { y[e] = S::store(f(x[e], y[e])); }
 };
 
-template <class T, int V, bool W>
-struct NormOp : Base<T, V> {
-  using B = Base<T, V>;
+template <class T, int V, bool W, bool NT = true>
+struct NormOp : Base<T, V, NT> {
+  using B = Base<T, V, NT>;
   using S = typename B::S;
   using E = typename B::E;
   using C = typename B::C;
@@ -165,9 +174,9 @@ struct NormOp : Base<T, V> {
   __device__ void scalar(int64_t e) { add(x[e], W ? w[e] : E{}); }
 };
 
-template <class T, int V>
-struct DotOp : Base<T, V> {
-  using B = Base<T, V>;
+template <class T, int V, bool NT = true>
+struct DotOp : Base<T, V, NT> {
+  using B = Base<T, V, NT>;
   using S = typename B::S;
   using E = typename B::E;
   using C = typename B::C;
@@ -190,9 +199,9 @@ struct DotOp : Base<T, V> {
   __device__ void scalar(int64_t e) { dev::dw_acc_prod(acc, S::load(x[e]), S::load(y[e])); }
 };
 
-template <class T, int V, bool W>
-struct CgOp : Base<T, V> {
-  using B = Base<T, V>;
+template <class T, int V, bool W, bool NT = true>
+struct CgOp : Base<T, V, NT> {
+  using B = Base<T, V, NT>;
   using S = typename B::S;
   using E = typename B::E;
   using C = typename B::C;

@@ -289,7 +289,9 @@ def test_error_paths(ctx):
     assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 3) == INVALID
     assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 12) == INVALID  # dispatch order and XCD runs at once
     assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 11) == INVALID
-    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 16) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 16 + 3) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 16 + 12) == INVALID
+    assert L.bs_ctx_set_tune(h, 0, 0, 4, 16, 32) == INVALID
     # n == 0 with NULL pointers is a valid no-op; reductions write 0
     assert L.bs_copy(h, 0, 0, None, None, s) == 0
     assert L.bs_dot(h, 0, 0, None, None, o.data_ptr(), s) == 0
@@ -330,3 +332,33 @@ def test_workgroup_sizes_agree(dtype, n, unroll, cap):
                 assert rel_err(b, a) <= 1e-14, (v, a, b)
             else:  # compensated binary32 sums of n terms of magnitude <= 1: within 2u * n each
                 assert abs(b - a) <= 4 * 2.0 ** -24 * n, (v, a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("n,unroll,cap,order", [(1000003, 4, 1 << 30, 0), (4194305, 8, 4096, 1), (777, 1, 1, 2)])
+def test_cache_policies_agree(dtype, n, unroll, cap, order):
+    # cached accesses (variant + 16) against nontemporal ones: every vector and
+    # every reduction bit-identical (same packets, same order of additions)
+    res = {}
+    for v in (order, order + 16, order + 4 + 16):
+        ctx = bs.bs_ctx_create(0)
+        try:
+            for op in ("copy", "axpy", "norm", "dot", "cg_update"):
+                bs.bs_ctx_set_tune(ctx, op, unroll, cap, v)
+            x, y, p, Ap, w = (dev_uniform(n, s, lo=0.0 if s == 5 else -1.0, dtype=dtype) for s in (1, 2, 3, 4, 5))
+            z = torch.empty_like(x)
+            bs.bs_copy(ctx, x, z)
+            o = torch.zeros(3, dtype=torch.float64, device="cuda")
+            bs.bs_norm(ctx, x, w, o[0:1])
+            bs.bs_dot(ctx, x, y, o[1:2])
+            bs.bs_cg_update(ctx, 0.37, z, p, y, Ap, w, o[2:3])
+            bs.bs_axpy(ctx, 0.37, x, 0.61, p)
+            res[v] = [bits(to_host(t)) for t in (z, y, p)] + [bits(to_host(o))]
+        finally:
+            torch.cuda.synchronize()
+            ctx.close()
+    for a, b in zip(res[order], res[order + 16]):
+        assert np.array_equal(a, b)
+    # with a different workgroup size only the vectors stay bit-identical
+    for a, b in zip(res[order][:3], res[order + 4 + 16][:3]):
+        assert np.array_equal(a, b)
