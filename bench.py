@@ -1005,7 +1005,8 @@ def main():
     cnb = {1: 128, 2: 512}.get((cvar >> 2) & 3, 256)
     corder = cvar & 3 if (cvar & 3) in (1, 2) else 0
     cg_grid = max(1, min(cg_cap, 1 << 21, -(-(n // 2) // (cnb * cu))))
-    roofline = {"bound": "hbm", "kernel": f"k_cg_update<double, 2, {cu}, true, {cnb}>", "workgroups": cg_grid,
+    cnt = "false" if cvar & 16 else "true"  # nontemporal accesses unless the tune entry asks for cached ones
+    roofline = {"bound": "hbm", "kernel": f"k_cg_update<double, 2, {cu}, true, {cnb}, {cnt}>", "workgroups": cg_grid,
                 "workgroup_order": corder, "workgroup_size": cnb, "achieved": cg_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(cg_gbs / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "alg_bytes_per_launch": byt["cg_update"],
