@@ -109,7 +109,8 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * the small-size regime of Section 4's launch-latency model).  For gather and scatter, variant is a kernel choice,
  * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
  * 256 blocks per XCD in every group of 2048, instead of one contiguous range
- * of blocks per XCD.  Gather: 0 = rows in the plan's permuted order (by default
+ * of blocks per XCD, plus 16 for cached accesses in kernel 0 (as for the streaming
+ * operations).  Gather: 0 = rows in the plan's permuted order (by default
  * in groups of 9 consecutive scatter tiles of the visiting order, each row
  * in the first group holding one of its copies, rows of a group in ascending
  * global id; bs_gs_order_rows and bs_gs_order_elements replace it; falls

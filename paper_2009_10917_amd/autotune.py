@@ -27,7 +27,8 @@ Candidates:
                       box-mesh instances (binary64, binary32)
   gather, scatter   kernel variant {0, 1, 2}, each in the three workgroup orders
                     (one range per XCD, +4 dispatch order, +8 runs of 256 blocks
-                    per XCD), on permuted and oriented N = 7 meshes, with
+                    per XCD), and up to 2^24 local entries kernel 0 with cached
+                    accesses (+16), on permuted and oriented N = 7 meshes, with
                     plans as bs_gs_create builds them (a caller that applies
                     bs_gs_order_rows chooses gather variant 0 itself); for the
                     scatter's tile variants (0, 1) also 1, 2 or 4 tiles per
@@ -60,7 +61,7 @@ BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 23, 1 << 
            (1 << 27, 1 << 28))
 # cached accesses (+16) are tried where an operation's vectors can stay in the 256 MB last-level cache
 CACHED_MAX_N = 1 << 24
-MESH_K = ((0, 4), (1 << 20, 16), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
+MESH_K = ((0, 4), (1 << 20, 16), (1 << 24, 32), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
 DEFAULTS = {"copy": (1, 1 << 30, 0), "axpy": (1, 1 << 30, 0), "norm": (8, 4096, 0), "dot": (8, 4096, 0),
             "cg_update": (4, 65536, 0), "gather": (1, 1 << 30, 1), "scatter": (2, 1 << 30, 1),
             "batch": (8, 1 << 30, 0)}
@@ -166,7 +167,10 @@ def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
             for op, call in (("gather", lambda: bs.bs_gather(ctx, plan, xL, xG)),
                              ("scatter", lambda: bs.bs_gs_scatter(ctx, plan, xG, xL))):
                 times = {}
-                for v in (0, 1, 2, 4, 5, 6, 8, 9, 10):
+                variants = [0, 1, 2, 4, 5, 6, 8, 9, 10]
+                if NL <= CACHED_MAX_N:  # kernel 0 with cached accesses (+ 16)
+                    variants += [16, 20, 24]
+                for v in variants:
                     unrolls = (1,) if op == "gather" else ((1, 2, 4) if v % 4 < 2 else (1, 4))
                     for u in unrolls:
                         bs.bs_ctx_set_tune(ctx, op, u, 1 << 30, v)

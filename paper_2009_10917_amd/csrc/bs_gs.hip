@@ -27,6 +27,10 @@
 //   1  the same tiles, read in local order
 //   2  local order over the whole vector, `unroll` entries per thread
 //
+// For gather kernel 0 and scatter kernel 0, tune variant + 16 selects cached
+// instead of nontemporal accesses (arrays that stay in the last-level cache
+// between calls).
+//
 // Workgroups are renumbered per XCD so that neighbouring blocks, which share
 // cache lines, run on the same XCD's L2: by default each XCD takes one
 // contiguous range of blocks; the tune variant may instead keep the dispatch
@@ -42,6 +46,21 @@ namespace {
 
 using dev::bf16;
 using dev::Storage;
+
+// Accesses of the index words and of the values the kernels stream: by
+// default nontemporal; with NT = false (tune variant + 16, for meshes whose
+// arrays stay in the 256 MB last-level cache from one call to the next)
+// ordinary cached ones.
+template <bool NT, class X>
+__device__ __forceinline__ X ld_pol(const X* p) {
+  if constexpr (NT) return dev::ld_nt(p);
+  else return *p;
+}
+template <bool NT, class X>
+__device__ __forceinline__ void st_pol(X* p, const X& v) {
+  if constexpr (NT) dev::st_nt(p, v);
+  else *p = v;
+}
 
 // ---------------------------------------------------------------- BS6 gather, rows in visiting order
 
@@ -69,7 +88,7 @@ __device__ __forceinline__ C row_sum(const C* v, int32_t a, int32_t e) {
 // row-start bits, and every row adds its copies from LDS in CSR order, i.e.
 // in ascending local index, as the definition of x_G = Z^T x_L does.
 // Seven workgroups per CU: 21.5 KB of LDS each, and at most 72 VGPRs.
-template <class T>
+template <class T, bool NT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_gather_perm(
     const uint32_t* __restrict__ words, const int32_t* __restrict__ segs, const int32_t* __restrict__ segoff,
     const int32_t* __restrict__ prows, const int32_t* __restrict__ runoff, const int32_t* __restrict__ runs,
@@ -94,7 +113,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
   const int64_t b = dev::block_order(blockIdx.x, gridDim.x, wg_order);
   if (b >= n_pblocks) {  // rows without copies: +0.0
     const int64_t q = n_nzrows + (b - n_pblocks) * kBlock + t;
-    if (q < n_rows) dev::st_nt(xG + prows[q], S::store(C(0)));
+    if (q < n_rows) st_pol<NT>(xG + prows[q], S::store(C(0)));
     return;
   }
   const int64_t w0 = pbnz0[b];
@@ -113,7 +132,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
   //    entry, so that no load waits behind a branch
   uint32_t wd[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) wd[k] = dev::ld_nt(words + w0 + min(t + k * kBlock, n - 1));
+  for (int k = 0; k < L; ++k) wd[k] = ld_pol<NT>(words + w0 + min(t + k * kBlock, n - 1));
   int32_t gid[L];
   if (by_runs) {
     for (int i = t; i < nr; i += kBlock) {
@@ -193,7 +212,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     const int32_t q = t + k * kBlock;
-    if (q < nrows) dev::st_nt(xG + gid[k], S::store(row_sum<C>(lds, sst[q], sst[q + 1])));
+    if (q < nrows) st_pol<NT>(xG + gid[k], S::store(row_sum<C>(lds, sst[q], sst[q + 1])));
   }
 }
 
@@ -323,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ r
 // values fetched in that order and put in place through LDS, and the tile's
 // entries are written contiguously.  The plan stores the pairs in visiting
 // order, so they are loaded alongside the tile's index, not after it.
-template <class E, int TPW, bool PACKED>
+template <class E, int TPW, bool PACKED, bool NT>
 __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __restrict__ order,
                                                            const int32_t* __restrict__ tgid,
                                                            const uint16_t* __restrict__ tloc,
@@ -360,12 +379,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
       const int q = min(static_cast<int>(threadIdx.x) + k * kBlock, kTile - 1);
       const int64_t v = min(t0 + i, n_tiles - 1);
       if (PACKED) {
-        const uint32_t w = dev::ld_nt(tword + v * kTile + q);
+        const uint32_t w = ld_pol<NT>(tword + v * kTile + q);
         g[i][k] = g0[i] + static_cast<int32_t>(w >> 9);
         o[i][k] = static_cast<uint16_t>(w & 511u);
       } else {
-        g[i][k] = dev::ld_nt(tgid + v * kTile + q);
-        o[i][k] = dev::ld_nt(tloc + v * kTile + q);
+        g[i][k] = ld_pol<NT>(tgid + v * kTile + q);
+        o[i][k] = ld_pol<NT>(tloc + v * kTile + q);
       }
     }
   E v[TPW][P];
@@ -394,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sorted(const int32_t* __rest
 #pragma unroll
     for (int k = 0; k < P; ++k) {
       const int q = threadIdx.x + k * kBlock;
-      if (q < ntile && has[i][q]) dev::st_nt(xL + base + q, val[i][q]);
+      if (q < ntile && has[i][q]) st_pol<NT>(xL + base + q, val[i][q]);
     }
   }
 }
@@ -469,12 +488,18 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
   if (kind == 0) {
     const int64_t zero_blocks = (gs->n_global - gs->n_nzrows + kBlock - 1) / kBlock;
     const int64_t grid = gs->n_pblocks + zero_blocks;
-    if (grid > 0)
-      hipLaunchKernelGGL((k_gather_perm<T>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
-                         gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff, gs->perm_runs,
-                         gs->perm_bstart, gs->perm_bnz0,
-                         static_cast<const E*>(xL), static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global,
-                         order);
+    if (grid > 0) {
+      if (tn.variant & kCachedAccess)
+        hipLaunchKernelGGL((k_gather_perm<T, false>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
+                           gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff,
+                           gs->perm_runs, gs->perm_bstart, gs->perm_bnz0, static_cast<const E*>(xL),
+                           static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global, order);
+      else
+        hipLaunchKernelGGL((k_gather_perm<T, true>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
+                           gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff,
+                           gs->perm_runs, gs->perm_bstart, gs->perm_bnz0, static_cast<const E*>(xL),
+                           static_cast<E*>(xG), gs->n_pblocks, gs->n_nzrows, gs->n_global, order);
+    }
   } else if (kind == 1) {
     hipLaunchKernelGGL((k_gather_nnz<T>), dim3(static_cast<unsigned int>(gs->n_blocks)), dim3(kBlock), 0, st,
                        gs->row_starts, gs->col_ids, gs->block_starts, static_cast<const E*>(xL), static_cast<E*>(xG),
@@ -507,19 +532,25 @@ void scatter_by_map(int unroll, const int32_t* map, int64_t n_local, int64_t n_g
   else launch_scatter_map<E, 1>(map, n_local, n_global, cap, xG, xL, st);
 }
 
-template <class E, int TPW>
-void launch_scatter_sorted(const bs_gs* gs, int wg_order, const void* xG, void* xL, hipStream_t st) {
+template <class E, int TPW, bool NT>
+void launch_scatter_sorted_nt(const bs_gs* gs, int wg_order, const void* xG, void* xL, hipStream_t st) {
   const unsigned int grid = static_cast<unsigned int>((gs->n_tiles + TPW - 1) / TPW);
   if (gs->tile_packed)
-    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, true>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
+    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, true, NT>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
                        static_cast<const int32_t*>(nullptr), static_cast<const uint16_t*>(nullptr), gs->tile_word,
                        gs->tile_min, gs->tile_count, static_cast<const E*>(xG), static_cast<E*>(xL), gs->n_local,
                        gs->n_tiles, wg_order);
   else
-    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, false>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
+    hipLaunchKernelGGL((k_scatter_sorted<E, TPW, false, NT>), dim3(grid), dim3(kBlock), 0, st, gs->tile_order,
                        gs->tile_gid, gs->tile_loc, static_cast<const uint32_t*>(nullptr),
                        static_cast<const int32_t*>(nullptr), gs->tile_count, static_cast<const E*>(xG),
                        static_cast<E*>(xL), gs->n_local, gs->n_tiles, wg_order);
+}
+
+template <class E, int TPW>
+void launch_scatter_sorted(const bs_gs* gs, int wg_order, bool cached, const void* xG, void* xL, hipStream_t st) {
+  if (cached) launch_scatter_sorted_nt<E, TPW, false>(gs, wg_order, xG, xL, st);
+  else launch_scatter_sorted_nt<E, TPW, true>(gs, wg_order, xG, xL, st);
 }
 
 template <class E, int TPW>
@@ -542,9 +573,10 @@ bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hi
     // and the kernels' padding lanes read xG[0])
     if (gs->n_tiles > 0 && gs->n_global > 0) {
       if (kind == 0) {
-        if (tpw == 4) launch_scatter_sorted<E, 4>(gs, order, xG, xL, st);
-        else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, order, xG, xL, st);
-        else launch_scatter_sorted<E, 1>(gs, order, xG, xL, st);
+        const bool cached = (tn.variant & kCachedAccess) != 0;
+        if (tpw == 4) launch_scatter_sorted<E, 4>(gs, order, cached, xG, xL, st);
+        else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, order, cached, xG, xL, st);
+        else launch_scatter_sorted<E, 1>(gs, order, cached, xG, xL, st);
       } else {
         if (tpw == 4) launch_scatter_tiles<E, 4>(gs, order, xG, xL, st);
         else if (tpw == 2) launch_scatter_tiles<E, 2>(gs, order, xG, xL, st);

@@ -184,6 +184,7 @@ static_assert(kStage == 8 * kBlock, "gather stages eight values per thread");
 constexpr int kVariantMask = 3;
 constexpr int kNoXcdRemap = 4;
 constexpr int kGroupOrder = 8;
+constexpr int kCachedAccess = 16;  // cached instead of nontemporal accesses (streaming ops; gather and scatter kernel 0)
 
 // Workgroup order (see dev::block_order) a gather or scatter variant selects.
 inline int gs_order(int variant) { return (variant & kNoXcdRemap) ? 0 : (variant & kGroupOrder) ? 1 : 2; }

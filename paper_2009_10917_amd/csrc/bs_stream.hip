@@ -201,8 +201,7 @@ inline int stream_block(const Span& sp, int variant) {
 
 // Cache policy of a streaming launch: nontemporal accesses unless the tune
 // variant asks for cached ones (+16, the small-size regime).
-constexpr int kCached = 16;
-inline bool stream_nt(int variant) { return (variant & kCached) == 0; }
+inline bool stream_nt(int variant) { return (variant & kCachedAccess) == 0; }
 
 // Launch `K<T, V, U, NB, NT>` for the runtime unroll, packet width, block
 // size and cache policy.

@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 import paper_2009_10917_amd as bs  # noqa: E402
 from gpu_util import bits, dev_uniform, host_uniform, to_host  # noqa: E402
 
-VARIANTS = [0, 1, 2, 4, 5, 6, 8, 9, 10]  # kernel choice, plus 4 = dispatch order, plus 8 = XCD runs of 256 blocks
+# kernel choice, plus 4 = dispatch order, plus 8 = XCD runs of 256 blocks; plus 16 = cached accesses (kernel 0)
+VARIANTS = [0, 1, 2, 4, 5, 6, 8, 9, 10, 16, 20, 24]
 MESHES = [(1, 1, None), (2, 1, 1), (3, 2, 2), (8, 3, None), (4, 7, 3), (3, 15, 4), (6, 5, 5), (5, 4, None),
           (12, 2, 6)]
 
@@ -189,7 +190,7 @@ def test_scatter_map_order_unrolls(ctx, unroll):
     assert np.array_equal(bits(to_host(xL)), bits(ref))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 4, 5, 8, 9])
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 8, 9, 16, 24])
 @pytest.mark.parametrize("tpw", [1, 2, 4, 8])
 def test_scatter_tiles_per_workgroup(ctx, variant, tpw):
     # tile variants take 1, 2 or 4 tiles of the visiting order per workgroup
