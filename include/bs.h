@@ -34,6 +34,10 @@
  *   not overlap any other argument; read-only inputs may alias each other
  *   (bs_dot(x, x) is fine).
  * - Reductions write one binary64 value to a caller-owned device double.
+ *   Up to 128 workgroups a reduction finishes in the same launch (the last
+ *   workgroup to publish its partial sum adds them all, in index order);
+ *   longer grids take a second launch (Section 4 counts two launches for
+ *   the paper's reductions).
  * - Arguments are validated on the host before anything is launched; a
  *   failed check returns BS_ERR_INVALID_ARG (or BS_ERR_UNSUPPORTED for a
  *   valid but unimplemented dtype) and launches nothing.  A HIP launch or
@@ -106,11 +110,13 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * with one another always run 256-thread workgroups); plus 16 for ordinary
  * cached loads and stores instead of nontemporal ones (faster when the
  * operands stay in the 256 MB last-level cache from one call to the next,
- * the small-size regime of Section 4's launch-latency model).  For gather and scatter, variant is a kernel choice,
+ * the small-size regime of Section 4's launch-latency model; calls whose
+ * operands exceed 288 MiB run nontemporal whatever the variant).  For
+ * gather and scatter, variant is a kernel choice,
  * plus 4 to keep the hardware's dispatch order or plus 8 for the runs of
  * 256 blocks per XCD in every group of 2048, instead of one contiguous range
  * of blocks per XCD, plus 16 for cached accesses in kernel 0 (as for the streaming
- * operations).  Gather: 0 = rows in the plan's permuted order (by default
+ * operations, with both value vectors and 4 bytes per local entry counted).  Gather: 0 = rows in the plan's permuted order (by default
  * in groups of 9 consecutive scatter tiles of the visiting order, each row
  * in the first group holding one of its copies, rows of a group in ascending
  * global id; bs_gs_order_rows and bs_gs_order_elements replace it; falls
@@ -127,7 +133,7 @@ bs_status bs_ctx_destroy(bs_ctx* ctx);
  * replaces them, see below). */
 bs_status bs_ctx_set_tune(bs_ctx* ctx, int op, bs_dtype dtype, int unroll, int grid_cap, int variant);
 
-/* Tune entries by length.  Each (op, dtype) holds up to 8 entries; entry k
+/* Tune entries by length.  Each (op, dtype) holds up to 16 entries; entry k
  * applies to lengths n >= n_min[k] up to the next entry (gather and scatter
  * look up the plan's local length).  bs_ctx_set_tune replaces them with one
  * entry for every dtype and length; bs_ctx_set_tune_entry inserts or
@@ -216,12 +222,15 @@ bs_status bs_cg_update_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha,
  * capture, serving loops, harnesses that forbid hipMalloc): the result of
  * bs_cg_update with no context.  The per-workgroup partial sums go to a
  * static device array of the library instead of a context's workspace:
- * 65,536 compensated pairs plus 16 chunk sums (1 MiB + 256 B per device,
- * held until the process ends), with the launch shape fixed at 4 packets
- * per thread and at most 65,536 workgroups, grid-striding over longer
- * vectors, so every length fits; a grid that would need more pairs is
- * rejected with BS_ERR_INVALID_ARG.  Nothing is allocated and nothing in the
- * array needs to start at zero (each call writes every pair it reads).  The
+ * 65,536 compensated pairs plus 16 chunk sums and a counter (1 MiB + 512 B
+ * per device, held until the process ends), with the launch shape fixed at
+ * 4 packets per thread and at most 65,536 workgroups, grid-striding over
+ * longer vectors, so every length fits; a grid that would need more pairs is
+ * rejected with BS_ERR_INVALID_ARG.  Nothing is allocated.  The pairs need
+ * not start at zero (each call writes every pair it reads); the counter of
+ * the single-launch finish (grids of at most 128 workgroups, as for the
+ * context's reductions) starts at zero when the library loads and every
+ * call that uses it leaves it at zero.  The
  * first call on a device looks the array's address up once (with that
  * device current).  Calls on one device share the array: calls that overlap
  * in time on one GPU (different streams, or threads) race and must be

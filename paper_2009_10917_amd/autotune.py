@@ -57,8 +57,10 @@ STREAM_OPS = ("copy", "axpy", "norm", "dot", "cg_update")
 REDUCTIONS = ("norm", "dot", "cg_update")
 DTYPES = (("f64", 0), ("f32", 1), ("bf16", 2))
 # bucket lower bounds and the length timed in each bucket
-BUCKETS = ((0, 1 << 14), (1 << 16, 1 << 18), (1 << 20, 1 << 22), (1 << 23, 1 << 24), (1 << 25, 1 << 26),
-           (1 << 27, 1 << 28))
+# (past 2^24 elements most operations' operands outgrow the last-level cache and the library
+# drops cached accesses, so the launch shape timed with them at 2^24 stops at 2^24)
+BUCKETS = ((0, 1 << 12), (1 << 13, 1 << 14), (1 << 15, 1 << 15), (1 << 16, 1 << 18), (1 << 20, 1 << 22),
+           (1 << 23, 1 << 24), ((1 << 24) + 1, 3 << 23), (1 << 25, 1 << 26), (1 << 27, 1 << 28))
 # cached accesses (+16) are tried where an operation's vectors can stay in the 256 MB last-level cache
 CACHED_MAX_N = 1 << 24
 MESH_K = ((0, 4), (1 << 20, 16), (1 << 24, 32), (1 << 26, 64), (1 << 29, 128))  # (n_min of N_L, K) for gather/scatter
@@ -81,6 +83,34 @@ def _time(torch, fn, reps, trials=3):
         b.record()
         torch.cuda.synchronize()
         out.append(a.elapsed_time(b) / reps)
+    return statistics.median(out)
+
+
+def _time_graph(torch, fn, reps, trials=3):
+    """`reps` calls captured in one HIP graph, replayed: the device's time per call
+    without the host's per-call cost, which hides launch shapes at short lengths."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(trials):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / reps)
+    del g
     return statistics.median(out)
 
 
@@ -113,10 +143,13 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
                 "cg_update": lambda: bs.bs_cg_update(ctx, 1e-3, vec["x"], vec["p"], vec["r"], vec["Ap"], vec["w"], out),
             }
             reps = 50 if n <= (1 << 20) else 10
+            # up to 2^22 elements a call takes less device time than the host spends issuing it
+            timer = _time_graph if n <= (1 << 22) else _time
             for op in STREAM_OPS:
                 caps = (256, 1024, 4096, 16384, 65536, 1 << 30) if op in REDUCTIONS else (1024, 4096, 16384, 65536, 1 << 30)
                 if op in REDUCTIONS and n <= (1 << 20):
-                    caps = (1,) + caps
+                    # grids of up to 128 workgroups finish the reduction in the same launch
+                    caps = (1, 16, 64, 128) + caps
                 times = {}
                 # below 2^20 elements a launch has fewer than 2048 workgroups (or one),
                 # where the orders differ little
@@ -129,7 +162,7 @@ def tune_streaming(torch, bs, bsgen, ctx, quick, log):
                     for g in caps:
                         for v in variants:
                             bs.bs_ctx_set_tune(ctx, op, u, g, v)
-                            times[(u, g, v)] = _time(torch, calls[op], reps)
+                            times[(u, g, v)] = timer(torch, calls[op], reps)
                             log.write(json.dumps({"op": op, "dtype": dname, "n": n, "unroll": u, "grid_cap": g,
                                                   "variant": v, "ms": round(times[(u, g, v)], 5)}) + "\n")
                 choice = _pick(times, DEFAULTS[op])

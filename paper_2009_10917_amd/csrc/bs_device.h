@@ -168,6 +168,42 @@ __device__ __forceinline__ void block_store_pair(DW<double> a, double* partials,
   }
 }
 
+// The same with the second stage folded into the launch (the small-size
+// regime: one launch instead of two): with a counter, each workgroup
+// publishes its pair and takes a ticket, and the workgroup that arrives last
+// adds all gridDim.x pairs in index order (thread t takes pairs t, t + BLOCK,
+// ..., then the workgroup tree), writes *out and resets the counter for the
+// next launch.  No workgroup waits for another.  A NULL counter keeps the
+// two-launch form.
+template <int BLOCK>
+__device__ __forceinline__ void block_finish(DW<double> a, double* partials, unsigned int* counter, double* out) {
+  if (!counter || gridDim.x == 1) {
+    block_store_pair<BLOCK>(a, partials, out);
+    return;
+  }
+  __shared__ int s_last;
+  a = block_reduce<BLOCK>(a);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = a.s;
+    partials[2 * blockIdx.x + 1] = a.c;
+    // release: the pair is visible before the ticket; only the last
+    // workgroup needs the acquire that makes every pair visible to it
+    const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == gridDim.x - 1;
+    if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  if (!s_last) return;
+  DW<double> r{0.0, 0.0};
+  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += BLOCK)
+    r = dw_add(r, DW<double>{partials[2 * i], partials[2 * i + 1]});
+  r = block_reduce<BLOCK>(r);
+  if (threadIdx.x == 0) {
+    *out = r.s + r.c;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Streaming (nontemporal) accesses for data touched exactly once.
 template <class T>
 __device__ __forceinline__ T ld_nt(const T* p) {

@@ -478,6 +478,13 @@ inline unsigned int blocks_for(int64_t n) { return static_cast<unsigned int>((n 
 
 template <class T> constexpr int dtype_index() { return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2; }
 
+// Bytes one gather or scatter moves: both value vectors and one 4-byte index
+// per local entry (what decides whether cached accesses can pay).
+template <class E>
+int64_t gs_operand_bytes(const bs_gs* gs) {
+  return (gs->n_local + gs->n_global) * static_cast<int64_t>(sizeof(E)) + 4 * gs->n_local;
+}
+
 template <class T>
 bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hipStream_t st) {
   using E = typename Storage<T>::E;
@@ -489,7 +496,7 @@ bs_status run_gather(bs_ctx* ctx, const bs_gs* gs, const void* xL, void* xG, hip
     const int64_t zero_blocks = (gs->n_global - gs->n_nzrows + kBlock - 1) / kBlock;
     const int64_t grid = gs->n_pblocks + zero_blocks;
     if (grid > 0) {
-      if (tn.variant & kCachedAccess)
+      if (cached_access(tn.variant, gs_operand_bytes<E>(gs)))
         hipLaunchKernelGGL((k_gather_perm<T, false>), dim3(static_cast<unsigned int>(grid)), dim3(kBlock), 0, st,
                            gs->perm_words, gs->perm_segs, gs->perm_segoff, gs->perm_rows, gs->perm_runoff,
                            gs->perm_runs, gs->perm_bstart, gs->perm_bnz0, static_cast<const E*>(xL),
@@ -573,7 +580,7 @@ bs_status run_scatter(bs_ctx* ctx, const bs_gs* gs, const void* xG, void* xL, hi
     // and the kernels' padding lanes read xG[0])
     if (gs->n_tiles > 0 && gs->n_global > 0) {
       if (kind == 0) {
-        const bool cached = (tn.variant & kCachedAccess) != 0;
+        const bool cached = cached_access(tn.variant, gs_operand_bytes<E>(gs));
         if (tpw == 4) launch_scatter_sorted<E, 4>(gs, order, cached, xG, xL, st);
         else if (tpw == 2) launch_scatter_sorted<E, 2>(gs, order, cached, xG, xL, st);
         else launch_scatter_sorted<E, 1>(gs, order, cached, xG, xL, st);

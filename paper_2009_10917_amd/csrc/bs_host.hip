@@ -147,13 +147,15 @@ extern "C" bs_status bs_ctx_create(int device, bs_ctx** out) {
   bs_ctx* c = new bs_ctx();
   c->device = device;
   void* ws = nullptr;
-  const size_t bytes = sizeof(double) * 2 * kPartialPairs;
+  const size_t pair_bytes = sizeof(double) * 2 * kPartialPairs;
+  const size_t bytes = pair_bytes + 256;  // the pairs, then the counter of single-launch reductions
   if (hipMalloc(&ws, bytes) != hipSuccess) {
     delete c;
     (void)hipSetDevice(prev);
     return fail(BS_ERR_ALLOC, "bs_ctx_create: cannot allocate %zu bytes of workspace", bytes);
   }
   c->partials = static_cast<double*>(ws);
+  c->counter = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + pair_bytes);
   s = check_hip(hipMemset(ws, 0, bytes), "bs_ctx_create");
   if (!s) s = check_hip(hipDeviceSynchronize(), "bs_ctx_create");
   if (s) {

@@ -52,7 +52,7 @@ enum Op { OP_COPY = 0, OP_AXPY, OP_NORM, OP_DOT, OP_CG_UPDATE, OP_GATHER, OP_SCA
 // Tune entries of one operation and dtype, by length: entry k applies to
 // lengths n >= n_min[k] up to the next entry's n_min (n_min[0] == 0,
 // ascending).  Gather and scatter use the plan's local length.
-constexpr int kTuneEntries = 8;
+constexpr int kTuneEntries = 16;
 struct TuneList {
   int count;
   int64_t n_min[kTuneEntries];
@@ -80,6 +80,7 @@ constexpr int kPartialPairs = kMaxStreamBlocks + kMaxStreamBlocks / kFinishChunk
 struct bs_ctx {
   int device;
   double* partials;  // 2 * kPartialPairs doubles: (sum, compensation) per workgroup, then the chunk sums
+  unsigned int* counter;  // single-launch reductions: workgroups that have published their pair (0 between launches)
   bs::TuneList tune[bs::OP_COUNT][3];
 };
 
@@ -185,6 +186,14 @@ constexpr int kVariantMask = 3;
 constexpr int kNoXcdRemap = 4;
 constexpr int kGroupOrder = 8;
 constexpr int kCachedAccess = 16;  // cached instead of nontemporal accesses (streaming ops; gather and scatter kernel 0)
+// Cached accesses pay while one call's operands fit the last-level cache (256 MB
+// of MALL plus 8 x 4 MB of L2); past that they evict what the next call reads and
+// run slower than nontemporal ones (a weighted norm over 305 MB: 5.1 against
+// 6.5 TB/s), so the variant's + 16 is honoured only up to this many bytes.
+constexpr int64_t kCachedBytesMax = int64_t{288} << 20;
+inline bool cached_access(int variant, int64_t bytes) {
+  return (variant & kCachedAccess) != 0 && bytes <= kCachedBytesMax;
+}
 
 // Workgroup order (see dev::block_order) a gather or scatter variant selects.
 inline int gs_order(int variant) { return (variant & kNoXcdRemap) ? 0 : (variant & kGroupOrder) ? 1 : 2; }

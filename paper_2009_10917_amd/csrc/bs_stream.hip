@@ -54,11 +54,11 @@ __global__ __launch_bounds__(NB) void k_axpy(typename Storage<T>::C alpha, const
 template <class T, int V, int U, bool W, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_norm(const typename Storage<T>::E* __restrict__ x,
                                                  const typename Storage<T>::E* __restrict__ w, Span sp,
-                                                 double* partials, double* out) {
+                                                 double* partials, double* out, unsigned int* counter) {
   using C = typename Storage<T>::C;
   NormOp<T, V, W, NT> op{{}, x, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
-  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  dev::block_finish<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, counter, out);
 }
 
 // ---------------------------------------------------------------- BS4 inner product
@@ -67,11 +67,11 @@ __global__ __launch_bounds__(NB) void k_norm(const typename Storage<T>::E* __res
 template <class T, int V, int U, int NB, bool NT>
 __global__ __launch_bounds__(NB) void k_dot(const typename Storage<T>::E* __restrict__ x,
                                                 const typename Storage<T>::E* __restrict__ y, Span sp,
-                                                double* partials, double* out) {
+                                                double* partials, double* out, unsigned int* counter) {
   using C = typename Storage<T>::C;
   DotOp<T, V, NT> op{{}, x, y, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
-  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  dev::block_finish<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, counter, out);
 }
 
 // ---------------------------------------------------------------- BS5 fused CG update
@@ -83,11 +83,11 @@ __global__ __launch_bounds__(NB) void k_cg_update(typename Storage<T>::C alpha, 
                                                       typename Storage<T>::E* __restrict__ r,
                                                       const typename Storage<T>::E* __restrict__ Ap,
                                                       const typename Storage<T>::E* __restrict__ w, Span sp,
-                                                      double* partials, double* out) {
+                                                      double* partials, double* out, unsigned int* counter) {
   using C = typename Storage<T>::C;
   CgOp<T, V, W, NT> op{{}, alpha, x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
-  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  dev::block_finish<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, counter, out);
 }
 
 // ---------------------------------------------------------------- device scalars
@@ -122,11 +122,11 @@ __global__ __launch_bounds__(NB) void k_cg_update_dev(DevScalar a, typename Stor
                                                           typename Storage<T>::E* __restrict__ r,
                                                           const typename Storage<T>::E* __restrict__ Ap,
                                                           const typename Storage<T>::E* __restrict__ w, Span sp,
-                                                          double* partials, double* out) {
+                                                          double* partials, double* out, unsigned int* counter) {
   using C = typename Storage<T>::C;
   CgOp<T, V, W, NT> op{{}, static_cast<C>(dev_scalar(a)), x, p, r, Ap, w, sp.head, DW<C>{C(0), C(0)}};
   stream_loop<U, NB>(op, sp);
-  dev::block_store_pair<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, out);
+  dev::block_finish<NB>(DW<double>{static_cast<double>(op.acc.s), static_cast<double>(op.acc.c)}, partials, counter, out);
 }
 
 // ---------------------------------------------------------------- host side
@@ -159,11 +159,27 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish_chunks(const double* __
   }
 }
 
+// Up to this many workgroups a reduction finishes in its own launch (the
+// last workgroup adds the pairs, dev::block_finish).  Each workgroup's
+// release is a write-back of its XCD's L2 (gfx950's L2s are not coherent
+// with one another), which beyond about a hundred workgroups costs more
+// than the second launch it saves (measured: norm at n = 2.8 M, 23 against
+// 12 us with 1024); longer grids keep the second stage.
+constexpr int kLastBlockMax = 128;
+
+// The counter a reduction launch of `grid` workgroups finishes with (NULL:
+// the two-launch form).
+inline unsigned int* finish_counter(unsigned int* counter, int grid) {
+  return (grid > 1 && grid <= kLastBlockMax) ? counter : nullptr;
+}
+
 // Second stage over `grid` pairs in `partials`; `sums` holds the chunk sums
-// of the two-launch form (grid / kFinishChunk pairs, rounded up).
-bs_status finish_on(const double* partials, double* sums, int grid, double* out, hipStream_t st, const char* op) {
+// of the two-launch form (grid / kFinishChunk pairs, rounded up).  Nothing
+// to do when the launch finished itself (`counter` non-NULL).
+bs_status finish_on(const double* partials, double* sums, int grid, double* out, hipStream_t st, const char* op,
+                    const unsigned int* counter = nullptr) {
   bs_status s = check_launch(op);
-  if (s || grid == 1) return s;
+  if (s || grid == 1 || counter) return s;
   if (grid <= kFinishDirect) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishBlock), 0, st, partials, grid, out);
     return check_launch(op);
@@ -175,9 +191,10 @@ bs_status finish_on(const double* partials, double* sums, int grid, double* out,
   return check_launch(op);
 }
 
-bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op) {
+bs_status finish(bs_ctx* ctx, int grid, double* out, hipStream_t st, const char* op, const unsigned int* counter) {
   // chunks <= kMaxStreamBlocks / kFinishChunk
-  return finish_on(ctx->partials, ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), grid, out, st, op);
+  return finish_on(ctx->partials, ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), grid, out, st, op,
+                   counter);
 }
 
 // Tune variant of a streaming operation -> Span::order (1 and 2 select the
@@ -199,9 +216,16 @@ inline int stream_block(const Span& sp, int variant) {
   return s == 1 ? 128 : s == 2 ? 512 : kBlock;
 }
 
-// Cache policy of a streaming launch: nontemporal accesses unless the tune
-// variant asks for cached ones (+16, the small-size regime).
-inline bool stream_nt(int variant) { return (variant & kCachedAccess) == 0; }
+// Cache policy of a streaming launch over `bytes` of operands: nontemporal
+// accesses unless the tune variant asks for cached ones (+16, the small-size
+// regime) and the operands fit the last-level cache.
+inline bool stream_nt(int variant, int64_t bytes) { return !cached_access(variant, bytes); }
+
+// Operand bytes of a call that touches `vectors` vectors of n elements.
+template <class T>
+int64_t operand_bytes(int64_t n, int vectors) {
+  return n * vectors * static_cast<int64_t>(sizeof(typename Storage<T>::E));
+}
 
 // Launch `K<T, V, U, NB, NT>` for the runtime unroll, packet width, block
 // size and cache policy.
@@ -262,7 +286,7 @@ bs_status run_copy(bs_ctx* ctx, int64_t n, const void* x, void* y, hipStream_t s
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, 2));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
   BS_DISPATCH_NB(K_COPY, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<typename Storage<T>::E*>(y), sp);
   return check_launch("bs_copy");
@@ -276,7 +300,7 @@ bs_status run_axpy(bs_ctx* ctx, int64_t n, double alpha, const void* x, double b
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, 3));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
   BS_DISPATCH_NB(K_AXPY, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<const typename Storage<T>::E*>(x), static_cast<C>(beta),
               static_cast<typename Storage<T>::E*>(y), sp);
@@ -291,15 +315,16 @@ bs_status run_norm(bs_ctx* ctx, int64_t n, const void* x, const void* w, double*
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, w ? 2 : 1));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
+  unsigned int* cnt = finish_counter(ctx->counter, g);
   if (w)
     BS_DISPATCH_NB(K_NORM_W, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(w), sp,
-                  ctx->partials, out);
+                  ctx->partials, out, cnt);
   else
     BS_DISPATCH_NB(K_NORM, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(x), sp,
-                  ctx->partials, out);
-  return finish(ctx, g, out, st, "bs_norm");
+                  ctx->partials, out, cnt);
+  return finish(ctx, g, out, st, "bs_norm", cnt);
 }
 
 template <class T>
@@ -310,10 +335,11 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, 2));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
-  BS_DISPATCH_NB(K_DOT, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out);
-  return finish(ctx, g, out, st, "bs_dot");
+  unsigned int* cnt = finish_counter(ctx->counter, g);
+  BS_DISPATCH_NB(K_DOT, T, sp, u, nb, nt, g, st, static_cast<const typename Storage<T>::E*>(x), static_cast<const typename Storage<T>::E*>(y), sp, ctx->partials, out, cnt);
+  return finish(ctx, g, out, st, "bs_dot", cnt);
 }
 
 // BS5 with an explicit launch shape and reduction buffers: `partials` holds
@@ -321,27 +347,28 @@ bs_status run_dot(bs_ctx* ctx, int64_t n, const void* x, const void* y, double* 
 template <class T>
 bs_status launch_cg_update(int64_t n, double alpha, void* x, const void* p, void* r, const void* Ap, const void* w,
                            double* out, int unroll, int cap, int variant, double* partials, double* sums,
-                           hipStream_t st, const char* op) {
+                           unsigned int* counter, hipStream_t st, const char* op) {
   using C = typename Storage<T>::C;
   using E = typename Storage<T>::E;
   Span sp = make_span<T>(n, {x, p, r, Ap, w});
   sp.order = stream_order(variant);
   const int u = norm_unroll(unroll);
   const int nb = stream_block(sp, variant);
-  const bool nt = stream_nt(variant);
+  const bool nt = stream_nt(variant, operand_bytes<T>(n, w ? 7 : 6));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
   if (g > cap)
     return fail(BS_ERR_INVALID_ARG, "%s: %d workgroups need more reduction pairs than the %d the buffer holds", op, g,
                 cap);
+  unsigned int* cnt = finish_counter(counter, g);
   if (w)
     BS_DISPATCH_NB(K_UPD_W, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w),
-                  sp, partials, out);
+                  sp, partials, out, cnt);
   else
     BS_DISPATCH_NB(K_UPD, T, sp, u, nb, nt, g, st, static_cast<C>(alpha), static_cast<E*>(x),
                   static_cast<const E*>(p), static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p),
-                  sp, partials, out);
-  return finish_on(partials, sums, g, out, st, op);
+                  sp, partials, out, cnt);
+  return finish_on(partials, sums, g, out, st, op, cnt);
 }
 
 template <class T>
@@ -350,20 +377,25 @@ bs_status run_cg_update(bs_ctx* ctx, int64_t n, double alpha, void* x, const voi
   const Tune& tn = tune_for(ctx, OP_CG_UPDATE, dtype_index<T>(), n);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   return launch_cg_update<T>(n, alpha, x, p, r, Ap, w, out, tn.unroll, cap, tn.variant, ctx->partials,
-                             ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), st, "bs_cg_update");
+                             ctx->partials + 2 * static_cast<size_t>(kMaxStreamBlocks), ctx->counter, st,
+                             "bs_cg_update");
 }
 
 // ---------------------------------------------------------------- allocation-free BS5
 
 // Reduction buffer of bs_cg_update_noalloc: kNoAllocPairs per-workgroup
-// pairs, then the chunk sums of the second stage.  One copy per device, held
-// until the process ends.  Host code never passes `scratch` itself (in host
-// code it names a host-side stand-in): it passes the device address that
+// pairs, then the chunk sums of the second stage, then (in the last 256
+// bytes) the counter of the single-launch finish, which starts at zero (the
+// array is zero-initialised when the code object loads) and which every
+// launch that uses it leaves at zero.  One copy per device, held until the
+// process ends.  Host code never passes `scratch` itself (in host code it
+// names a host-side stand-in): it passes the device address that
 // hipGetSymbolAddress returns for the current device.
 constexpr int kNoAllocPairs = kMaxReduceBlocks;
 constexpr int kNoAllocSums = (kNoAllocPairs + kFinishChunk - 1) / kFinishChunk;
+constexpr int kNoAllocCounter = 2 * (kNoAllocPairs + kNoAllocSums);  // offset (in doubles) of the counter
 constexpr int kNoAllocUnroll = 4;  // the built-in launch shape of the CG update
-static __device__ __align__(256) double scratch[2 * (kNoAllocPairs + kNoAllocSums)];
+static __device__ __align__(256) double scratch[kNoAllocCounter + 32];
 
 constexpr int kMaxScratchDevices = 64;
 std::mutex g_scratch_mutex;
@@ -396,7 +428,7 @@ bs_status run_axpy_dev(bs_ctx* ctx, int64_t n, DevScalar a, const void* x, DevSc
   sp.order = stream_order(tn.variant);
   const int u = norm_unroll(tn.unroll);
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, 3));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, tn.grid_cap, nb);
   BS_DISPATCH_NB(K_AXPY_DEV, T, sp, u, nb, nt, g, st, a, static_cast<const E*>(x), b, static_cast<E*>(y), sp);
   return check_launch("bs_axpy_dev");
@@ -412,15 +444,16 @@ bs_status run_cg_update_dev(bs_ctx* ctx, int64_t n, DevScalar a, void* x, const 
   const int u = norm_unroll(tn.unroll);
   const int cap = tn.grid_cap < kMaxStreamBlocks ? tn.grid_cap : kMaxStreamBlocks;
   const int nb = stream_block(sp, tn.variant);
-  const bool nt = stream_nt(tn.variant);
+  const bool nt = stream_nt(tn.variant, operand_bytes<T>(n, w ? 7 : 6));
   const int g = grid_for(sp, sp.vwidth == 1 ? 4 : u, cap, nb);
+  unsigned int* cnt = finish_counter(ctx->counter, g);
   if (w)
     BS_DISPATCH_NB(K_UPD_DEV_W, T, sp, u, nb, nt, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
-                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w), sp, ctx->partials, out);
+                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(w), sp, ctx->partials, out, cnt);
   else
     BS_DISPATCH_NB(K_UPD_DEV, T, sp, u, nb, nt, g, st, a, static_cast<E*>(x), static_cast<const E*>(p),
-                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p), sp, ctx->partials, out);
-  return finish(ctx, g, out, st, "bs_cg_update_dev");
+                  static_cast<E*>(r), static_cast<const E*>(Ap), static_cast<const E*>(p), sp, ctx->partials, out, cnt);
+  return finish(ctx, g, out, st, "bs_cg_update_dev", cnt);
 }
 
 bs_status check_scalar_ptr(const char* op, const char* name, const double* d) {
@@ -529,8 +562,9 @@ extern "C" bs_status bs_cg_update_noalloc(bs_dtype dtype, int64_t n, double alph
   double* buf = nullptr;
   if ((s = scratch_for_current_device(&buf, op))) return s;
   double* sums = buf + 2 * static_cast<size_t>(kNoAllocPairs);
+  unsigned int* counter = reinterpret_cast<unsigned int*>(buf + kNoAllocCounter);
   BS_TYPED(dtype, launch_cg_update<T>(n, alpha, x, p, r, Ap, w, d_rr, kNoAllocUnroll, kNoAllocPairs, 0, buf, sums,
-                                      static_cast<hipStream_t>(stream), op));
+                                      counter, static_cast<hipStream_t>(stream), op));
 }
 
 extern "C" bs_status bs_axpy_dev(bs_ctx* ctx, bs_dtype dtype, int64_t n, double alpha, const double* d_alpha_num,

@@ -156,3 +156,25 @@ def test_binding_rejects_host_tensors_before_any_launch():
     for f in calls:
         with pytest.raises(ValueError, match="HIP device"):
             f()
+
+
+def test_shipped_tune_table_fits_the_loader():
+    """The table bs_ctx_create loads: known operations and dtypes, at most 16 lengths per
+    (operation, dtype), ascending lengths, in-range launch shapes (the loader rejects the whole
+    table otherwise, and that check needs a device)."""
+    path = os.path.join(ROOT, "paper_2009_10917_amd", "tune_gfx950.txt")
+    ops = ("copy", "axpy", "norm", "dot", "cg_update", "gather", "scatter", "batch")
+    per = {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        op, dt, n_min, unroll, cap, variant = f[0], f[1], *map(int, f[2:])
+        assert op in ops and dt in ("f64", "f32", "bf16"), line
+        assert n_min >= 0 and unroll in (1, 2, 4, 8) and cap >= 1 and 0 <= variant <= 27, line
+        assert variant & 3 != 3 and variant & 12 != 12, line
+        per.setdefault((op, dt), []).append(n_min)
+    assert per
+    for key, mins in per.items():
+        assert len(mins) <= 16, key
+        assert mins == sorted(set(mins)), key

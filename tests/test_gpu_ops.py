@@ -362,3 +362,77 @@ def test_cache_policies_agree(dtype, n, unroll, cap, order):
     # with a different workgroup size only the vectors stay bit-identical
     for a, b in zip(res[order][:3], res[order + 4 + 16][:3]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_single_launch_finish_across_its_limit(dtype):
+    # grids of up to 128 workgroups add the pairs in the launch that reads the vectors (the
+    # last workgroup to take a ticket does it and resets the counter); 129 and more use a
+    # second launch. Calls alternate between the two so that a counter left nonzero would
+    # show; each cap repeats bit for bit, and every sum stays within the tolerance.
+    n = 300_007
+    tol = TOL if dtype == torch.float64 else 1e-6
+    h = {k: host_uniform(n, s, lo=0.0 if k == "w" else -1.0) for k, s in (("x", 1), ("y", 2), ("w", 5))}
+    if dtype == torch.float32:
+        h = {k: v.astype(np.float32).astype(np.float64) for k, v in h.items()}
+    want_norm, want_dot = ops.norm(h["x"], h["w"]), ops.dot(h["x"], h["y"])
+    x, y, w = (torch.from_numpy(h[k]).to(dtype).cuda() for k in ("x", "y", "w"))
+    ctx = bs.bs_ctx_create(0)
+    try:
+        seen = {}
+        for cap in (2, 128, 129, 64, 300, 127, 128, 2, 129):
+            for op in ("norm", "dot"):
+                bs.bs_ctx_set_tune(ctx, op, 1, cap)
+            o = scalar_out()
+            bs.bs_norm(ctx, x, w, o)
+            nv = to_host(o).copy()
+            bs.bs_dot(ctx, x, y, o)
+            dv = to_host(o).copy()
+            assert rel_err(float(nv[0]), want_norm) <= tol and rel_err(float(dv[0]), want_dot) <= tol, cap
+            if cap in seen:
+                assert np.array_equal(bits(seen[cap][0]), bits(nv)), cap
+                assert np.array_equal(bits(seen[cap][1]), bits(dv)), cap
+            seen[cap] = (nv, dv)
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+
+def test_single_launch_finish_in_graph_replays():
+    # the ticket counter is reset by the kernel itself (no memset), so a captured sequence of
+    # finishing launches gives the eager bits on every replay, with eager work in between
+    n = 200_003
+    x, y, w = dev_uniform(n, 1), dev_uniform(n, 2), dev_uniform(n, 5, lo=0.0)
+    ctx = bs.bs_ctx_create(0)
+    try:
+        for op in ("norm", "dot"):
+            bs.bs_ctx_set_tune(ctx, op, 2, 100)
+        eager_n, eager_d = scalar_out(), scalar_out()
+        bs.bs_norm(ctx, x, w, eager_n)
+        bs.bs_dot(ctx, x, y, eager_d)
+        want = (bits(to_host(eager_n)), bits(to_host(eager_d)))
+        gn, gd = scalar_out(), scalar_out()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            bs.bs_norm(ctx, x, w, gn)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(3):
+                bs.bs_norm(ctx, x, w, gn)
+                bs.bs_dot(ctx, x, y, gd)
+        for _ in range(3):
+            gn.fill_(0.0)
+            gd.fill_(0.0)
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(bits(to_host(gn)), want[0]) and np.array_equal(bits(to_host(gd)), want[1])
+            o = scalar_out()
+            bs.bs_dot(ctx, x, w, o)  # eager work between replays
+            torch.cuda.synchronize()
+        del g
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
