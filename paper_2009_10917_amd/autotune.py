@@ -207,7 +207,7 @@ def tune_gather_scatter(torch, np, bs, bsgen, ctx, quick, log):
                     unrolls = (1,) if op == "gather" else ((1, 2, 4) if v % 4 < 2 else (1, 4))
                     for u in unrolls:
                         bs.bs_ctx_set_tune(ctx, op, u, 1 << 30, v)
-                        times[(u, 1 << 30, v)] = _time(torch, call, reps)
+                        times[(u, 1 << 30, v)] = (_time_graph if NL <= (1 << 22) else _time)(torch, call, reps)
                         log.write(json.dumps({"op": op, "dtype": dname, "n_local": NL, "unroll": u, "variant": v,
                                               "ms": round(times[(u, 1 << 30, v)], 5)}) + "\n")
                 choice = _pick(times, DEFAULTS[op])
