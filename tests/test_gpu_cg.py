@@ -131,14 +131,15 @@ def test_ir_cg_binary32_reaches_binary64_accuracy(ctx, m):
     assert np.linalg.norm(xg - xo) <= kappa * 1e-10 * np.linalg.norm(xo)
 
 
-def test_ir_cg_bfloat16_reports_its_outcome(ctx):
+@pytest.mark.parametrize("inner_tol", [0.1, 3e-3])
+def test_ir_cg_bfloat16_reports_its_outcome(ctx, inner_tol):
     # bfloat16 storage: kappa * 2^-8 is above 1 on this grid, so inner solves may
     # fail to contract; the solver must then say so instead of looping
     m = 64
     b = rhs(m)
     x = torch.zeros(m ** 3, dtype=torch.float64, device="cuda")
     res = bs.bs_cg_ir_solve(ctx, bs.BS_BF16, m, SHIFT, torch.from_numpy(b).cuda(), x, tol=1e-10,
-                            inner_tol=0.1, max_outer=60, check=False)
+                            inner_tol=inner_tol, max_outer=60, check=False)
     rr = true_relres(to_host(x), b, m)
     assert abs(rr - res["rel_residual"]) <= 1e-6 * max(rr, 1e-12) + 1e-14
     if res["status"] == "BS_OK":
@@ -166,6 +167,13 @@ def test_full_size_fp64_and_mixed(ctx):
     assert np.linalg.norm(a - c) <= kappa * 2e-10 * np.linalg.norm(a)
     assert np.linalg.norm(a - d) <= kappa * 2e-10 * np.linalg.norm(a)
     assert r16["outer_iterations"] >= 2 and r32["outer_iterations"] >= 2
+    # the benchmark's bfloat16 inner tolerance
+    x16b = torch.zeros_like(x64)
+    r16b = bs.bs_cg_ir_solve(ctx, bs.BS_BF16, m, SHIFT, db, x16b, tol=1e-10, inner_tol=3e-3, max_outer=60)
+    assert r16b["status"] == "BS_OK"
+    e = to_host(x16b)
+    assert true_relres(e, b, m) <= 1e-10
+    assert np.linalg.norm(a - e) <= kappa * 2e-10 * np.linalg.norm(a)
     # Chebyshev bound on the A-norm error, turned into one on the residual
     # (a factor sqrt(kappa) between the two): a ceiling, not an estimate
     ceiling = math.sqrt(kappa) / 2 * math.log(2 * math.sqrt(kappa) / 1e-10)
