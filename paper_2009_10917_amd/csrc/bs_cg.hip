@@ -424,7 +424,10 @@ struct Batches {
       if (!s) s = check_hip(hipStreamSynchronize(st), "cg");
       if (s || out->done) break;
       const int64_t k = next_iterations(*out);
-      s = launch_at_least(k < kSize[0] ? k : kSize[0], out, st, enqueue);
+      // far from the end (at least 46 iterations to go at the mean rate), two
+      // batches per read-back; near it, one
+      const int64_t cap = k >= 4 * kSize[0] ? 2 * kSize[0] : kSize[0];
+      s = launch_at_least(k < cap ? k : cap, out, st, enqueue);
     }
     return s;
   }
